@@ -1,0 +1,410 @@
+"""Plain FP64 reference implementation of the D3Q19 lattice-Boltzmann update.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import this
+module: only the tests, the smoke check and the CPU baseline leg of the
+benchmark use it.  It shares no code, tables or constants with the HIP
+library; the two meet only on the seeded inputs they are both given.
+
+What the paper fixes and what is a reading
+------------------------------------------
+The paper's benchmark (Section IV, "Application Benchmark Results") is a
+lattice-Boltzmann collision for a mixture of two fluids, taken from a
+code that couples LB hydrodynamics to a free-energy order parameter whose
+gradients are computed by finite differences (Section II-A).  Lattice
+fields are double precision, stored structure-of-arrays with consecutive
+sites contiguous (Section III-B), and the innermost loops run over the 19
+discrete momenta or the 3 spatial dimensions (Section IV).  The paper
+prints no equation for any of this, so every formula below is a stated
+textbook reading:
+
+* D3Q19 velocity set and weights with c_s^2 = 1/3, and the second-order
+  equilibrium of the BGK model (Qian, d'Humieres & Lallemand 1992).
+* Symmetric phi^4 free energy F = A/2 phi^2 + B/4 phi^4 + kappa/2 |grad phi|^2,
+  chemical potential mu = A phi + B phi^3 - kappa lap(phi) and the chemical
+  (thermodynamic) stress P_ab entering the second moment of f^eq, with a
+  second distribution g carrying phi (Swift, Osborn & Yeomans 1995;
+  Swift, Orlandini, Osborn & Yeomans 1996).
+* Second-order 7-point central differences for grad(phi) and lap(phi).
+* Collide, then propagate; periodic in x, y and z; the state the user sees
+  is the post-propagation (pre-collision) distribution.
+
+Layout: every distribution is an array of shape (19, nz, ny, nx), so the
+site index s = x + nx*(y + ny*z) runs fastest in x (Section III-B's
+structure-of-arrays field[i*N + s]).  Scalar fields are (nz, ny, nx).
+
+The arithmetic is written so that it also runs on complex128 arrays; the
+tests use that for complex-step derivatives of the whole rollout.
+"""
+
+from dataclasses import dataclass
+
+import numpy as np
+
+# ---------------------------------------------------------------------------
+# D3Q19 velocity set
+# ---------------------------------------------------------------------------
+
+
+def _velocity_set():
+    """Rest velocity first, then the 18 velocities with |c|^2 in {1, 2} in
+    lexicographic order of (c_x, c_y, c_z).  The paper only says there are
+    19 momenta (Section IV); this ordering is a reading, and it is part of
+    the interface because gradients with respect to f expose it."""
+    vel = [(0, 0, 0)]
+    for cx in (-1, 0, 1):
+        for cy in (-1, 0, 1):
+            for cz in (-1, 0, 1):
+                if cx * cx + cy * cy + cz * cz in (1, 2):
+                    vel.append((cx, cy, cz))
+    return np.array(vel, dtype=np.int64)
+
+
+C = _velocity_set()                       # (19, 3) integer velocities
+NQ = C.shape[0]                           # 19
+_C2 = (C * C).sum(axis=1)                 # |c_i|^2
+W = np.where(_C2 == 0, 1.0 / 3.0, np.where(_C2 == 1, 1.0 / 18.0, 1.0 / 36.0))
+OPP = np.array([int(np.flatnonzero((C == -C[i]).all(axis=1))[0]) for i in range(NQ)])
+CS2 = 1.0 / 3.0
+
+# Axis of a (nz, ny, nx) scalar field that each velocity component moves along.
+_AXIS_OF_COMPONENT = (2, 1, 0)            # c_x -> axis 2, c_y -> axis 1, c_z -> axis 0
+
+
+@dataclass
+class Params:
+    """Physical parameters of one run (plain numbers, no derived state)."""
+    tau_f: float = 1.0
+    A: float = -0.0625
+    B: float = 0.0625
+    kappa: float = 0.04
+    mobility: float = 0.45
+    gamma: float = 1.0
+
+    @property
+    def tau_g(self):
+        # Cahn-Hilliard mobility M = Gamma (tau_g - 1/2)  =>  tau_g = M/Gamma + 1/2.
+        return self.mobility / self.gamma + 0.5
+
+
+# ---------------------------------------------------------------------------
+# Small helpers on periodic scalar fields
+# ---------------------------------------------------------------------------
+
+
+def shift(field, c):
+    """Return h with h(s) = field(s - c) on the periodic lattice, i.e. every
+    value moved by +c.  `field` is (nz, ny, nx); c = (cx, cy, cz)."""
+    out = field
+    for comp in range(3):
+        if c[comp] != 0:
+            out = np.roll(out, int(c[comp]), axis=_AXIS_OF_COMPONENT[comp])
+    return out
+
+
+def neighbour(field, c):
+    """Return h with h(s) = field(s + c)."""
+    return shift(field, (-int(c[0]), -int(c[1]), -int(c[2])))
+
+
+# ---------------------------------------------------------------------------
+# Moments
+# ---------------------------------------------------------------------------
+
+
+def density(f):
+    """rho(s) = sum_i f_i(s)."""
+    rho = np.zeros_like(f[0])
+    for i in range(NQ):
+        rho = rho + f[i]
+    return rho
+
+
+def momentum(f):
+    """j_a(s) = sum_i f_i(s) c_ia, returned as a (3, nz, ny, nx) array."""
+    j = np.zeros((3,) + f.shape[1:], dtype=f.dtype)
+    for i in range(NQ):
+        for a in range(3):
+            if C[i, a] != 0:
+                j[a] = j[a] + C[i, a] * f[i]
+    return j
+
+
+def velocity(f):
+    """u = j / rho (no forcing correction: the fluids couple through the
+    chemical stress in the equilibrium, not through a body force)."""
+    rho = density(f)
+    return momentum(f) / rho, rho
+
+
+def order_parameter(g):
+    """phi(s) = sum_i g_i(s)."""
+    return density(g)
+
+
+# ---------------------------------------------------------------------------
+# Finite differences and free energy (binary fluid)
+# ---------------------------------------------------------------------------
+
+
+def gradient(phi):
+    """Second-order central difference d_a phi = [phi(s+e_a) - phi(s-e_a)] / 2,
+    periodic.  Returns (3, nz, ny, nx) ordered (x, y, z)."""
+    out = np.zeros((3,) + phi.shape, dtype=phi.dtype)
+    for a in range(3):
+        e = [0, 0, 0]
+        e[a] = 1
+        out[a] = 0.5 * (neighbour(phi, e) - neighbour(phi, [-v for v in e]))
+    return out
+
+
+def laplacian(phi):
+    """Second-order 7-point Laplacian sum_a [phi(s+e_a) + phi(s-e_a)] - 6 phi(s)."""
+    out = -6.0 * phi
+    for a in range(3):
+        e = [0, 0, 0]
+        e[a] = 1
+        out = out + neighbour(phi, e) + neighbour(phi, [-v for v in e])
+    return out
+
+
+def chemical_potential(phi, lap, prm):
+    """mu = dF/dphi = A phi + B phi^3 - kappa lap(phi)."""
+    return prm.A * phi + prm.B * phi ** 3 - prm.kappa * lap
+
+
+def chemical_stress(phi, grad, lap, prm):
+    """Thermodynamic stress of the phi^4 free energy (without the ideal-gas
+    rho c_s^2 part, which the equilibrium carries itself):
+
+        P_ab = [A/2 phi^2 + 3B/4 phi^4 - kappa phi lap(phi) - kappa/2 |grad phi|^2] delta_ab
+               + kappa d_a phi d_b phi.
+
+    Returned as a (3, 3, nz, ny, nx) array."""
+    iso = (0.5 * prm.A * phi ** 2 + 0.75 * prm.B * phi ** 4
+           - prm.kappa * phi * lap
+           - 0.5 * prm.kappa * (grad[0] ** 2 + grad[1] ** 2 + grad[2] ** 2))
+    P = np.zeros((3, 3) + phi.shape, dtype=np.result_type(phi, grad))
+    for a in range(3):
+        for b in range(3):
+            P[a, b] = prm.kappa * grad[a] * grad[b]
+        P[a, a] = P[a, a] + iso
+    return P
+
+
+# ---------------------------------------------------------------------------
+# Equilibria
+# ---------------------------------------------------------------------------
+
+
+def equilibrium_f(rho, u, P=None):
+    """Second-order equilibrium whose moments are rho, rho u and
+    rho c_s^2 delta + rho u u + P:
+
+        f^eq_i = w_i { rho [1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u]
+                       + 9/2 [c_i.P.c_i - tr(P)/3] }.
+    P = None is the single fluid."""
+    uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2]
+    if P is not None:
+        trP = P[0, 0] + P[1, 1] + P[2, 2]
+    feq = np.zeros((NQ,) + rho.shape, dtype=np.result_type(rho, u))
+    for i in range(NQ):
+        cu = C[i, 0] * u[0] + C[i, 1] * u[1] + C[i, 2] * u[2]
+        val = rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu)
+        if P is not None:
+            cPc = np.zeros_like(trP)
+            for a in range(3):
+                for b in range(3):
+                    if C[i, a] != 0 and C[i, b] != 0:
+                        cPc = cPc + C[i, a] * C[i, b] * P[a, b]
+            val = val + 4.5 * (cPc - trP / 3.0)
+        feq[i] = W[i] * val
+    return feq
+
+
+def equilibrium_g(phi, u, mu, prm):
+    """Equilibrium of the order-parameter distribution with moments phi,
+    phi u and Gamma mu delta + phi u u:
+
+        g^eq_i = w_i { phi [1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u]
+                       + 9/2 (Gamma mu - phi/3)(|c_i|^2 - 1) }."""
+    uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2]
+    geq = np.zeros((NQ,) + phi.shape, dtype=np.result_type(phi, u, mu))
+    for i in range(NQ):
+        cu = C[i, 0] * u[0] + C[i, 1] * u[1] + C[i, 2] * u[2]
+        val = phi * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu)
+        val = val + 4.5 * (prm.gamma * mu - phi / 3.0) * (_C2[i] - 1)
+        geq[i] = W[i] * val
+    return geq
+
+
+# ---------------------------------------------------------------------------
+# Collision, propagation, step
+# ---------------------------------------------------------------------------
+
+
+def bgk(f, feq, tau):
+    """BGK relaxation f* = f - (f - f^eq) / tau."""
+    return f - (f - feq) / tau
+
+
+def collide_single(f, tau):
+    """Single-fluid BGK collision of every site."""
+    u, rho = velocity(f)
+    return bgk(f, equilibrium_f(rho, u), tau)
+
+
+def binary_fields(g, prm):
+    """phi, grad phi, lap phi, mu and P of the current g (whole lattice first,
+    because the stencils need phi at the neighbours)."""
+    phi = order_parameter(g)
+    grad = gradient(phi)
+    lap = laplacian(phi)
+    mu = chemical_potential(phi, lap, prm)
+    P = chemical_stress(phi, grad, lap, prm)
+    return phi, grad, lap, mu, P
+
+
+def collide_binary(f, g, prm):
+    """Binary-fluid collision: f relaxes to f^eq(rho, u, P) with tau_f and g
+    relaxes to g^eq(phi, u, mu) with tau_g; u comes from f."""
+    phi, _grad, _lap, mu, P = binary_fields(g, prm)
+    u, rho = velocity(f)
+    f_new = bgk(f, equilibrium_f(rho, u, P), prm.tau_f)
+    g_new = bgk(g, equilibrium_g(phi, u, mu, prm), prm.tau_g)
+    return f_new, g_new
+
+
+def propagate(f):
+    """Periodic streaming f_i(s + c_i) <- f_i(s): a pure permutation."""
+    out = np.empty_like(f)
+    for i in range(NQ):
+        out[i] = shift(f[i], C[i])
+    return out
+
+
+def step_single(f, tau, nsteps=1):
+    for _ in range(nsteps):
+        f = propagate(collide_single(f, tau))
+    return f
+
+
+def step_binary(f, g, prm, nsteps=1):
+    for _ in range(nsteps):
+        f, g = collide_binary(f, g, prm)
+        f, g = propagate(f), propagate(g)
+    return f, g
+
+
+# ---------------------------------------------------------------------------
+# Initial state
+# ---------------------------------------------------------------------------
+
+
+def init_single(rho, u):
+    """f = f^eq(rho, u)."""
+    return equilibrium_f(rho, u)
+
+
+def init_binary(rho, u, phi, prm):
+    """f = f^eq(rho, u, P(phi)) and g = g^eq(phi, u, mu(phi)), with the same
+    stencils the collision uses applied to the given phi."""
+    grad = gradient(phi)
+    lap = laplacian(phi)
+    mu = chemical_potential(phi, lap, prm)
+    P = chemical_stress(phi, grad, lap, prm)
+    return equilibrium_f(rho, u, P), equilibrium_g(phi, u, mu, prm)
+
+
+# ---------------------------------------------------------------------------
+# Conserved sums
+# ---------------------------------------------------------------------------
+
+
+def conserved_sums(f, g=None):
+    """(sum rho, sum j_x, sum j_y, sum j_z, sum phi) over the lattice."""
+    rho = density(f)
+    j = momentum(f)
+    phi_sum = order_parameter(g).sum() if g is not None else 0.0
+    return np.array([rho.sum(), j[0].sum(), j[1].sum(), j[2].sum(), phi_sum])
+
+
+# ---------------------------------------------------------------------------
+# Adjoint of the single-fluid BGK step
+# ---------------------------------------------------------------------------
+
+
+def velocity_loss(f):
+    """L = (1/N) sum_s u(s).u(s), written with u*u (not |u|^2) so that it is
+    analytic for complex-step differentiation."""
+    u, _rho = velocity(f)
+    return (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]).mean()
+
+
+def velocity_loss_seed(f):
+    """dL/df_j(s) = (2/N) u.(c_j - u) / rho, the adjoint at the final step."""
+    u, rho = velocity(f)
+    n = rho.size
+    lam = np.zeros_like(f)
+    for j in range(NQ):
+        acc = np.zeros_like(rho)
+        for a in range(3):
+            acc = acc + u[a] * (C[j, a] - u[a])
+        lam[j] = 2.0 / n * acc / rho
+    return lam
+
+
+def adjoint_step_single(f_n, lam_next, tau):
+    """Reverse of one step f^{n+1} = propagate(collide(f^n)).
+
+    With lambda*_i(s) = lambda^{n+1}_i(s + c_i) (the transpose of the
+    streaming permutation) and omega = 1/tau, the transpose of the local
+    collision Jacobian gives
+
+        lambda^n_j = (1 - omega) lambda*_j
+                     + omega [ S + sum_a T_a (c_ja - u_a) / rho ],
+        S   = sum_i lambda*_i f^eq_i / rho,
+        T_a = sum_i lambda*_i w_i rho (3 c_ia + 9 (c_i.u) c_ia - 3 u_a),
+
+    from d f^eq_i / d f_j = f^eq_i/rho + w_i rho dE_i/du_a (c_ja - u_a)/rho.
+    The relaxation-rate sensitivity is dL/domega = sum_s sum_i
+    lambda*_i (f^eq_i - f_i).  Returns (lambda^n, dL/domega)."""
+    omega = 1.0 / tau
+    lam_star = np.empty_like(lam_next)
+    for i in range(NQ):
+        lam_star[i] = neighbour(lam_next[i], C[i])
+    u, rho = velocity(f_n)
+    feq = equilibrium_f(rho, u)
+    S = np.zeros_like(rho)
+    T = np.zeros((3,) + rho.shape, dtype=np.result_type(rho, lam_star))
+    for i in range(NQ):
+        S = S + lam_star[i] * feq[i] / rho
+        cu = C[i, 0] * u[0] + C[i, 1] * u[1] + C[i, 2] * u[2]
+        for a in range(3):
+            T[a] = T[a] + lam_star[i] * W[i] * rho * (3.0 * C[i, a] + 9.0 * cu * C[i, a] - 3.0 * u[a])
+    lam_n = np.empty_like(lam_star)
+    for j in range(NQ):
+        acc = S.copy()
+        for a in range(3):
+            acc = acc + T[a] * (C[j, a] - u[a]) / rho
+        lam_n[j] = (1.0 - omega) * lam_star[j] + omega * acc
+    domega = (lam_star * (feq - f_n)).sum()
+    return lam_n, domega
+
+
+def rollout_gradient(f0, tau, nsteps, seed=velocity_loss_seed):
+    """Gradient of L(f^T) with respect to f^0 and tau by a plain reverse
+    sweep over every stored state (small lattices only).  Returns
+    (L, dL/df0, dL/dtau)."""
+    states = [f0]
+    f = f0
+    for _ in range(nsteps):
+        f = step_single(f, tau)
+        states.append(f)
+    loss = velocity_loss(f)
+    lam = seed(f)
+    domega = 0.0
+    for n in range(nsteps - 1, -1, -1):
+        lam, dw = adjoint_step_single(states[n], lam, tau)
+        domega = domega + dw
+    dtau = -domega / (tau * tau)           # omega = 1/tau
+    return loss, lam, dtau
