@@ -1,0 +1,181 @@
+/*
+ * lb.h -- C ABI of the MI355X D3Q19 lattice-Boltzmann library (liblb.so).
+ *
+ * The operation is the per-site lattice-Boltzmann update the paper
+ * benchmarks (Section IV: an LB collision for a mixture of two fluids,
+ * inner loops over the 19 lattice momenta and the 3 dimensions, double
+ * precision lattice fields), followed by periodic propagation.  The paper
+ * gives no formula; the library implements the standard readings:
+ *
+ *   single fluid  f*_i = f_i - (f_i - f^eq_i(rho, u)) / tau_f
+ *   binary fluid  f*_i = f_i - (f_i - f^eq_i(rho, u, P)) / tau_f
+ *                 g*_i = g_i - (g_i - g^eq_i(phi, u, mu)) / tau_g
+ *   propagation   f_i(s + c_i) <- f*_i(s)   (periodic in x, y, z)
+ *
+ * with rho = sum f_i, u = sum f_i c_i / rho, phi = sum g_i,
+ *   mu   = A phi + B phi^3 - kappa lap(phi),
+ *   P_ab = [A/2 phi^2 + 3B/4 phi^4 - kappa phi lap(phi) - kappa/2 |grad phi|^2] d_ab
+ *          + kappa d_a phi d_b phi,
+ *   f^eq_i = w_i {rho [1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u] + 9/2 [c_i.P.c_i - tr P / 3]},
+ *   g^eq_i = w_i {phi [1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u] + 9/2 (gamma mu - phi/3)(|c_i|^2 - 1)},
+ *   tau_g  = mobility / gamma + 1/2,
+ * grad and lap by second-order 7-point central differences (the paper's
+ * application solves its order parameter by finite differences, Section
+ * II-A).
+ *
+ * Velocity ordering (i = 0..18): rest first, then the 18 velocities with
+ * |c|^2 in {1,2} in lexicographic order of (c_x, c_y, c_z):
+ *   1 (-1,-1,0)  2 (-1,0,-1)  3 (-1,0,0)  4 (-1,0,1)  5 (-1,1,0)  6 (0,-1,-1)
+ *   7 (0,-1,0)   8 (0,-1,1)   9 (0,0,-1) 10 (0,0,1)  11 (0,1,-1) 12 (0,1,0)
+ *  13 (0,1,1)   14 (1,-1,0)  15 (1,0,-1) 16 (1,0,0)  17 (1,0,1)  18 (1,1,0)
+ * weights 1/3 (rest), 1/18 (|c|^2 = 1), 1/36 (|c|^2 = 2).
+ *
+ * Layout (Section III-B, structure of arrays): site s = x + nx*(y + ny*z);
+ * a distribution in "canonical" layout is 19 arrays of N = nx*ny*nz values,
+ * direction-major, i.e. element (i, s) at offset i*N + s.  Vector moments
+ * are component-major: u[a*N + s], a = x, y, z.
+ *
+ * Memory and streams.  Every pointer passed to a liblb.so function is a
+ * DEVICE pointer unless stated otherwise.  The caller owns all memory: the
+ * workspace given to lb_create and every input/output array.  All calls
+ * that touch device memory are asynchronous on the context's stream and
+ * never synchronise the device (the exceptions are lb_kernel_times, which
+ * waits for the events it reads, and lb_destroy, which waits for the
+ * stream).  Kernel launch failures return LB_EDEVICE; faults inside a
+ * kernel surface at the caller's next synchronisation.  A context is not
+ * thread-safe.  Invalid arguments are detected before any work is queued
+ * and leave the context unchanged.
+ *
+ * The target copy of the lattice is the master copy (Section III-A): the
+ * host sees the state only through lb_moments, lb_get_state and
+ * lb_conserved_sums.
+ */
+#ifndef LB_H
+#define LB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes.  Every function returns one of these (lb_strerror aside). */
+#define LB_OK        0
+#define LB_EINVAL   (-1)   /* bad argument: NULL pointer, size, parameter range, wrong model */
+#define LB_ENOMEM   (-2)   /* workspace smaller than lb_workspace_bytes() */
+#define LB_EDEVICE  (-3)   /* a HIP runtime call or kernel launch failed */
+#define LB_ENOTSUP  (-4)   /* valid request this build does not implement */
+
+/* Models. */
+#define LB_SINGLE   0      /* one fluid, distribution f */
+#define LB_BINARY   1      /* binary mixture, distributions f and g (g carries phi) */
+
+/* Storage precision of the distributions.
+ * LB_F64: f and g stored as IEEE double, FP64 arithmetic, stored directly.
+ * LB_F32: stored as float deviations d_i = f_i - w_i*rho0 (g: g_i - w_i*phi0),
+ *         FP32 arithmetic written in deviation form.
+ * LB_F16: as LB_F32 but stored as IEEE binary16 (round to nearest even). */
+#define LB_F64      0
+#define LB_F32      1
+#define LB_F16      2
+
+typedef struct lb_params {
+    int32_t nx, ny, nz;   /* periodic extents, each >= 1                      */
+    int32_t model;        /* LB_SINGLE or LB_BINARY                           */
+    int32_t storage;      /* LB_F64, LB_F32 or LB_F16                          */
+    int32_t reserved;     /* must be 0                                        */
+    double  tau_f;        /* BGK relaxation time of f, > 0.5                  */
+    double  A, B, kappa;  /* free energy (binary only); kappa >= 0            */
+    double  mobility;     /* Cahn-Hilliard mobility M > 0 (binary only)       */
+    double  gamma;        /* mobility parameter Gamma > 0 (binary only)       */
+    double  rho0, phi0;   /* deviation references for LB_F32/LB_F16; ignored for LB_F64 */
+} lb_params;
+
+typedef struct lb_ctx lb_ctx;   /* opaque; created by lb_create */
+
+/* Bytes of device workspace a context with these parameters needs.
+ * Host-only (touches no device).  LB_EINVAL on bad parameters. */
+int lb_workspace_bytes(const lb_params* p, size_t* bytes);
+
+/* Create a context.  `workspace` is a device allocation of at least
+ * lb_workspace_bytes() bytes, 256-byte aligned, owned by the caller and
+ * borrowed until lb_destroy; `stream` is a hipStream_t (NULL = the null
+ * stream).  Queues no device work.  *out receives the context. */
+int lb_create(const lb_params* p, void* workspace, size_t workspace_bytes,
+              void* stream, lb_ctx** out);
+
+/* Change the stream subsequent calls are queued on. */
+int lb_set_stream(lb_ctx* ctx, void* stream);
+
+/* Set the state to equilibrium: f = f^eq(rho, u[, P(phi)]) and, for the
+ * binary model, g = g^eq(phi, u, mu(phi)), the stencils applied to the given
+ * phi.  rho[N], u[3*N] component-major, phi[N] (NULL for LB_SINGLE), all
+ * FP64 device arrays in site order.  The state becomes the pre-collision
+ * state at t = 0. */
+int lb_init_equilibrium(lb_ctx* ctx, const double* rho, const double* u, const double* phi);
+
+/* One collision of every site of the current state (binary: computes phi,
+ * its stencils, mu and P from the current g first). */
+int lb_collide(lb_ctx* ctx);
+
+/* One periodic propagation f_i(s + c_i) <- f_i(s) of every population. */
+int lb_propagate(lb_ctx* ctx);
+
+/* nsteps x (collide; propagate).  nsteps == 0 is a no-op, < 0 is LB_EINVAL.
+ * Each step is one fused pull-stream + collide kernel (binary: preceded by
+ * the phi kernel). */
+int lb_step(lb_ctx* ctx, int32_t nsteps);
+
+/* Moments of the current state, FP64: rho[N], u[3*N] component-major, and
+ * phi[N] (binary only; NULL to skip).  rho or u may be NULL to skip them. */
+int lb_moments(lb_ctx* ctx, double* rho, double* u, double* phi);
+
+/* out[5] (device, FP64) = (sum rho, sum j_x, sum j_y, sum j_z, sum phi) of
+ * the current state, summed in a fixed order (bitwise reproducible for a
+ * given lattice and state).  sum phi is 0 for LB_SINGLE. */
+int lb_conserved_sums(lb_ctx* ctx, double* out);
+
+/* Copy the current state out / in, canonical layout, storage dtype (double,
+ * float or binary16), deviations for LB_F32/LB_F16.  f has 19*N elements; g
+ * likewise (binary only; NULL otherwise). */
+int lb_get_state(lb_ctx* ctx, void* f, void* g);
+int lb_set_state(lb_ctx* ctx, const void* f, const void* g);
+
+/* Change tau_f (> 0.5) for subsequent collisions. */
+int lb_set_tau(lb_ctx* ctx, double tau_f);
+
+/* Adjoint (reverse) of one single-fluid BGK step f^{n+1} = propagate(collide(f^n)),
+ * LB_SINGLE + LB_F64 only.  f_n[19*N] is the pre-collision state of step n,
+ * lam_next[19*N] = dL/df^{n+1}, both canonical FP64; lam_n[19*N] receives
+ * dL/df^n (must not alias the inputs).  *domega (one device double) is
+ * INCREMENTED by this step's dL/d(1/tau_f); the caller zeroes it first and
+ * converts with dL/dtau = -dL/domega / tau^2.  Uses the context's tau_f. */
+int lb_adjoint_step(lb_ctx* ctx, const double* f_n, const double* lam_next,
+                    double* lam_n, double* domega);
+
+/* Per-kernel timing with HIP events on the context's stream.
+ * lb_profile(ctx, 1) starts recording an event pair around every kernel
+ * launch (and clears earlier records); lb_profile(ctx, 0) stops.
+ * lb_kernel_times waits for the recorded events and returns, for kernel
+ * class `kind`, the summed duration in milliseconds and the launch count. */
+#define LB_K_COLLIDE  0   /* collide / fused pull-stream + collide */
+#define LB_K_PHI      1   /* order-parameter kernel (binary) */
+#define LB_K_STREAM   2   /* stand-alone propagation */
+#define LB_K_ADJOINT  3   /* adjoint step */
+#define LB_K_OTHER    4   /* init, moments, sums, copies */
+int lb_profile(lb_ctx* ctx, int enable);
+int lb_kernel_times(lb_ctx* ctx, int kind, double* total_ms, int64_t* launches);
+
+/* Destroy a context (waits for its stream).  NULL is allowed (LB_OK).
+ * The workspace is not freed: it belongs to the caller. */
+int lb_destroy(lb_ctx* ctx);
+
+/* Static description of a status code. */
+const char* lb_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LB_H */

@@ -1,0 +1,508 @@
+// C ABI of the gfx950 D3Q19 lattice-Boltzmann library: argument checks,
+// workspace carving, the direct/pending state machine and kernel launches on
+// the caller's stream.  See include/lb.h for the contract of every call.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/lb.h"
+#include "kernels.h"
+
+using namespace lbk;
+
+namespace {
+
+constexpr size_t kAlign = 4096;
+// Extra bytes between consecutive direction arrays, so the 19 (38) streams of
+// a power-of-two lattice do not start on the same HBM channel.
+constexpr size_t kDirPadBytes = 1024;
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+size_t storage_size(int storage) { return storage == LB_F64 ? 8 : (storage == LB_F32 ? 4 : 2); }
+size_t compute_size(int storage) { return storage == LB_F64 ? 8 : 4; }
+
+struct Layout {
+    int64_t nsite;
+    int64_t dstride;        // elements
+    size_t dist_bytes;      // one 19-direction buffer
+    size_t phi_bytes;
+    int nblocks;
+    size_t partial_bytes;
+    size_t off_f[2], off_g[2], off_phi, off_partial, total;
+};
+
+int check_params(const lb_params* p) {
+    if (!p) return LB_EINVAL;
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) return LB_EINVAL;
+    const int64_t n = (int64_t)p->nx * p->ny * p->nz;
+    if (n > (int64_t)INT32_MAX) return LB_EINVAL;
+    if (p->model != LB_SINGLE && p->model != LB_BINARY) return LB_EINVAL;
+    if (p->storage != LB_F64 && p->storage != LB_F32 && p->storage != LB_F16) return LB_EINVAL;
+    if (p->reserved != 0) return LB_EINVAL;
+    if (!std::isfinite(p->tau_f) || !(p->tau_f > 0.5)) return LB_EINVAL;
+    if (p->model == LB_BINARY) {
+        if (!std::isfinite(p->A) || !std::isfinite(p->B) || !std::isfinite(p->kappa)) return LB_EINVAL;
+        if (!(p->kappa >= 0.0)) return LB_EINVAL;
+        if (!std::isfinite(p->mobility) || !(p->mobility > 0.0)) return LB_EINVAL;
+        if (!std::isfinite(p->gamma) || !(p->gamma > 0.0)) return LB_EINVAL;
+    }
+    if (!std::isfinite(p->rho0) || !std::isfinite(p->phi0)) return LB_EINVAL;
+    return LB_OK;
+}
+
+Layout layout_of(const lb_params* p) {
+    Layout L{};
+    L.nsite = (int64_t)p->nx * p->ny * p->nz;
+    const size_t es = storage_size(p->storage);
+    const size_t stride_bytes = round_up((size_t)L.nsite * es, kAlign) + kDirPadBytes;
+    L.dstride = (int64_t)(stride_bytes / es);
+    L.dist_bytes = round_up(stride_bytes * Q, kAlign);
+    L.phi_bytes = round_up((size_t)L.nsite * compute_size(p->storage), kAlign);
+    const int gx = (p->nx + TX - 1) / TX, gy = (p->ny + TY - 1) / TY;
+    L.nblocks = gx * gy * p->nz;
+    L.partial_bytes = round_up((size_t)L.nblocks * 8 * sizeof(double), kAlign);
+    size_t o = 0;
+    for (int b = 0; b < 2; ++b) { L.off_f[b] = o; o += L.dist_bytes; }
+    if (p->model == LB_BINARY) {
+        for (int b = 0; b < 2; ++b) { L.off_g[b] = o; o += L.dist_bytes; }
+        L.off_phi = o; o += L.phi_bytes;
+    } else {
+        L.off_g[0] = L.off_g[1] = L.off_phi = 0;
+    }
+    L.off_partial = o; o += L.partial_bytes;
+    L.total = o;
+    return L;
+}
+
+struct Rec { int kind; hipEvent_t start, stop; };
+
+}  // namespace
+
+struct lb_ctx {
+    lb_params p;
+    Layout L;
+    hipStream_t stream;
+    char* ws;
+    int cur;          // buffer index holding the state
+    bool pending;     // true: the state is propagate(buffer[cur])
+    bool profiling;
+    bool launched;    // any device work queued (lb_destroy waits for it)
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+
+    Geo geo() const {
+        Geo g;
+        g.nx = p.nx; g.ny = p.ny; g.nz = p.nz;
+        g.plane = (uint32_t)p.nx * (uint32_t)p.ny;
+        g.nsite = (uint32_t)L.nsite;
+        g.dstride = L.dstride;
+        return g;
+    }
+    Geo canonical_geo() const { Geo g = geo(); g.dstride = L.nsite; return g; }
+    dim3 grid() const { return dim3((p.nx + TX - 1) / TX, (p.ny + TY - 1) / TY, p.nz); }
+    void* fbuf(int b) const { return ws + L.off_f[b]; }
+    void* gbuf(int b) const { return p.model == LB_BINARY ? ws + L.off_g[b] : nullptr; }
+    void* phi() const { return ws + L.off_phi; }
+    double* partial() const { return reinterpret_cast<double*>(ws + L.off_partial); }
+
+    hipEvent_t take_event() {
+        if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    void release_records() {
+        for (auto& r : recs) { pool.push_back(r.start); pool.push_back(r.stop); }
+        recs.clear();
+    }
+};
+
+namespace {
+
+// Brackets one launch with an event pair when profiling is on.
+struct Timed {
+    lb_ctx* c; int kind; hipEvent_t a = nullptr, b = nullptr;
+    Timed(lb_ctx* c_, int kind_) : c(c_), kind(kind_) {
+        if (c->profiling) {
+            a = c->take_event(); b = c->take_event();
+            if (a && b) (void)hipEventRecord(a, c->stream);
+        }
+    }
+    ~Timed() {
+        if (c->profiling && a && b) {
+            (void)hipEventRecord(b, c->stream);
+            c->recs.push_back({kind, a, b});
+        } else {
+            if (a) c->pool.push_back(a);
+            if (b) c->pool.push_back(b);
+        }
+    }
+};
+
+int launch_status() { return hipGetLastError() == hipSuccess ? LB_OK : LB_EDEVICE; }
+
+
+
+template <class S>
+CollParams<typename Compute<S>::T> coll_params(const lb_ctx* c) {
+    using T = typename Compute<S>::T;
+    CollParams<T> cp;
+    cp.omega_f = (T)(1.0 / c->p.tau_f);
+    const double tau_g = c->p.model == LB_BINARY ? c->p.mobility / c->p.gamma + 0.5 : 1.0;
+    cp.omega_g = (T)(1.0 / tau_g);
+    cp.A = (T)c->p.A; cp.B = (T)c->p.B; cp.kappa = (T)c->p.kappa; cp.gamma = (T)c->p.gamma;
+    const bool dev = c->p.storage != LB_F64;
+    cp.rho0 = dev ? (T)c->p.rho0 : T(0);
+    cp.phi0 = dev ? (T)c->p.phi0 : T(0);
+    return cp;
+}
+
+// ----- typed launchers ------------------------------------------------------
+
+template <class S>
+int run_phi(lb_ctx* c) {
+    using T = typename Compute<S>::T;
+    Timed t(c, LB_K_PHI);
+    const S* g = (const S*)c->gbuf(c->cur);
+    const T phi0 = coll_params<S>(c).phi0;
+    if (c->pending) k_phi<S, true><<<c->grid(), dim3(TX, TY), 0, c->stream>>>(g, (T*)c->phi(), c->geo(), phi0);
+    else k_phi<S, false><<<c->grid(), dim3(TX, TY), 0, c->stream>>>(g, (T*)c->phi(), c->geo(), phi0);
+    return launch_status();
+}
+
+// One collision of the logical state; on return the state is direct.
+template <class S>
+int run_collide(lb_ctx* c) {
+    using T = typename Compute<S>::T;
+    const bool bin = c->p.model == LB_BINARY;
+    if (bin) { int rc = run_phi<S>(c); if (rc) return rc; }
+    const auto cp = coll_params<S>(c);
+    const int src = c->cur, dst = c->pending ? 1 - c->cur : c->cur;
+    const S* fs = (const S*)c->fbuf(src); S* fd = (S*)c->fbuf(dst);
+    const S* gs = (const S*)c->gbuf(src); S* gd = (S*)c->gbuf(dst);
+    const T* phi = (const T*)c->phi();
+    const dim3 grid = c->grid(), block(TX, TY);
+    {
+        Timed t(c, LB_K_COLLIDE);
+        if (bin) {
+            if (c->pending) k_collide<MODEL_BINARY, S, true><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd, phi, c->geo(), cp);
+            else k_collide<MODEL_BINARY, S, false><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd, phi, c->geo(), cp);
+        } else {
+            if (c->pending) k_collide<MODEL_SINGLE, S, true><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd, phi, c->geo(), cp);
+            else k_collide<MODEL_SINGLE, S, false><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd, phi, c->geo(), cp);
+        }
+    }
+    int rc = launch_status();
+    if (rc) return rc;
+    c->cur = dst;
+    c->pending = false;
+    return LB_OK;
+}
+
+// Materialise propagate(buffer[src]) into (f, g) of the given stride.
+template <class S>
+int run_stream_into(lb_ctx* c, int src, S* f, S* g, int64_t stride) {
+    Timed t(c, LB_K_STREAM);
+    k_stream<S><<<c->grid(), dim3(TX, TY), 0, c->stream>>>((const S*)c->fbuf(src), f, c->geo(), stride);
+    if (c->p.model == LB_BINARY)
+        k_stream<S><<<c->grid(), dim3(TX, TY), 0, c->stream>>>((const S*)c->gbuf(src), g, c->geo(), stride);
+    return launch_status();
+}
+
+template <class S>
+int run_propagate(lb_ctx* c) {
+    if (!c->pending) { c->pending = true; return LB_OK; }   // propagation of a direct buffer is deferred
+    const int dst = 1 - c->cur;
+    int rc = run_stream_into<S>(c, c->cur, (S*)c->fbuf(dst), (S*)c->gbuf(dst), c->L.dstride);
+    if (rc) return rc;
+    c->cur = dst;
+    return LB_OK;
+}
+
+template <class S>
+int run_step(lb_ctx* c, int32_t n) {
+    for (int32_t k = 0; k < n; ++k) {
+        int rc = run_collide<S>(c);
+        if (rc) return rc;
+        c->pending = true;
+    }
+    return LB_OK;
+}
+
+template <class S>
+int run_init(lb_ctx* c, const double* rho, const double* u, const double* phi) {
+    Timed t(c, LB_K_OTHER);
+    CollParams<double> cp;
+    const auto ct = coll_params<S>(c);
+    cp.omega_f = ct.omega_f; cp.omega_g = ct.omega_g;
+    cp.A = c->p.A; cp.B = c->p.B; cp.kappa = c->p.kappa; cp.gamma = c->p.gamma;
+    cp.rho0 = c->p.storage == LB_F64 ? 0.0 : c->p.rho0;
+    cp.phi0 = c->p.storage == LB_F64 ? 0.0 : c->p.phi0;
+    S* f = (S*)c->fbuf(c->cur);
+    S* g = (S*)c->gbuf(c->cur);
+    if (c->p.model == LB_BINARY) k_init<MODEL_BINARY, S><<<c->grid(), dim3(TX, TY), 0, c->stream>>>(rho, u, phi, f, g, c->geo(), cp);
+    else k_init<MODEL_SINGLE, S><<<c->grid(), dim3(TX, TY), 0, c->stream>>>(rho, u, phi, f, g, c->geo(), cp);
+    int rc = launch_status();
+    if (rc == LB_OK) c->pending = false;
+    return rc;
+}
+
+template <class S>
+int run_moments(lb_ctx* c, double* rho, double* u, double* phi) {
+    Timed t(c, LB_K_OTHER);
+    const double r0 = c->p.storage == LB_F64 ? 0.0 : c->p.rho0;
+    const double p0 = c->p.storage == LB_F64 ? 0.0 : c->p.phi0;
+    const S* f = (const S*)c->fbuf(c->cur);
+    const S* g = (const S*)c->gbuf(c->cur);
+    const dim3 grid = c->grid(), block(TX, TY);
+    if (c->p.model == LB_BINARY) {
+        if (c->pending) k_moments<MODEL_BINARY, S, true><<<grid, block, 0, c->stream>>>(f, g, rho, u, phi, c->geo(), r0, p0);
+        else k_moments<MODEL_BINARY, S, false><<<grid, block, 0, c->stream>>>(f, g, rho, u, phi, c->geo(), r0, p0);
+    } else {
+        if (c->pending) k_moments<MODEL_SINGLE, S, true><<<grid, block, 0, c->stream>>>(f, g, rho, u, nullptr, c->geo(), r0, p0);
+        else k_moments<MODEL_SINGLE, S, false><<<grid, block, 0, c->stream>>>(f, g, rho, u, nullptr, c->geo(), r0, p0);
+    }
+    return launch_status();
+}
+
+template <class S>
+int run_sums(lb_ctx* c, double* out) {
+    Timed t(c, LB_K_OTHER);
+    const S* f = (const S*)c->fbuf(c->cur);
+    const S* g = (const S*)c->gbuf(c->cur);
+    if (c->p.model == LB_BINARY) k_sums_partial<MODEL_BINARY, S><<<c->grid(), dim3(TX, TY), 0, c->stream>>>(f, g, c->geo(), c->partial());
+    else k_sums_partial<MODEL_SINGLE, S><<<c->grid(), dim3(TX, TY), 0, c->stream>>>(f, g, c->geo(), c->partial());
+    const bool dev = c->p.storage != LB_F64;
+    const double n = (double)c->L.nsite;
+    const double b0 = dev ? n * c->p.rho0 : 0.0;
+    const double b4 = (dev && c->p.model == LB_BINARY) ? n * c->p.phi0 : 0.0;
+    k_sums_final<5><<<1, dim3(TX, TY), 0, c->stream>>>(c->partial(), c->L.nblocks, out, b0, b4, 0);
+    return launch_status();
+}
+
+template <class S>
+int run_get_state(lb_ctx* c, S* f, S* g) {
+    const int64_t n = c->L.nsite;
+    if (c->pending) return run_stream_into<S>(c, c->cur, f, g, n);
+    Timed t(c, LB_K_OTHER);
+    const size_t w = (size_t)n * sizeof(S), sp = (size_t)c->L.dstride * sizeof(S);
+    if (hipMemcpy2DAsync(f, w, c->fbuf(c->cur), sp, w, Q, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+        return LB_EDEVICE;
+    if (c->p.model == LB_BINARY &&
+        hipMemcpy2DAsync(g, w, c->gbuf(c->cur), sp, w, Q, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+        return LB_EDEVICE;
+    return LB_OK;
+}
+
+template <class S>
+int run_set_state(lb_ctx* c, const S* f, const S* g) {
+    Timed t(c, LB_K_OTHER);
+    const int64_t n = c->L.nsite;
+    const size_t w = (size_t)n * sizeof(S), sp = (size_t)c->L.dstride * sizeof(S);
+    if (hipMemcpy2DAsync(c->fbuf(c->cur), sp, f, w, w, Q, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+        return LB_EDEVICE;
+    if (c->p.model == LB_BINARY &&
+        hipMemcpy2DAsync(c->gbuf(c->cur), sp, g, w, w, Q, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+        return LB_EDEVICE;
+    c->pending = false;
+    return LB_OK;
+}
+
+// Dispatch on the storage type.
+template <class F>
+int by_storage(lb_ctx* c, F&& fn) {
+    c->launched = true;
+    switch (c->p.storage) {
+        case LB_F64: return fn((double*)nullptr);
+        case LB_F32: return fn((float*)nullptr);
+        case LB_F16: return fn((_Float16*)nullptr);
+    }
+    return LB_EINVAL;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lb_workspace_bytes(const lb_params* p, size_t* bytes) {
+    if (!bytes) return LB_EINVAL;
+    int rc = check_params(p);
+    if (rc) return rc;
+    *bytes = layout_of(p).total;
+    return LB_OK;
+}
+
+int lb_create(const lb_params* p, void* workspace, size_t workspace_bytes, void* stream, lb_ctx** out) {
+    if (!out) return LB_EINVAL;
+    *out = nullptr;
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (!workspace || ((uintptr_t)workspace % 256) != 0) return LB_EINVAL;
+    const Layout L = layout_of(p);
+    if (workspace_bytes < L.total) return LB_ENOMEM;
+    lb_ctx* c = new (std::nothrow) lb_ctx();
+    if (!c) return LB_ENOMEM;
+    c->p = *p;
+    c->L = L;
+    c->stream = (hipStream_t)stream;
+    c->ws = (char*)workspace;
+    c->cur = 0;
+    c->pending = false;
+    c->profiling = false;
+    c->launched = false;
+    *out = c;
+    return LB_OK;
+}
+
+int lb_set_stream(lb_ctx* c, void* stream) {
+    if (!c) return LB_EINVAL;
+    c->stream = (hipStream_t)stream;
+    return LB_OK;
+}
+
+int lb_init_equilibrium(lb_ctx* c, const double* rho, const double* u, const double* phi) {
+    if (!c || !rho || !u) return LB_EINVAL;
+    if (c->p.model == LB_BINARY && !phi) return LB_EINVAL;
+    return by_storage(c, [&](auto tag) {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        return run_init<S>(c, rho, u, phi);
+    });
+}
+
+int lb_collide(lb_ctx* c) {
+    if (!c) return LB_EINVAL;
+    return by_storage(c, [&](auto tag) {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        return run_collide<S>(c);
+    });
+}
+
+int lb_propagate(lb_ctx* c) {
+    if (!c) return LB_EINVAL;
+    return by_storage(c, [&](auto tag) {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        return run_propagate<S>(c);
+    });
+}
+
+int lb_step(lb_ctx* c, int32_t nsteps) {
+    if (!c || nsteps < 0) return LB_EINVAL;
+    if (nsteps == 0) return LB_OK;
+    return by_storage(c, [&](auto tag) {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        return run_step<S>(c, nsteps);
+    });
+}
+
+int lb_moments(lb_ctx* c, double* rho, double* u, double* phi) {
+    if (!c) return LB_EINVAL;
+    if (phi && c->p.model != LB_BINARY) return LB_EINVAL;
+    if (!rho && !u && !phi) return LB_OK;
+    return by_storage(c, [&](auto tag) {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        return run_moments<S>(c, rho, u, phi);
+    });
+}
+
+int lb_conserved_sums(lb_ctx* c, double* out) {
+    if (!c || !out) return LB_EINVAL;
+    return by_storage(c, [&](auto tag) {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        return run_sums<S>(c, out);
+    });
+}
+
+int lb_get_state(lb_ctx* c, void* f, void* g) {
+    if (!c || !f) return LB_EINVAL;
+    if ((c->p.model == LB_BINARY) != (g != nullptr)) return LB_EINVAL;
+    return by_storage(c, [&](auto tag) {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        return run_get_state<S>(c, (S*)f, (S*)g);
+    });
+}
+
+int lb_set_state(lb_ctx* c, const void* f, const void* g) {
+    if (!c || !f) return LB_EINVAL;
+    if ((c->p.model == LB_BINARY) != (g != nullptr)) return LB_EINVAL;
+    return by_storage(c, [&](auto tag) {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        return run_set_state<S>(c, (const S*)f, (const S*)g);
+    });
+}
+
+int lb_set_tau(lb_ctx* c, double tau_f) {
+    if (!c || !std::isfinite(tau_f) || !(tau_f > 0.5)) return LB_EINVAL;
+    c->p.tau_f = tau_f;
+    return LB_OK;
+}
+
+int lb_adjoint_step(lb_ctx* c, const double* f_n, const double* lam_next, double* lam_n, double* domega) {
+    if (!c || !f_n || !lam_next || !lam_n || !domega) return LB_EINVAL;
+    if (c->p.model != LB_SINGLE || c->p.storage != LB_F64) return LB_ENOTSUP;
+    if (lam_n == lam_next || lam_n == f_n) return LB_EINVAL;
+    c->launched = true;
+    {
+        Timed t(c, LB_K_ADJOINT);
+        k_adjoint<<<c->grid(), dim3(TX, TY), 0, c->stream>>>(f_n, lam_next, lam_n, c->partial(), c->canonical_geo(),
+                                                           1.0 / c->p.tau_f);
+    }
+    k_sums_final<1><<<1, dim3(TX, TY), 0, c->stream>>>(c->partial(), c->L.nblocks, domega, 0.0, 0.0, 1);
+    return launch_status();
+}
+
+int lb_profile(lb_ctx* c, int enable) {
+    if (!c) return LB_EINVAL;
+    if (enable) {
+        if (hipStreamSynchronize(c->stream) != hipSuccess) return LB_EDEVICE;
+        c->release_records();
+    }
+    c->profiling = enable != 0;
+    return LB_OK;
+}
+
+int lb_kernel_times(lb_ctx* c, int kind, double* total_ms, int64_t* launches) {
+    if (!c || !total_ms || !launches || kind < 0 || kind > LB_K_OTHER) return LB_EINVAL;
+    double ms = 0.0;
+    int64_t n = 0;
+    for (auto& r : c->recs) {
+        if (r.kind != kind) continue;
+        if (hipEventSynchronize(r.stop) != hipSuccess) return LB_EDEVICE;
+        float e = 0.0f;
+        if (hipEventElapsedTime(&e, r.start, r.stop) != hipSuccess) return LB_EDEVICE;
+        ms += e;
+        ++n;
+    }
+    *total_ms = ms;
+    *launches = n;
+    return LB_OK;
+}
+
+int lb_destroy(lb_ctx* c) {
+    if (!c) return LB_OK;
+    int rc = LB_OK;
+    if (c->launched && hipStreamSynchronize(c->stream) != hipSuccess) rc = LB_EDEVICE;
+    c->release_records();
+    for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+    delete c;
+    return rc;
+}
+
+const char* lb_strerror(int status) {
+    switch (status) {
+        case LB_OK: return "ok";
+        case LB_EINVAL: return "invalid argument";
+        case LB_ENOMEM: return "workspace too small";
+        case LB_EDEVICE: return "HIP runtime or kernel launch failure";
+        case LB_ENOTSUP: return "not supported for this model or storage";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

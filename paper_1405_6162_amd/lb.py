@@ -1,0 +1,285 @@
+"""Python binding of liblb.so: the C ABI of include/lb.h, same names,
+argument marshalling only.
+
+Device memory and streams come from PyTorch: the workspace is a uint8 CUDA
+(HIP) tensor, every array passed in or out is a contiguous device tensor,
+and calls are queued on ``torch.cuda.current_stream()``.  Every step of the
+update runs in the HIP kernels of liblb.so; there is no CPU fallback, and
+``load()`` raises if the library has not been built.
+"""
+
+import ctypes
+import os
+
+import torch
+
+LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_ENOTSUP = 0, -1, -2, -3, -4
+LB_SINGLE, LB_BINARY = 0, 1
+LB_F64, LB_F32, LB_F16 = 0, 1, 2
+LB_K_COLLIDE, LB_K_PHI, LB_K_STREAM, LB_K_ADJOINT, LB_K_OTHER = 0, 1, 2, 3, 4
+Q = 19
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "liblb.so")
+
+STORAGE_DTYPE = {LB_F64: torch.float64, LB_F32: torch.float32, LB_F16: torch.float16}
+
+
+class LBError(RuntimeError):
+    def __init__(self, fn, status):
+        self.status = status
+        msg = _lib.lb_strerror(status).decode() if _lib is not None else str(status)
+        super().__init__("%s failed: %s (%d)" % (fn, msg, status))
+
+
+class lb_params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("model", ctypes.c_int32), ("storage", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("tau_f", ctypes.c_double),
+        ("A", ctypes.c_double), ("B", ctypes.c_double), ("kappa", ctypes.c_double),
+        ("mobility", ctypes.c_double), ("gamma", ctypes.c_double),
+        ("rho0", ctypes.c_double), ("phi0", ctypes.c_double),
+    ]
+
+
+def make_params(nx, ny, nz, model=LB_SINGLE, storage=LB_F64, tau_f=1.0, A=-0.0625, B=0.0625,
+                kappa=0.04, mobility=0.45, gamma=1.0, rho0=1.0, phi0=0.0):
+    return lb_params(nx, ny, nz, model, storage, 0, tau_f, A, B, kappa, mobility, gamma, rho0, phi0)
+
+
+_lib = None
+_vp, _i32, _int = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int
+_SIGNATURES = {
+    "lb_workspace_bytes": (_int, [ctypes.POINTER(lb_params), ctypes.POINTER(ctypes.c_size_t)]),
+    "lb_create": (_int, [ctypes.POINTER(lb_params), _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]),
+    "lb_set_stream": (_int, [_vp, _vp]),
+    "lb_init_equilibrium": (_int, [_vp, _vp, _vp, _vp]),
+    "lb_collide": (_int, [_vp]),
+    "lb_propagate": (_int, [_vp]),
+    "lb_step": (_int, [_vp, _i32]),
+    "lb_moments": (_int, [_vp, _vp, _vp, _vp]),
+    "lb_conserved_sums": (_int, [_vp, _vp]),
+    "lb_get_state": (_int, [_vp, _vp, _vp]),
+    "lb_set_state": (_int, [_vp, _vp, _vp]),
+    "lb_set_tau": (_int, [_vp, ctypes.c_double]),
+    "lb_adjoint_step": (_int, [_vp, _vp, _vp, _vp, _vp]),
+    "lb_profile": (_int, [_vp, _int]),
+    "lb_kernel_times": (_int, [_vp, _int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
+    "lb_destroy": (_int, [_vp]),
+    "lb_strerror": (ctypes.c_char_p, [_int]),
+}
+
+
+def load(path=LIB_PATH):
+    """Load liblb.so (once).  Raises if it is missing: there is no fallback."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("liblb.so not built (%s); run python -m paper_1405_6162_amd.build" % path)
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype, fn.argtypes = res, args
+    _lib = lib
+    return lib
+
+
+def _check(fn, rc):
+    if rc != LB_OK:
+        raise LBError(fn, rc)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("liblb.so takes device tensors")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def _stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+# ---- the C ABI, one Python function per symbol -----------------------------
+
+def lb_workspace_bytes(params):
+    load()
+    n = ctypes.c_size_t(0)
+    _check("lb_workspace_bytes", _lib.lb_workspace_bytes(ctypes.byref(params), ctypes.byref(n)))
+    return n.value
+
+
+def lb_create(params, workspace, stream=None):
+    load()
+    ctx = _vp()
+    nbytes = workspace.numel() * workspace.element_size()
+    _check("lb_create", _lib.lb_create(ctypes.byref(params), _ptr(workspace), nbytes,
+                                       _stream() if stream is None else stream, ctypes.byref(ctx)))
+    return ctx
+
+
+def lb_set_stream(ctx, stream):
+    _check("lb_set_stream", _lib.lb_set_stream(ctx, stream))
+
+
+def lb_init_equilibrium(ctx, rho, u, phi=None):
+    _check("lb_init_equilibrium", _lib.lb_init_equilibrium(ctx, _ptr(rho), _ptr(u), _ptr(phi)))
+
+
+def lb_collide(ctx):
+    _check("lb_collide", _lib.lb_collide(ctx))
+
+
+def lb_propagate(ctx):
+    _check("lb_propagate", _lib.lb_propagate(ctx))
+
+
+def lb_step(ctx, nsteps):
+    _check("lb_step", _lib.lb_step(ctx, int(nsteps)))
+
+
+def lb_moments(ctx, rho, u, phi=None):
+    _check("lb_moments", _lib.lb_moments(ctx, _ptr(rho), _ptr(u), _ptr(phi)))
+
+
+def lb_conserved_sums(ctx, out):
+    _check("lb_conserved_sums", _lib.lb_conserved_sums(ctx, _ptr(out)))
+
+
+def lb_get_state(ctx, f, g=None):
+    _check("lb_get_state", _lib.lb_get_state(ctx, _ptr(f), _ptr(g)))
+
+
+def lb_set_state(ctx, f, g=None):
+    _check("lb_set_state", _lib.lb_set_state(ctx, _ptr(f), _ptr(g)))
+
+
+def lb_set_tau(ctx, tau_f):
+    _check("lb_set_tau", _lib.lb_set_tau(ctx, float(tau_f)))
+
+
+def lb_adjoint_step(ctx, f_n, lam_next, lam_n, domega):
+    _check("lb_adjoint_step", _lib.lb_adjoint_step(ctx, _ptr(f_n), _ptr(lam_next), _ptr(lam_n), _ptr(domega)))
+
+
+def lb_profile(ctx, enable):
+    _check("lb_profile", _lib.lb_profile(ctx, 1 if enable else 0))
+
+
+def lb_kernel_times(ctx, kind):
+    ms, n = ctypes.c_double(0.0), ctypes.c_int64(0)
+    _check("lb_kernel_times", _lib.lb_kernel_times(ctx, kind, ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
+def lb_destroy(ctx):
+    if _lib is not None and ctx is not None:
+        _check("lb_destroy", _lib.lb_destroy(ctx))
+
+
+def lb_strerror(status):
+    load()
+    return _lib.lb_strerror(status).decode()
+
+
+# ---- a small owner object ---------------------------------------------------
+
+class Lattice:
+    """One context plus the torch-owned workspace it borrows.
+
+    Shapes: scalar fields (nz, ny, nx); vector fields (3, nz, ny, nx);
+    distributions (19, nz, ny, nx), all contiguous on the device.
+    """
+
+    def __init__(self, nx, ny, nz, model=LB_SINGLE, storage=LB_F64, device="cuda", **phys):
+        self.params = make_params(nx, ny, nz, model=model, storage=storage, **phys)
+        self.shape = (nz, ny, nx)
+        self.model, self.storage = model, storage
+        self.device = torch.device(device)
+        nbytes = lb_workspace_bytes(self.params)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.ctx = lb_create(self.params, self.workspace)
+
+    @property
+    def nsite(self):
+        return self.shape[0] * self.shape[1] * self.shape[2]
+
+    def _dev(self, a, count, dtype=torch.float64, name="array"):
+        t = torch.as_tensor(a, dtype=dtype, device=self.device).contiguous()
+        if t.numel() != count:
+            raise ValueError("%s has %d elements, expected %d" % (name, t.numel(), count))
+        return t
+
+    def init_equilibrium(self, rho, u, phi=None):
+        n = self.nsite
+        rho, u = self._dev(rho, n, name="rho"), self._dev(u, 3 * n, name="u")
+        if (phi is None) != (self.model != LB_BINARY):
+            raise ValueError("phi is required for the binary model and only for it")
+        phi = self._dev(phi, n, name="phi") if phi is not None else None
+        lb_set_stream(self.ctx, _stream())
+        lb_init_equilibrium(self.ctx, rho, u, phi)
+        self._keep = (rho, u, phi)          # inputs stay alive until the queued kernel ran
+
+    def step(self, n=1):
+        lb_set_stream(self.ctx, _stream())
+        lb_step(self.ctx, n)
+
+    def collide(self):
+        lb_set_stream(self.ctx, _stream())
+        lb_collide(self.ctx)
+
+    def propagate(self):
+        lb_set_stream(self.ctx, _stream())
+        lb_propagate(self.ctx)
+
+    def moments(self):
+        lb_set_stream(self.ctx, _stream())
+        rho = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        u = torch.empty((3,) + self.shape, dtype=torch.float64, device=self.device)
+        phi = torch.empty(self.shape, dtype=torch.float64, device=self.device) \
+            if self.model == LB_BINARY else None
+        lb_moments(self.ctx, rho, u, phi)
+        return rho, u, phi
+
+    def conserved_sums(self):
+        lb_set_stream(self.ctx, _stream())
+        out = torch.empty(5, dtype=torch.float64, device=self.device)
+        lb_conserved_sums(self.ctx, out)
+        return out
+
+    def get_state(self):
+        lb_set_stream(self.ctx, _stream())
+        dt = STORAGE_DTYPE[self.storage]
+        f = torch.empty((Q,) + self.shape, dtype=dt, device=self.device)
+        g = torch.empty_like(f) if self.model == LB_BINARY else None
+        lb_get_state(self.ctx, f, g)
+        return f, g
+
+    def set_state(self, f, g=None):
+        lb_set_stream(self.ctx, _stream())
+        dt = STORAGE_DTYPE[self.storage]
+        if (g is None) != (self.model != LB_BINARY):
+            raise ValueError("g is required for the binary model and only for it")
+        f = self._dev(f, Q * self.nsite, dt, "f")
+        g = self._dev(g, Q * self.nsite, dt, "g") if g is not None else None
+        lb_set_state(self.ctx, f, g)
+        self._keep = (f, g)
+
+    def set_tau(self, tau_f):
+        lb_set_tau(self.ctx, tau_f)
+        self.params.tau_f = float(tau_f)
+
+    def close(self):
+        if self.ctx is not None:
+            lb_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
