@@ -1,0 +1,107 @@
+"""Adjoint (reverse) of the single-fluid FP64 step on the GPU, against the
+oracle's hand-derived adjoint (itself pinned by complex-step derivatives)
+and against central finite differences of the GPU forward."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import lb_oracle as O
+from paper_1405_6162_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def relerr(a, ref):
+    return float(np.abs(np.asarray(a) - ref).max() / np.abs(ref).max())
+
+
+def _state(nx, ny, nz, seed, noise=1e-3):
+    rho, u = inputs.shear_wave(nx, ny, nz, amplitude=0.01, noise=noise, seed=seed)
+    f = O.init_single(rho, u)
+    rng = np.random.default_rng(seed + 50)
+    return f + 1e-4 * rng.standard_normal(f.shape) * O.W[:, None, None, None]
+
+
+@pytest.mark.parametrize("nx,ny,nz", [(4, 4, 4), (5, 6, 7), (67, 9, 5), (16, 16, 16)])
+def test_adjoint_step_kernel(lbgpu, nx, ny, nz):
+    print("case adjoint step", nx, ny, nz, flush=True)
+    tau = 0.8
+    f = _state(nx, ny, nz, seed=1)
+    rng = np.random.default_rng(2)
+    lam_next = rng.standard_normal(f.shape)
+    want, want_dw = O.adjoint_step_single(f, lam_next, tau)
+    lat = lbgpu.Lattice(nx, ny, nz, tau_f=tau)
+    dev = lambda a: torch.as_tensor(a, device="cuda").contiguous()
+    ft, lt = dev(f), dev(lam_next)
+    out = torch.empty_like(lt)
+    dw = torch.full((1,), 0.25, dtype=torch.float64, device="cuda")   # the call increments it
+    lbgpu.lb_set_stream(lat.ctx, lbgpu._stream())
+    lbgpu.lb_adjoint_step(lat.ctx, ft, lt, out, dw)
+    assert relerr(out.cpu().numpy(), want) < 1e-12
+    assert abs(dw.item() - 0.25 - want_dw) <= 1e-12 * max(abs(want_dw), np.abs(want).max())
+
+
+@pytest.mark.parametrize("nsteps,every", [(7, 3), (7, 7), (7, 1), (6, 2), (0, 4)])
+def test_rollout_gradient_vs_oracle(lbgpu, nsteps, every):
+    from paper_1405_6162_amd.adjoint import rollout, velocity_loss
+    nx, ny, nz, tau = 8, 8, 8, 0.8
+    f0 = _state(nx, ny, nz, seed=3)
+    loss_o, g_o, dtau_o = O.rollout_gradient(f0, tau, nsteps)
+    lat = lbgpu.Lattice(nx, ny, nz, tau_f=tau)
+    f0t = torch.tensor(f0, device="cuda", requires_grad=True)
+    taut = torch.tensor(tau, dtype=torch.float64, device="cuda", requires_grad=True)
+    loss = velocity_loss(rollout(f0t, taut, lat, nsteps, every))
+    loss.backward()
+    assert abs(loss.item() - loss_o) <= 1e-12 * loss_o
+    assert relerr(f0t.grad.cpu().numpy(), g_o) < 1e-10
+    if nsteps > 0:
+        assert abs(taut.grad.item() - dtau_o) <= 1e-10 * abs(dtau_o)
+    else:
+        assert taut.grad.item() == 0.0
+
+
+def test_shear_wave_64_adjoint_vs_finite_differences(lbgpu):
+    """64^3, u_x = 0.01 sin(2 pi y / 64) + U(-1e-4, 1e-4) noise on each
+    component, rho = 1, f = f^eq, tau = 0.8 (learnable), 200 steps, loss =
+    mean u.u at the final step, checkpoints every 20 steps.  Gradients with
+    respect to 20 random components of f0 and tau against central
+    differences (eps = 1e-6) of the GPU forward."""
+    from paper_1405_6162_amd.adjoint import rollout, velocity_loss
+    n, tau, T, K, eps = 64, 0.8, 200, 20, 1e-6
+    rho, u = inputs.shear_wave(n, n, n, amplitude=0.01, noise=1e-4, seed=0)
+    lat = lbgpu.Lattice(n, n, n, tau_f=tau)
+    lat.init_equilibrium(rho, u)
+    f0 = lat.get_state()[0].clone()
+    f0t = f0.clone().requires_grad_(True)
+    taut = torch.tensor(tau, dtype=torch.float64, device="cuda", requires_grad=True)
+    loss = velocity_loss(rollout(f0t, taut, lat, T, K))
+    loss.backward()
+    g = f0t.grad.reshape(19, -1)
+    # closed-form estimate: viscous decay exp(-2 nu k^2 T), nu = (tau - 1/2)/3
+    k = 2 * np.pi / n
+    est = 0.5 * 0.01 ** 2 * np.exp(-2 * (tau - 0.5) / 3 * k * k * T)
+    assert abs(loss.item() / est - 1) < 0.05
+
+    def L(f, t):
+        lat.set_tau(t)
+        lat.set_state(f)
+        lat.step(T)
+        return velocity_loss(lat.get_state()[0]).item()
+
+    comps = inputs.sample_components(n ** 3, 20, seed=1)
+    gmax = g.abs().max().item()
+    worst = 0.0
+    for (i, s) in comps:
+        fp, fm = f0.clone(), f0.clone()
+        fp.view(19, -1)[i, s] += eps
+        fm.view(19, -1)[i, s] -= eps
+        fd = (L(fp, tau) - L(fm, tau)) / (2 * eps)
+        err = abs(fd - g[i, s].item())
+        worst = max(worst, err / (abs(fd) + 1e-5 * gmax))
+        # 1e-6 relative, with a floor of 1e-5 max|g| for components near zero
+        assert err <= 1e-6 * abs(fd) + 1e-5 * gmax, (i, s, fd, g[i, s].item())
+    fd_tau = (L(f0, tau + eps) - L(f0, tau - eps)) / (2 * eps)
+    print("adjoint vs FD: worst component %.2e, tau rel %.2e (dL/dtau %.4e)"
+          % (worst, abs(fd_tau - taut.grad.item()) / abs(fd_tau), taut.grad.item()), flush=True)
+    assert abs(fd_tau - taut.grad.item()) <= 1e-6 * abs(fd_tau)
