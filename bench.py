@@ -33,6 +33,10 @@ WORKLOADS = {
     "binary384_f32": ("binary", "f32", 384, "D3Q19 binary fluid 384^3 periodic, FP32 deviation storage"),
     "single256_f64": ("single", "f64", 256, "D3Q19 single-fluid BGK 256^3 periodic, FP64, tau = 1"),
     "single256_f32": ("single", "f32", 256, "D3Q19 single-fluid BGK 256^3 periodic, FP32 deviation storage"),
+    "adjoint64_f64": ("adjoint", "f64", 64, "D3Q19 single-fluid BGK 64^3 shear wave, FP64, 200-step rollout "
+                                            "+ adjoint with checkpoints every 20 steps"),
+    "adjoint128_f64": ("adjoint", "f64", 128, "D3Q19 single-fluid BGK 128^3 shear wave, FP64, 200-step rollout "
+                                              "+ adjoint with checkpoints every 20 steps"),
 }
 
 ES = {"f64": 8, "f32": 4, "f16": 2}
@@ -45,12 +49,26 @@ def log(*a):
 def algorithmic_bytes(model, storage):
     """Bytes per site the method must move, per kernel: every distribution
     value read once and written once; phi written once by its kernel and
-    read once by the collision (compute precision: 8 B for FP64, else 4)."""
+    read once by the collision (compute precision: 8 B for FP64, else 4);
+    the adjoint step reads f^n and lambda^{n+1} and writes lambda^n."""
     es = ES[storage]
     ps = 8 if storage == "f64" else 4
     if model == "single":
         return {"collide": 2 * 19 * es, "phi": 0}
+    if model == "adjoint":
+        return {"collide": 2 * 19 * es, "phi": 0, "adjoint": 3 * 19 * es, "stream": 2 * 19 * es}
     return {"collide": 2 * 38 * es + ps, "phi": 19 * es + ps}
+
+
+def traffic_from_profile(workload):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter summary, or None when there is none or the kernel
+    sources changed since it was taken."""
+    from paper_1405_6162_amd import profsummary
+    info = profsummary.read_traffic(os.path.join(ROOT, "profiles", "pmc_%s.txt" % workload))
+    if not info or info.get("source_digest") != profsummary.kernel_source_digest():
+        return None
+    return int(float(info["traffic_bytes_per_launch"]))
 
 
 def cpu_baseline(model, n, seconds_target=12.0):
@@ -101,6 +119,63 @@ def copy_probe(torch, nbytes=2 << 30, reps=10):
     return {"bytes_per_launch": 2 * nbytes, "GB/s": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
 
 
+def bench_adjoint(args, n, desc, T=200, K=20):
+    """Forward rollout + backward (recompute + adjoint kernel) per timed
+    iteration; a step here is one forward step plus one adjoint step."""
+    import torch
+    from paper_1405_6162_amd import inputs, lb
+    from paper_1405_6162_amd.adjoint import rollout, velocity_loss
+    log("bench: %s" % desc)
+    rho, u = inputs.shear_wave(n, n, n, amplitude=0.01, noise=1e-4, seed=0)
+    lat = lb.Lattice(n, n, n, tau_f=0.8)
+    lat.init_equilibrium(rho, u)
+    f0 = lat.get_state()[0].clone()
+
+    def once():
+        f = f0.clone().requires_grad_(True)
+        tau = torch.tensor(0.8, dtype=torch.float64, device="cuda", requires_grad=True)
+        loss = velocity_loss(rollout(f, tau, lat, T, K))
+        loss.backward()
+        return f.grad, tau.grad
+
+    for _ in range(max(args.warmup // 10, 1)):
+        once()
+    torch.cuda.synchronize()
+    iters = max(args.steps // 100, 1)
+    lb.lb_profile(lat.ctx, True)
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        g, gt = once()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lb.lb_profile(lat.ctx, False)
+    adj_ms, adj_n = lb.lb_kernel_times(lat.ctx, lb.LB_K_ADJOINT)
+    finite = bool(torch.isfinite(g).all()) and bool(torch.isfinite(gt))
+    lat.close()
+    if not finite:
+        print("non-finite gradient", file=sys.stderr)
+        sys.exit(1)
+    nsite = n ** 3
+    alg = algorithmic_bytes("adjoint", "f64")
+    avg = adj_ms / max(adj_n, 1)
+    achieved = alg["adjoint"] * nsite / (avg * 1e-3) / 1e9
+    out = {
+        "metric": METRIC, "value": round(nsite * T * iters / wall / 1e6, 2), "unit": "MLUPS",
+        "n_gpus": 1, "steps": T * iters, "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / (T * iters), 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": desc, "nx": n, "ny": n, "nz": n, "tau": 0.8, "rollout_steps": T,
+                   "checkpoint_every": K, "seed": 0},
+        "roofline": {"bound": "hbm", "kernel": "k_adjoint (adjoint of the fused step)",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(args.workload),
+                     "bytes_per_site": alg["adjoint"], "avg_launch_ms": round(avg, 5), "launches": adj_n},
+    }
+    if not args.no_copy:
+        out["copy_probe"] = copy_probe(torch)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,6 +200,8 @@ def main():
     model, storage, n, desc = WORKLOADS[args.workload]
     lb.load()
     torch.cuda.set_device(0)
+    if model == "adjoint":
+        return bench_adjoint(args, n, desc)
     mcode = lb.LB_BINARY if model == "binary" else lb.LB_SINGLE
     scode = {"f64": lb.LB_F64, "f32": lb.LB_F32, "f16": lb.LB_F16}[storage]
     log("bench: %s, %d warmup + %d timed steps" % (desc, args.warmup, args.steps))
@@ -193,7 +270,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": traffic_from_profile(args.workload),
             "bytes_per_site": alg["collide"],
             "avg_launch_ms": round(col_avg_ms, 5),
             "launches": col_n,

@@ -41,44 +41,100 @@ template <> struct Compute<double>   { using T = double; };
 template <> struct Compute<float>    { using T = float; };
 template <> struct Compute<_Float16> { using T = float; };
 
-template <class T, class S> __device__ __forceinline__ T load_as(const S* p) { return static_cast<T>(*p); }
-template <class S, class T> __device__ __forceinline__ void store_as(S* p, T v) { *p = static_cast<S>(v); }
 
 // Lattice geometry.  Site offsets fit in 32 bits (N < 2^31 is checked on
-// the host); direction offsets (i * dstride) are 64-bit.
+// the host); direction offsets (i * dstride) are 64-bit.  gx, gy, gz and
+// nblocks describe the tiling of the launch that receives this Geo.
 struct Geo {
     int nx, ny, nz;
     uint32_t plane;     // nx * ny
     uint32_t nsite;     // nx * ny * nz
     int64_t dstride;    // elements between consecutive direction arrays
+    int gx, gy, gz;     // tiles along x, y and z
+    int nblocks;        // gx * gy * gz: the 1-D grid size
 };
 
-// Launch tile: one site per lane, 64 x 4 sites of one z plane per block, so a
-// wavefront covers 64 consecutive x and every direction array is read and
-// written in 512-byte (FP64) contiguous runs.
-constexpr int TX = 64;
-constexpr int TY = 4;
-constexpr int TPB = TX * TY;
+// Launch policy.  A block covers TX x TY x TZ sites; each lane owns one
+// (x, y) column of the tile and TZ consecutive z planes of it (TZ sites per
+// lane: the strip-mined "virtual vector" of the targetDP execution model,
+// Section III-C, mapped onto a GPU lane).  A wavefront spans 64 consecutive
+// x, so every direction array is read and written in contiguous runs.
+// Blocks form a 1-D grid; with XCD ordering, block b is given tile
+// (b mod 8) * nblocks/8 + b/8, so each of the eight XCDs (which receive
+// blocks round-robin) sweeps a contiguous slab of tiles and the neighbouring
+// rows a pull or a stencil touches are in its own L2.  NTL / NTS select
+// nontemporal loads / stores of the distributions.
+template <int TX_, int TY_, int TZ_, bool NTL_, bool NTS_, bool XCD_>
+struct Tiling {
+    static constexpr int TX = TX_, TY = TY_, TZ = TZ_, TPB = TX_ * TY_;
+    static constexpr bool nt_load = NTL_, nt_store = NTS_, xcd = XCD_;
+    static_assert(TPB % 64 == 0, "whole wavefronts");
+};
 
-// Coordinates of this lane's site and of its +-1 neighbours (periodic).
+__host__ __device__ constexpr int tiles(int n, int t) { return (n + t - 1) / t; }
+
+// The lane's (x, y) column, its +-1 neighbours (periodic), and the tile origin.
+struct Column {
+    int x, y, xm, xp, ym, yp;
+    int x0, y0, z0;
+    bool active;        // (x, y) inside the lattice
+};
+
+// One site of the column: z, its +-1 neighbours, and whether z < nz.
 struct Site {
     int x, y, z, xm, xp, ym, yp, zm, zp;
     bool active;
 };
 
-__device__ __forceinline__ Site site_of_thread(const Geo& g) {
+template <class P>
+__device__ __forceinline__ int tile_index(const Geo& g) {
+    int b = blockIdx.x;
+    if constexpr (P::xcd) {
+        if ((g.nblocks & 7) == 0) b = (b & 7) * (g.nblocks >> 3) + (b >> 3);
+    }
+    return b;
+}
+
+template <class P>
+__device__ __forceinline__ Column column_of_thread(const Geo& g) {
+    const int b = tile_index<P>(g);
+    const int bx = b % g.gx;
+    const int t = b / g.gx;
+    const int by = t % g.gy;
+    Column c;
+    c.z0 = (t / g.gy) * P::TZ;
+    c.x0 = bx * P::TX;
+    c.y0 = by * P::TY;
+    c.x = c.x0 + (int)(threadIdx.x % P::TX);
+    c.y = c.y0 + (int)(threadIdx.x / P::TX);
+    c.active = (c.x < g.nx) && (c.y < g.ny);
+    c.xm = c.x == 0 ? g.nx - 1 : c.x - 1;
+    c.xp = c.x + 1 >= g.nx ? 0 : c.x + 1;
+    c.ym = c.y == 0 ? g.ny - 1 : c.y - 1;
+    c.yp = c.y + 1 >= g.ny ? 0 : c.y + 1;
+    return c;
+}
+
+__device__ __forceinline__ Site site_at(const Column& c, int v, const Geo& g) {
     Site s;
-    s.x = blockIdx.x * TX + threadIdx.x;
-    s.y = blockIdx.y * TY + threadIdx.y;
-    s.z = blockIdx.z;
-    s.active = (s.x < g.nx) && (s.y < g.ny);
-    s.xm = s.x == 0 ? g.nx - 1 : s.x - 1;
-    s.xp = s.x + 1 >= g.nx ? 0 : s.x + 1;
-    s.ym = s.y == 0 ? g.ny - 1 : s.y - 1;
-    s.yp = s.y + 1 >= g.ny ? 0 : s.y + 1;
+    s.x = c.x; s.y = c.y; s.xm = c.xm; s.xp = c.xp; s.ym = c.ym; s.yp = c.yp;
+    s.z = c.z0 + v;
+    s.active = c.active && s.z < g.nz;
     s.zm = s.z == 0 ? g.nz - 1 : s.z - 1;
     s.zp = s.z + 1 >= g.nz ? 0 : s.z + 1;
     return s;
+}
+
+// Global loads and stores, nontemporal when the policy says so.
+template <bool NT, class S>
+__device__ __forceinline__ S ldg(const S* p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NT, class S>
+__device__ __forceinline__ void stg(S* p, S v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
 }
 
 // Offset of the site s + (dx, dy, dz), each of dx, dy, dz in {-1, 0, 1}.

@@ -1,10 +1,11 @@
 // gfx950 kernels of the D3Q19 lattice-Boltzmann update.
 //
-// One lattice site per lane; every distribution is stored structure-of-arrays
-// (direction-major, x fastest), so each of the 19 (binary: 38) direction
-// streams is a coalesced HBM stream.  The update is bandwidth bound (well
-// under one flop per byte), so there is no MFMA here: the design goal is to
-// move each distribution value through HBM once per step.
+// Every distribution is stored structure-of-arrays (direction-major, x
+// fastest; the paper's lattice-field layout, Section III-B), and each lane
+// updates TZ sites of one (x, y) column, so each of the 19 (binary: 38)
+// direction streams is a coalesced HBM stream.  The update is bandwidth
+// bound (well under one flop per byte), so there is no MFMA here: the design
+// goal is to move each distribution value through HBM once per step.
 //
 // State convention.  A buffer either holds the state itself ("direct") or a
 // post-collision field whose propagation is still pending; in the second
@@ -80,86 +81,20 @@ struct FreeEnergy {
     }
 };
 
-// ---------------------------------------------------------------------------
-// Order parameter: phi(s) = phi0 + sum_i e_i, e = g - w phi0 (deviation).
-// ---------------------------------------------------------------------------
-
-template <class S, bool GATHER>
-__global__ __launch_bounds__(TPB) void k_phi(const S* __restrict__ g, typename Compute<S>::T* __restrict__ phi,
-                                             Geo geo, typename Compute<S>::T phi0) {
-    using T = typename Compute<S>::T;
-    const Site st = site_of_thread(geo);
-    if (!st.active) return;
-    T acc = T(0);
+// Load the 19 populations of one site (pulled from s - c_i when GATHER).
+template <class P, bool GATHER, class S, class T>
+__device__ __forceinline__ void load_site(const S* src, const Site& st, const Geo& geo, T (&v)[Q]) {
     static_for<0, Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        acc = acc + load_as<T>(g + i * geo.dstride + src_offset<i, GATHER>(st, geo));
+        v[i] = static_cast<T>(ldg<P::nt_load>(src + i * geo.dstride + src_offset<i, GATHER>(st, geo)));
     });
-    phi[offset_at<0, 0, 0>(st, geo)] = phi0 + acc;
 }
 
-// ---------------------------------------------------------------------------
-// Collision (GATHER = false: in place on a direct buffer) or fused pull-stream
-// + collision (GATHER = true: pending src buffer -> direct dst buffer).
-// The binary model stages the phi tile of this z plane (with a one-site halo
-// in x and y) in LDS for the gradient and Laplacian; the two z neighbours are
-// read straight from the phi field.
-// ---------------------------------------------------------------------------
-
-template <int MODEL, class S, bool GATHER>
-__global__ __launch_bounds__(TPB) void k_collide(const S* fsrc, const S* gsrc, S* fdst, S* gdst,
-                                                 const typename Compute<S>::T* __restrict__ phi, Geo geo,
-                                                 CollParams<typename Compute<S>::T> cp) {
-    using T = typename Compute<S>::T;
-    const Site st = site_of_thread(geo);
-
-    T phic = T(0), gx = T(0), gy = T(0), gz = T(0), lap = T(0);
-    if constexpr (MODEL == MODEL_BINARY) {
-        __shared__ T tile[TY + 2][TX + 2];
-        const int x0 = (int)blockIdx.x * TX - 1;
-        const int y0 = (int)blockIdx.y * TY - 1;
-        const uint32_t zoff = (uint32_t)st.z * geo.plane;
-        for (int k = threadIdx.y * TX + threadIdx.x; k < (TX + 2) * (TY + 2); k += TPB) {
-            const int lx = k % (TX + 2), ly = k / (TX + 2);
-            int xx = (x0 + lx) % geo.nx;
-            int yy = (y0 + ly) % geo.ny;
-            xx += xx < 0 ? geo.nx : 0;
-            yy += yy < 0 ? geo.ny : 0;
-            tile[ly][lx] = phi[zoff + (uint32_t)yy * (uint32_t)geo.nx + (uint32_t)xx];
-        }
-        __syncthreads();
-        if (!st.active) return;
-        const int lx = threadIdx.x + 1, ly = threadIdx.y + 1;
-        phic = tile[ly][lx];
-        const T pxm = tile[ly][lx - 1], pxp = tile[ly][lx + 1];
-        const T pym = tile[ly - 1][lx], pyp = tile[ly + 1][lx];
-        const T pzm = phi[offset_at<0, 0, -1>(st, geo)];
-        const T pzp = phi[offset_at<0, 0, 1>(st, geo)];
-        gx = T(0.5) * (pxp - pxm);
-        gy = T(0.5) * (pyp - pym);
-        gz = T(0.5) * (pzp - pzm);
-        lap = (pxp + pxm) + (pyp + pym) + (pzp + pzm) - T(6) * phic;
-    } else {
-        if (!st.active) return;
-    }
-
-    const uint32_t off = offset_at<0, 0, 0>(st, geo);
-
-    T f[Q];
-    static_for<0, Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        f[i] = load_as<T>(fsrc + i * geo.dstride + src_offset<i, GATHER>(st, geo));
-    });
-    T g[Q];
-    if constexpr (MODEL == MODEL_BINARY) {
-        static_for<0, Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            g[i] = load_as<T>(gsrc + i * geo.dstride + src_offset<i, GATHER>(st, geo));
-        });
-    }
-
-    // Moments (deviation form: rho = rho0 + sum d_i, j = sum d_i c_i).
-    T drho = T(0), jx = T(0), jy = T(0), jz = T(0);
+// Density deviation and momentum of 19 populations (deviation form:
+// rho = rho0 + sum d_i, j = sum d_i c_i).
+template <class T>
+__device__ __forceinline__ void moments_of(const T (&f)[Q], T& drho, T& jx, T& jy, T& jz) {
+    drho = T(0); jx = T(0); jy = T(0); jz = T(0);
     static_for<0, Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         drho = drho + f[i];
@@ -170,30 +105,126 @@ __global__ __launch_bounds__(TPB) void k_collide(const S* fsrc, const S* gsrc, S
         if constexpr (cz(i) > 0) jz = jz + f[i];
         if constexpr (cz(i) < 0) jz = jz - f[i];
     });
+}
+
+// ---------------------------------------------------------------------------
+// Order parameter: phi(s) = phi0 + sum_i e_i, e = g - w phi0 (deviation).
+// ---------------------------------------------------------------------------
+
+template <class P, class S, bool GATHER>
+__global__ __launch_bounds__(P::TPB) void k_phi(const S* __restrict__ g, typename Compute<S>::T* __restrict__ phi,
+                                                Geo geo, typename Compute<S>::T phi0) {
+    using T = typename Compute<S>::T;
+    const Column col = column_of_thread<P>(geo);
+#pragma unroll
+    for (int v = 0; v < P::TZ; ++v) {
+        const Site st = site_at(col, v, geo);
+        if (!st.active) continue;
+        T acc = T(0);
+        static_for<0, Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            acc = acc + static_cast<T>(ldg<P::nt_load>(g + i * geo.dstride + src_offset<i, GATHER>(st, geo)));
+        });
+        phi[offset_at<0, 0, 0>(st, geo)] = phi0 + acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Collision (GATHER = false: in place on a direct buffer) or fused pull-stream
+// + collision (GATHER = true: pending src buffer -> direct dst buffer).
+// The binary model stages the phi tile of the block (TX x TY x TZ sites plus
+// a one-site halo on every side) in LDS; the gradient and Laplacian read
+// their six neighbours from there.
+// ---------------------------------------------------------------------------
+
+template <class P, class S, class T>
+__device__ __forceinline__ void relax_single(const T (&f)[Q], S* fdst, uint32_t off, const Geo& geo,
+                                             const CollParams<T>& cp) {
+    T drho, jx, jy, jz;
+    moments_of(f, drho, jx, jy, jz);
     const T rho = cp.rho0 + drho;
     const T ux = jx / rho, uy = jy / rho, uz = jz / rho;
     const T usq = ux * ux + uy * uy + uz * uz;
+    static_for<0, Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        const T cu = cdot<i>(ux, uy, uz);
+        const T base = T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq;
+        const T feq = weight<T>(i) * (drho + rho * base);
+        stg<P::nt_store>(fdst + i * geo.dstride + off, static_cast<S>(f[i] - cp.omega_f * (f[i] - feq)));
+    });
+}
 
+template <class P, class S, class T>
+__device__ __forceinline__ void relax_binary(const T (&f)[Q], const T (&g)[Q], S* fdst, S* gdst, uint32_t off,
+                                             const Geo& geo, const CollParams<T>& cp, T phic, T gx, T gy, T gz,
+                                             T lap) {
+    T drho, jx, jy, jz;
+    moments_of(f, drho, jx, jy, jz);
+    const T rho = cp.rho0 + drho;
+    const T ux = jx / rho, uy = jy / rho, uz = jz / rho;
+    const T usq = ux * ux + uy * uy + uz * uz;
+    const FreeEnergy<T> fe(phic, gx, gy, gz, lap, cp);
+    const T dphi = phic - cp.phi0;
+    static_for<0, Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        const T cu = cdot<i>(ux, uy, uz);
+        const T base = T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq;
+        const T feq = weight<T>(i) * (drho + rho * base + fe.template stress_term<i>(cp));
+        const T geq = weight<T>(i) * (dphi + phic * base + fe.template mobility_term<i>(cp));
+        stg<P::nt_store>(fdst + i * geo.dstride + off, static_cast<S>(f[i] - cp.omega_f * (f[i] - feq)));
+        stg<P::nt_store>(gdst + i * geo.dstride + off, static_cast<S>(g[i] - cp.omega_g * (g[i] - geq)));
+    });
+}
+
+template <class P, int MODEL, class S, bool GATHER>
+__global__ __launch_bounds__(P::TPB) void k_collide(const S* fsrc, const S* gsrc, S* fdst, S* gdst,
+                                                    const typename Compute<S>::T* __restrict__ phi, Geo geo,
+                                                    CollParams<typename Compute<S>::T> cp) {
+    using T = typename Compute<S>::T;
+    const Column col = column_of_thread<P>(geo);
     if constexpr (MODEL == MODEL_BINARY) {
-        const FreeEnergy<T> fe(phic, gx, gy, gz, lap, cp);
-        const T dphi = phic - cp.phi0;
-        static_for<0, Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            const T cu = cdot<i>(ux, uy, uz);
-            const T base = T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq;
-            const T feq = weight<T>(i) * (drho + rho * base + fe.template stress_term<i>(cp));
-            const T geq = weight<T>(i) * (dphi + phic * base + fe.template mobility_term<i>(cp));
-            store_as(fdst + i * geo.dstride + off, f[i] - cp.omega_f * (f[i] - feq));
-            store_as(gdst + i * geo.dstride + off, g[i] - cp.omega_g * (g[i] - geq));
-        });
+        constexpr int TX = P::TX, TY = P::TY, TZ = P::TZ;
+        constexpr int LX = TX + 2, LY = TY + 2, LZ = TZ + 2;
+        __shared__ T tile[LZ][LY][LX];
+        for (int k = threadIdx.x; k < LX * LY * LZ; k += P::TPB) {
+            const int lx = k % LX, ly = (k / LX) % LY, lz = k / (LX * LY);
+            int xx = (col.x0 - 1 + lx) % geo.nx;
+            int yy = (col.y0 - 1 + ly) % geo.ny;
+            int zz = (col.z0 - 1 + lz) % geo.nz;
+            xx += xx < 0 ? geo.nx : 0;
+            yy += yy < 0 ? geo.ny : 0;
+            zz += zz < 0 ? geo.nz : 0;
+            tile[lz][ly][lx] = phi[(uint32_t)zz * geo.plane + (uint32_t)yy * (uint32_t)geo.nx + (uint32_t)xx];
+        }
+        __syncthreads();
+        const int lx = col.x - col.x0 + 1, ly = col.y - col.y0 + 1;
+#pragma unroll
+        for (int v = 0; v < TZ; ++v) {
+            const Site st = site_at(col, v, geo);
+            if (!st.active) continue;
+            const int lz = v + 1;
+            const T phic = tile[lz][ly][lx];
+            const T pxm = tile[lz][ly][lx - 1], pxp = tile[lz][ly][lx + 1];
+            const T pym = tile[lz][ly - 1][lx], pyp = tile[lz][ly + 1][lx];
+            const T pzm = tile[lz - 1][ly][lx], pzp = tile[lz + 1][ly][lx];
+            const T gx = T(0.5) * (pxp - pxm);
+            const T gy = T(0.5) * (pyp - pym);
+            const T gz = T(0.5) * (pzp - pzm);
+            const T lap = (pxp + pxm) + (pyp + pym) + (pzp + pzm) - T(6) * phic;
+            T f[Q], g[Q];
+            load_site<P, GATHER>(fsrc, st, geo, f);
+            load_site<P, GATHER>(gsrc, st, geo, g);
+            relax_binary<P>(f, g, fdst, gdst, offset_at<0, 0, 0>(st, geo), geo, cp, phic, gx, gy, gz, lap);
+        }
     } else {
-        static_for<0, Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            const T cu = cdot<i>(ux, uy, uz);
-            const T base = T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq;
-            const T feq = weight<T>(i) * (drho + rho * base);
-            store_as(fdst + i * geo.dstride + off, f[i] - cp.omega_f * (f[i] - feq));
-        });
+#pragma unroll
+        for (int v = 0; v < P::TZ; ++v) {
+            const Site st = site_at(col, v, geo);
+            if (!st.active) continue;
+            T f[Q];
+            load_site<P, GATHER>(fsrc, st, geo, f);
+            relax_single<P>(f, fdst, offset_at<0, 0, 0>(st, geo), geo, cp);
+        }
     }
 }
 
@@ -202,55 +233,65 @@ __global__ __launch_bounds__(TPB) void k_collide(const S* fsrc, const S* gsrc, S
 // materialise a pending buffer into caller memory of another stride.
 // ---------------------------------------------------------------------------
 
-template <class S>
-__global__ __launch_bounds__(TPB) void k_stream(const S* __restrict__ src, S* __restrict__ dst, Geo geo,
-                                                int64_t dst_stride) {
-    const Site st = site_of_thread(geo);
-    if (!st.active) return;
-    const uint32_t off = offset_at<0, 0, 0>(st, geo);
-    static_for<0, Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        dst[i * dst_stride + off] = src[i * geo.dstride + src_offset<i, true>(st, geo)];
-    });
+template <class P, class S>
+__global__ __launch_bounds__(P::TPB) void k_stream(const S* __restrict__ src, S* __restrict__ dst, Geo geo,
+                                                   int64_t dst_stride) {
+    const Column col = column_of_thread<P>(geo);
+#pragma unroll
+    for (int v = 0; v < P::TZ; ++v) {
+        const Site st = site_at(col, v, geo);
+        if (!st.active) continue;
+        const uint32_t off = offset_at<0, 0, 0>(st, geo);
+        static_for<0, Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            stg<P::nt_store>(dst + i * dst_stride + off,
+                             ldg<P::nt_load>(src + i * geo.dstride + src_offset<i, true>(st, geo)));
+        });
+    }
 }
 
 // ---------------------------------------------------------------------------
 // Equilibrium initialisation (FP64 arithmetic, stored in S as deviations).
 // ---------------------------------------------------------------------------
 
-template <int MODEL, class S>
-__global__ __launch_bounds__(TPB) void k_init(const double* __restrict__ rho_in, const double* __restrict__ u_in,
-                                              const double* __restrict__ phi_in, S* __restrict__ f,
-                                              S* __restrict__ g, Geo geo, CollParams<double> cp) {
-    const Site st = site_of_thread(geo);
-    if (!st.active) return;
-    const uint32_t off = offset_at<0, 0, 0>(st, geo);
-    const double rho = rho_in[off];
-    const double ux = u_in[off], uy = u_in[geo.nsite + off], uz = u_in[2 * (size_t)geo.nsite + off];
-    const double usq = ux * ux + uy * uy + uz * uz;
-    const double drho = rho - cp.rho0;
-    if constexpr (MODEL == MODEL_BINARY) {
-        const double p = phi_in[off];
-        const double pxm = phi_in[offset_at<-1, 0, 0>(st, geo)], pxp = phi_in[offset_at<1, 0, 0>(st, geo)];
-        const double pym = phi_in[offset_at<0, -1, 0>(st, geo)], pyp = phi_in[offset_at<0, 1, 0>(st, geo)];
-        const double pzm = phi_in[offset_at<0, 0, -1>(st, geo)], pzp = phi_in[offset_at<0, 0, 1>(st, geo)];
-        const double lap = (pxp + pxm) + (pyp + pym) + (pzp + pzm) - 6.0 * p;
-        const FreeEnergy<double> fe(p, 0.5 * (pxp - pxm), 0.5 * (pyp - pym), 0.5 * (pzp - pzm), lap, cp);
-        const double dphi = p - cp.phi0;
-        static_for<0, Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            const double cu = cdot<i>(ux, uy, uz);
-            const double base = 3.0 * cu + 4.5 * cu * cu - 1.5 * usq;
-            store_as(f + i * geo.dstride + off, weight<double>(i) * (drho + rho * base + fe.template stress_term<i>(cp)));
-            store_as(g + i * geo.dstride + off, weight<double>(i) * (dphi + p * base + fe.template mobility_term<i>(cp)));
-        });
-    } else {
-        static_for<0, Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            const double cu = cdot<i>(ux, uy, uz);
-            const double base = 3.0 * cu + 4.5 * cu * cu - 1.5 * usq;
-            store_as(f + i * geo.dstride + off, weight<double>(i) * (drho + rho * base));
-        });
+template <class P, int MODEL, class S>
+__global__ __launch_bounds__(P::TPB) void k_init(const double* __restrict__ rho_in, const double* __restrict__ u_in,
+                                                 const double* __restrict__ phi_in, S* __restrict__ f,
+                                                 S* __restrict__ g, Geo geo, CollParams<double> cp) {
+    const Column col = column_of_thread<P>(geo);
+    for (int v = 0; v < P::TZ; ++v) {
+        const Site st = site_at(col, v, geo);
+        if (!st.active) continue;
+        const uint32_t off = offset_at<0, 0, 0>(st, geo);
+        const double rho = rho_in[off];
+        const double ux = u_in[off], uy = u_in[geo.nsite + off], uz = u_in[2 * (size_t)geo.nsite + off];
+        const double usq = ux * ux + uy * uy + uz * uz;
+        const double drho = rho - cp.rho0;
+        if constexpr (MODEL == MODEL_BINARY) {
+            const double p = phi_in[off];
+            const double pxm = phi_in[offset_at<-1, 0, 0>(st, geo)], pxp = phi_in[offset_at<1, 0, 0>(st, geo)];
+            const double pym = phi_in[offset_at<0, -1, 0>(st, geo)], pyp = phi_in[offset_at<0, 1, 0>(st, geo)];
+            const double pzm = phi_in[offset_at<0, 0, -1>(st, geo)], pzp = phi_in[offset_at<0, 0, 1>(st, geo)];
+            const double lap = (pxp + pxm) + (pyp + pym) + (pzp + pzm) - 6.0 * p;
+            const FreeEnergy<double> fe(p, 0.5 * (pxp - pxm), 0.5 * (pyp - pym), 0.5 * (pzp - pzm), lap, cp);
+            const double dphi = p - cp.phi0;
+            static_for<0, Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                const double cu = cdot<i>(ux, uy, uz);
+                const double base = 3.0 * cu + 4.5 * cu * cu - 1.5 * usq;
+                f[i * geo.dstride + off] =
+                    static_cast<S>(weight<double>(i) * (drho + rho * base + fe.template stress_term<i>(cp)));
+                g[i * geo.dstride + off] =
+                    static_cast<S>(weight<double>(i) * (dphi + p * base + fe.template mobility_term<i>(cp)));
+            });
+        } else {
+            static_for<0, Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                const double cu = cdot<i>(ux, uy, uz);
+                const double base = 3.0 * cu + 4.5 * cu * cu - 1.5 * usq;
+                f[i * geo.dstride + off] = static_cast<S>(weight<double>(i) * (drho + rho * base));
+            });
+        }
     }
 }
 
@@ -258,40 +299,39 @@ __global__ __launch_bounds__(TPB) void k_init(const double* __restrict__ rho_in,
 // Moments of the current state in FP64 (pending buffers are read by pull).
 // ---------------------------------------------------------------------------
 
-template <int MODEL, class S, bool GATHER>
-__global__ __launch_bounds__(TPB) void k_moments(const S* __restrict__ f, const S* __restrict__ g,
-                                                 double* __restrict__ rho_out, double* __restrict__ u_out,
-                                                 double* __restrict__ phi_out, Geo geo, double rho0, double phi0) {
-    const Site st = site_of_thread(geo);
-    if (!st.active) return;
-    const uint32_t off = offset_at<0, 0, 0>(st, geo);
-    double drho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
-    static_for<0, Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        const double v = load_as<double>(f + i * geo.dstride + src_offset<i, GATHER>(st, geo));
-        drho = drho + v;
-        if constexpr (cx(i) > 0) jx = jx + v;
-        if constexpr (cx(i) < 0) jx = jx - v;
-        if constexpr (cy(i) > 0) jy = jy + v;
-        if constexpr (cy(i) < 0) jy = jy - v;
-        if constexpr (cz(i) > 0) jz = jz + v;
-        if constexpr (cz(i) < 0) jz = jz - v;
-    });
-    const double rho = rho0 + drho;
-    if (rho_out) rho_out[off] = rho;
-    if (u_out) {
-        u_out[off] = jx / rho;
-        u_out[geo.nsite + off] = jy / rho;
-        u_out[2 * (size_t)geo.nsite + off] = jz / rho;
-    }
-    if constexpr (MODEL == MODEL_BINARY) {
-        if (phi_out) {
-            double acc = 0.0;
-            static_for<0, Q>([&](auto I) {
-                constexpr int i = decltype(I)::value;
-                acc = acc + load_as<double>(g + i * geo.dstride + src_offset<i, GATHER>(st, geo));
-            });
-            phi_out[off] = phi0 + acc;
+template <class P, int MODEL, class S, bool GATHER>
+__global__ __launch_bounds__(P::TPB) void k_moments(const S* __restrict__ f, const S* __restrict__ g,
+                                                    double* __restrict__ rho_out, double* __restrict__ u_out,
+                                                    double* __restrict__ phi_out, Geo geo, double rho0,
+                                                    double phi0) {
+    const Column col = column_of_thread<P>(geo);
+    for (int v = 0; v < P::TZ; ++v) {
+        const Site st = site_at(col, v, geo);
+        if (!st.active) continue;
+        const uint32_t off = offset_at<0, 0, 0>(st, geo);
+        double fv[Q];
+        static_for<0, Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            fv[i] = static_cast<double>(f[i * geo.dstride + src_offset<i, GATHER>(st, geo)]);
+        });
+        double drho, jx, jy, jz;
+        moments_of(fv, drho, jx, jy, jz);
+        const double rho = rho0 + drho;
+        if (rho_out) rho_out[off] = rho;
+        if (u_out) {
+            u_out[off] = jx / rho;
+            u_out[geo.nsite + off] = jy / rho;
+            u_out[2 * (size_t)geo.nsite + off] = jz / rho;
+        }
+        if constexpr (MODEL == MODEL_BINARY) {
+            if (phi_out) {
+                double acc = 0.0;
+                static_for<0, Q>([&](auto I) {
+                    constexpr int i = decltype(I)::value;
+                    acc = acc + static_cast<double>(g[i * geo.dstride + src_offset<i, GATHER>(st, geo)]);
+                });
+                phi_out[off] = phi0 + acc;
+            }
         }
     }
 }
@@ -301,15 +341,11 @@ __global__ __launch_bounds__(TPB) void k_moments(const S* __restrict__ f, const 
 // block partials in index order.
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ int block_linear() {
-    return (int)(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z));
-}
-
 // Tree sum over the block of K values per thread, in a fixed order; on return
 // sh[k][0] holds the block total of value k (visible to every thread).
-template <int K>
+template <int TPB, int K>
 __device__ __forceinline__ void block_tree_sum(const double (&v)[K], double (*sh)[TPB]) {
-    const int t = threadIdx.y * TX + threadIdx.x;
+    const int t = threadIdx.x;
 #pragma unroll
     for (int k = 0; k < K; ++k) sh[k][t] = v[k];
     __syncthreads();
@@ -325,35 +361,38 @@ __device__ __forceinline__ void block_tree_sum(const double (&v)[K], double (*sh
 // Local sums of the stored values (streaming permutes values, so the sums of
 // a pending buffer equal those of the state it stands for, up to the order
 // of the additions).
-template <int MODEL, class S>
-__global__ __launch_bounds__(TPB) void k_sums_partial(const S* __restrict__ f, const S* __restrict__ g, Geo geo,
-                                                      double* __restrict__ partial) {
-    __shared__ double sh[5][TPB];
-    const Site st = site_of_thread(geo);
-    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (st.active) {
+template <class P, int MODEL, class S>
+__global__ __launch_bounds__(P::TPB) void k_sums_partial(const S* __restrict__ f, const S* __restrict__ g, Geo geo,
+                                                         double* __restrict__ partial) {
+    __shared__ double sh[5][P::TPB];
+    const Column col = column_of_thread<P>(geo);
+    double v5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int v = 0; v < P::TZ; ++v) {
+        const Site st = site_at(col, v, geo);
+        if (!st.active) continue;
         const uint32_t off = offset_at<0, 0, 0>(st, geo);
         static_for<0, Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            const double a = load_as<double>(f + i * geo.dstride + off);
-            v[0] = v[0] + a;
-            if constexpr (cx(i) != 0) v[1] = v[1] + cx(i) * a;
-            if constexpr (cy(i) != 0) v[2] = v[2] + cy(i) * a;
-            if constexpr (cz(i) != 0) v[3] = v[3] + cz(i) * a;
-            if constexpr (MODEL == MODEL_BINARY) v[4] = v[4] + load_as<double>(g + i * geo.dstride + off);
+            const double a = static_cast<double>(f[i * geo.dstride + off]);
+            v5[0] = v5[0] + a;
+            if constexpr (cx(i) != 0) v5[1] = v5[1] + cx(i) * a;
+            if constexpr (cy(i) != 0) v5[2] = v5[2] + cy(i) * a;
+            if constexpr (cz(i) != 0) v5[3] = v5[3] + cz(i) * a;
+            if constexpr (MODEL == MODEL_BINARY) v5[4] = v5[4] + static_cast<double>(g[i * geo.dstride + off]);
         });
     }
-    block_tree_sum<5>(v, sh);
-    const int t = threadIdx.y * TX + threadIdx.x;
-    if (t < 5) partial[8 * (size_t)block_linear() + t] = sh[t][0];
+    block_tree_sum<P::TPB, 5>(v5, sh);
+    const int t = threadIdx.x;
+    if (t < 5) partial[8 * (size_t)blockIdx.x + t] = sh[t][0];
 }
 
-// out[k] = base[k] + sum_b partial[8 b + k], k < K; one block of TPB threads.
-template <int K>
-__global__ __launch_bounds__(TPB) void k_sums_final(const double* __restrict__ partial, int nblocks, double* out,
-                                                    double base0, double base4, int accumulate) {
+// out[k] = base[k] + sum_b partial[8 b + k], k < K; one block of P::TPB threads.
+template <class P, int K>
+__global__ __launch_bounds__(P::TPB) void k_sums_final(const double* __restrict__ partial, int nblocks, double* out,
+                                                       double base0, double base4, int accumulate) {
+    constexpr int TPB = P::TPB;
     __shared__ double sh[K][TPB];
-    const int t = threadIdx.y * TX + threadIdx.x;
+    const int t = threadIdx.x;
     double v[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = 0.0;
@@ -361,7 +400,7 @@ __global__ __launch_bounds__(TPB) void k_sums_final(const double* __restrict__ p
 #pragma unroll
         for (int k = 0; k < K; ++k) v[k] = v[k] + partial[8 * (size_t)b + k];
     }
-    block_tree_sum<K>(v, sh);
+    block_tree_sum<TPB, K>(v, sh);
     if (t == 0) {
         for (int k = 0; k < K; ++k) {
             double r = sh[k][0];
@@ -377,13 +416,16 @@ __global__ __launch_bounds__(TPB) void k_sums_final(const double* __restrict__ p
 // lambda*_i(s) = lambda^{n+1}_i(s + c_i) is the transpose of the pull.
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(TPB) void k_adjoint(const double* __restrict__ fn, const double* __restrict__ lam_next,
-                                                 double* __restrict__ lam_n, double* __restrict__ partial, Geo geo,
-                                                 double omega) {
-    __shared__ double sh[1][TPB];
-    const Site st = site_of_thread(geo);
+template <class P>
+__global__ __launch_bounds__(P::TPB) void k_adjoint(const double* __restrict__ fn, const double* __restrict__ lam_next,
+                                                    double* __restrict__ lam_n, double* __restrict__ partial, Geo geo,
+                                                    double omega) {
+    __shared__ double sh[1][P::TPB];
+    const Column col = column_of_thread<P>(geo);
     double dw[1] = {0.0};
-    if (st.active) {
+    for (int v = 0; v < P::TZ; ++v) {
+        const Site st = site_at(col, v, geo);
+        if (!st.active) continue;
         const uint32_t off = offset_at<0, 0, 0>(st, geo);
         double f[Q], ls[Q];
         static_for<0, Q>([&](auto I) {
@@ -391,21 +433,12 @@ __global__ __launch_bounds__(TPB) void k_adjoint(const double* __restrict__ fn, 
             f[i] = fn[i * geo.dstride + off];
             ls[i] = lam_next[i * geo.dstride + offset_at<cx(i), cy(i), cz(i)>(st, geo)];
         });
-        double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
-        static_for<0, Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            rho = rho + f[i];
-            if constexpr (cx(i) > 0) jx = jx + f[i];
-            if constexpr (cx(i) < 0) jx = jx - f[i];
-            if constexpr (cy(i) > 0) jy = jy + f[i];
-            if constexpr (cy(i) < 0) jy = jy - f[i];
-            if constexpr (cz(i) > 0) jz = jz + f[i];
-            if constexpr (cz(i) < 0) jz = jz - f[i];
-        });
+        double rho, jx, jy, jz;
+        moments_of(f, rho, jx, jy, jz);
         const double ux = jx / rho, uy = jy / rho, uz = jz / rho;
         const double usq = ux * ux + uy * uy + uz * uz;
         // S = sum_i lambda*_i f^eq_i / rho = sum_i lambda*_i w_i E_i;
-        // T_a = rho sum_i lambda*_i w_i (3 c_ia + 9 (c_i.u) c_ia - 3 u_a).
+        // T_a / rho = sum_i lambda*_i w_i (3 c_ia + 9 (c_i.u) c_ia - 3 u_a).
         double Ssum = 0.0, lw = 0.0, tx = 0.0, ty = 0.0, tz = 0.0, dom = 0.0;
         static_for<0, Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
@@ -423,7 +456,6 @@ __global__ __launch_bounds__(TPB) void k_adjoint(const double* __restrict__ fn, 
             if constexpr (cz(i) < 0) tz = tz - h;
             dom = dom + ls[i] * (weight<double>(i) * rho * E - f[i]);
         });
-        // T_a / rho = tx - 3 u_a lw
         const double Tx = tx - 3.0 * ux * lw, Ty = ty - 3.0 * uy * lw, Tz = tz - 3.0 * uz * lw;
         const double TU = Tx * ux + Ty * uy + Tz * uz;
         static_for<0, Q>([&](auto I) {
@@ -431,10 +463,10 @@ __global__ __launch_bounds__(TPB) void k_adjoint(const double* __restrict__ fn, 
             const double tc = cdot<i>(Tx, Ty, Tz);
             lam_n[i * geo.dstride + off] = (1.0 - omega) * ls[i] + omega * (Ssum + tc - TU);
         });
-        dw[0] = dom;
+        dw[0] = dw[0] + dom;
     }
-    block_tree_sum<1>(dw, sh);
-    if (threadIdx.x == 0 && threadIdx.y == 0) partial[8 * (size_t)block_linear()] = sh[0][0];
+    block_tree_sum<P::TPB, 1>(dw, sh);
+    if (threadIdx.x == 0) partial[8 * (size_t)blockIdx.x] = sh[0][0];
 }
 
 }  // namespace lbk
