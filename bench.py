@@ -1,8 +1,9 @@
 #!/usr/bin/env python3
 """Throughput of the D3Q19 lattice-Boltzmann step on one MI355X.
 
-A step is one full update of every site: for the binary fluid the
-order-parameter kernel and the fused pull-stream + collision kernel.  The
+A step is one full update of every site: one launch of the fused
+pull-stream + collision kernel (for the binary fluid the single-pass kernel
+that also computes phi and its stencils).  The
 default workload is the binary fluid on a 128^3 periodic lattice in FP64
 (spinodal quench, rho = 1, u = 0, phi ~ U(-0.05, 0.05), seed 0), whose
 100-step run is the benchmark configuration.
@@ -37,6 +38,10 @@ WORKLOADS = {
                                             "+ adjoint with checkpoints every 20 steps"),
     "adjoint128_f64": ("adjoint", "f64", 128, "D3Q19 single-fluid BGK 128^3 shear wave, FP64, 200-step rollout "
                                               "+ adjoint with checkpoints every 20 steps"),
+    "precision256_f32": ("precision", "f32", 256, "D3Q19 binary fluid 256^3 spinodal quench, 500 steps: FP32 "
+                                                  "deviation storage against FP64"),
+    "precision384_f16": ("precision", "f16", 384, "D3Q19 binary fluid 384^3 spinodal quench, 1000 steps: FP16 "
+                                                  "deviation storage against FP32, and a 96^3 run against FP64"),
 }
 
 ES = {"f64": 8, "f32": 4, "f16": 2}
@@ -47,17 +52,16 @@ def log(*a):
 
 
 def algorithmic_bytes(model, storage):
-    """Bytes per site the method must move, per kernel: every distribution
-    value read once and written once; phi written once by its kernel and
-    read once by the collision (compute precision: 8 B for FP64, else 4);
-    the adjoint step reads f^n and lambda^{n+1} and writes lambda^n."""
+    """Bytes per site the method must move in one step: every distribution
+    value read once and written once (the binary step is a single kernel
+    that computes phi and its stencils on chip, so phi adds nothing); the
+    adjoint step reads f^n and lambda^{n+1} and writes lambda^n."""
     es = ES[storage]
-    ps = 8 if storage == "f64" else 4
     if model == "single":
-        return {"collide": 2 * 19 * es, "phi": 0}
+        return {"collide": 2 * 19 * es}
     if model == "adjoint":
-        return {"collide": 2 * 19 * es, "phi": 0, "adjoint": 3 * 19 * es, "stream": 2 * 19 * es}
-    return {"collide": 2 * 38 * es + ps, "phi": 19 * es + ps}
+        return {"collide": 2 * 19 * es, "adjoint": 3 * 19 * es}
+    return {"collide": 2 * 38 * es}
 
 
 def traffic_from_profile(workload):
@@ -176,6 +180,80 @@ def bench_adjoint(args, n, desc, T=200, K=20):
     print(json.dumps(out), flush=True)
 
 
+def _moment_errors(lb, ref, other):
+    """Per-moment max-norm relative errors of `other` against `ref` (Lattice
+    objects on the same lattice), and each one's conserved sums."""
+    r0, u0, p0 = ref.moments()
+    r1, u1, p1 = other.moments()
+    rel = lambda a, b: float((a - b).abs().max() / b.abs().max())
+    return {"rho": rel(r1, r0), "u": rel(u1, u0), "phi": rel(p1, p0)}, p0, p1
+
+
+def coarsening_length(phi):
+    """L = 2 pi sum S(k) / sum |k| S(k) over k != 0, S = |FFT(phi)|^2."""
+    import torch
+    n = phi.shape
+    S = torch.fft.fftn(phi.to(torch.float64)).abs() ** 2
+    ks = [2 * torch.pi * torch.fft.fftfreq(m, device=phi.device, dtype=torch.float64) for m in n]
+    kz, ky, kx = torch.meshgrid(*ks, indexing="ij")
+    k = torch.sqrt(kx * kx + ky * ky + kz * kz)
+    S[0, 0, 0] = 0
+    return float(2 * torch.pi * S.sum() / (k * S).sum())
+
+
+def bench_precision(args, storage, n, desc):
+    """Run the reduced-precision lattice and its reference from the same
+    spinodal initial state and report per-moment errors, drift and MLUPS."""
+    import torch
+    from paper_1405_6162_amd import inputs, lb
+    code = {"f64": lb.LB_F64, "f32": lb.LB_F32, "f16": lb.LB_F16}
+    ref_storage = "f64" if storage == "f32" else "f32"
+    steps = 500 if storage == "f32" else 1000
+    log("bench: %s" % desc)
+
+    def run(sto, nn, nsteps):
+        rho, u, phi = inputs.spinodal_quench(nn, nn, nn, seed=0)
+        lat = lb.Lattice(nn, nn, nn, model=lb.LB_BINARY, storage=code[sto], rho0=1.0, phi0=float(phi.mean()))
+        lat.init_equilibrium(rho, u, phi)
+        s0 = lat.conserved_sums().cpu()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat.step(nsteps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        s1 = lat.conserved_sums().cpu()
+        drift = {"mass_rel": float(abs(s1[0] - s0[0]) / abs(s0[0])),
+                 "phi_per_site": float(abs(s1[4] - s0[4]) / nn ** 3)}
+        return lat, nn ** 3 * nsteps / dt / 1e6, drift
+
+    ref, ref_mlups, ref_drift = run(ref_storage, n, steps)
+    low, mlups, drift = run(storage, n, steps)
+    err, p_ref, p_low = _moment_errors(lb, ref, low)
+    out = {"metric": METRIC, "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1, "steps": steps,
+           "warmup": 0, "ms_per_step": round(n ** 3 / mlups / 1e3, 5), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": storage, "data": "synthetic",
+           "config": {"workload": desc, "nx": n, "ny": n, "nz": n, "seed": 0},
+           "reference": {"storage": ref_storage, "MLUPS": round(ref_mlups, 2),
+                         "speedup": round(mlups / ref_mlups, 3)},
+           "errors_vs_reference": err, "drift": drift, "reference_drift": ref_drift,
+           "coarsening_length": {storage: coarsening_length(p_low), ref_storage: coarsening_length(p_ref)}}
+    ref.close()
+    low.close()
+    if storage == "f16":
+        # 96^3 run of all three storages, errors against the FP64 one
+        sub = {}
+        r64, _, d64 = run("f64", 96, steps)
+        for sto in ("f32", "f16"):
+            lat, _, d = run(sto, 96, steps)
+            e, p64, pl = _moment_errors(lb, r64, lat)
+            sub[sto] = {"errors_vs_f64": e, "drift": d, "coarsening_length": coarsening_length(pl)}
+            lat.close()
+        sub["f64"] = {"drift": d64, "coarsening_length": coarsening_length(p64)}
+        r64.close()
+        out["sub_run_96"] = sub
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -202,6 +280,8 @@ def main():
     torch.cuda.set_device(0)
     if model == "adjoint":
         return bench_adjoint(args, n, desc)
+    if model == "precision":
+        return bench_precision(args, storage, n, desc)
     mcode = lb.LB_BINARY if model == "binary" else lb.LB_SINGLE
     scode = {"f64": lb.LB_F64, "f32": lb.LB_F32, "f16": lb.LB_F16}[storage]
     log("bench: %s, %d warmup + %d timed steps" % (desc, args.warmup, args.steps))
@@ -230,7 +310,6 @@ def main():
     lb.lb_profile(lat.ctx, False)
     gpu_ms = e0.elapsed_time(e1)
     col_ms, col_n = lb.lb_kernel_times(lat.ctx, lb.LB_K_COLLIDE)
-    phi_ms, phi_n = lb.lb_kernel_times(lat.ctx, lb.LB_K_PHI)
     log("bench: timed region %.3f ms (events), %.3f s wall" % (gpu_ms, wall))
 
     nsite = n ** 3
@@ -246,7 +325,7 @@ def main():
     alg = algorithmic_bytes(model, storage)
     col_avg_ms = col_ms / max(col_n, 1)
     achieved = alg["collide"] * nsite / (col_avg_ms * 1e-3) / 1e9
-    step_bytes = alg["collide"] + alg["phi"]
+    step_bytes = alg["collide"]
 
     out = {
         "metric": METRIC,
@@ -265,7 +344,8 @@ def main():
                    "storage": storage, "seed": 0},
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_collide (fused pull-stream + collision)",
+            "kernel": ("k_binary_march (single-pass pull-stream + phi + collision)" if model == "binary"
+                       else "k_collide (fused pull-stream + collision)"),
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -279,7 +359,7 @@ def main():
             "bytes_per_site": step_bytes,
             "GB/s": round(step_bytes * nsite * args.steps / seconds / 1e9, 1),
             "frac": round(step_bytes * nsite * args.steps / seconds / 1e9 / HBM_PEAK_GBS, 4),
-            "phi_kernel_avg_ms": round(phi_ms / phi_n, 5) if phi_n else None,
+            "timing": "wall clock of the whole timed region",
         },
     }
     if not args.no_copy:

@@ -81,7 +81,7 @@ extern "C" {
 #define LB_F16      2
 
 typedef struct lb_params {
-    int32_t nx, ny, nz;   /* periodic extents, each >= 1                      */
+    int32_t nx, ny, nz;   /* periodic extents, each >= 1, nx*ny*nz < 2^29     */
     int32_t model;        /* LB_SINGLE or LB_BINARY                           */
     int32_t storage;      /* LB_F64, LB_F32 or LB_F16                          */
     int32_t reserved;     /* must be 0                                        */

@@ -125,14 +125,28 @@ __device__ __forceinline__ Site site_at(const Column& c, int v, const Geo& g) {
     return s;
 }
 
-// Global loads and stores, nontemporal when the policy says so.
+// Global loads and stores of element `off` of an array whose base is the
+// same for the whole launch, nontemporal when the policy says so.  The byte
+// offset is formed in 32 bits (every array here is below 4 GiB, checked on
+// the host), so the address is a scalar base plus a 32-bit vector offset and
+// no 64-bit address arithmetic is spent per lane.
+template <class S>
+__device__ __forceinline__ const S* at(const S* base, uint32_t off) {
+    return reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + (uint32_t)(off * (uint32_t)sizeof(S)));
+}
+template <class S>
+__device__ __forceinline__ S* at(S* base, uint32_t off) {
+    return reinterpret_cast<S*>(reinterpret_cast<char*>(base) + (uint32_t)(off * (uint32_t)sizeof(S)));
+}
 template <bool NT, class S>
-__device__ __forceinline__ S ldg(const S* p) {
+__device__ __forceinline__ S ldg(const S* base, uint32_t off) {
+    const S* p = at(base, off);
     if constexpr (NT) return __builtin_nontemporal_load(p);
     else return *p;
 }
 template <bool NT, class S>
-__device__ __forceinline__ void stg(S* p, S v) {
+__device__ __forceinline__ void stg(S* base, uint32_t off, S v) {
+    S* p = at(base, off);
     if constexpr (NT) __builtin_nontemporal_store(v, p);
     else *p = v;
 }

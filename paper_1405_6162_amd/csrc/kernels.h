@@ -86,7 +86,7 @@ template <class P, bool GATHER, class S, class T>
 __device__ __forceinline__ void load_site(const S* src, const Site& st, const Geo& geo, T (&v)[Q]) {
     static_for<0, Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        v[i] = static_cast<T>(ldg<P::nt_load>(src + i * geo.dstride + src_offset<i, GATHER>(st, geo)));
+        v[i] = static_cast<T>(ldg<P::nt_load>(src + i * geo.dstride, src_offset<i, GATHER>(st, geo)));
     });
 }
 
@@ -123,7 +123,7 @@ __global__ __launch_bounds__(P::TPB) void k_phi(const S* __restrict__ g, typenam
         T acc = T(0);
         static_for<0, Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            acc = acc + static_cast<T>(ldg<P::nt_load>(g + i * geo.dstride + src_offset<i, GATHER>(st, geo)));
+            acc = acc + static_cast<T>(ldg<P::nt_load>(g + i * geo.dstride, src_offset<i, GATHER>(st, geo)));
         });
         phi[offset_at<0, 0, 0>(st, geo)] = phi0 + acc;
     }
@@ -150,7 +150,7 @@ __device__ __forceinline__ void relax_single(const T (&f)[Q], S* fdst, uint32_t 
         const T cu = cdot<i>(ux, uy, uz);
         const T base = T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq;
         const T feq = weight<T>(i) * (drho + rho * base);
-        stg<P::nt_store>(fdst + i * geo.dstride + off, static_cast<S>(f[i] - cp.omega_f * (f[i] - feq)));
+        stg<P::nt_store>(fdst + i * geo.dstride, off, static_cast<S>(f[i] - cp.omega_f * (f[i] - feq)));
     });
 }
 
@@ -171,8 +171,8 @@ __device__ __forceinline__ void relax_binary(const T (&f)[Q], const T (&g)[Q], S
         const T base = T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq;
         const T feq = weight<T>(i) * (drho + rho * base + fe.template stress_term<i>(cp));
         const T geq = weight<T>(i) * (dphi + phic * base + fe.template mobility_term<i>(cp));
-        stg<P::nt_store>(fdst + i * geo.dstride + off, static_cast<S>(f[i] - cp.omega_f * (f[i] - feq)));
-        stg<P::nt_store>(gdst + i * geo.dstride + off, static_cast<S>(g[i] - cp.omega_g * (g[i] - geq)));
+        stg<P::nt_store>(fdst + i * geo.dstride, off, static_cast<S>(f[i] - cp.omega_f * (f[i] - feq)));
+        stg<P::nt_store>(gdst + i * geo.dstride, off, static_cast<S>(g[i] - cp.omega_g * (g[i] - geq)));
     });
 }
 
@@ -229,6 +229,159 @@ __global__ __launch_bounds__(P::TPB) void k_collide(const S* fsrc, const S* gsrc
 }
 
 // ---------------------------------------------------------------------------
+// Single-pass binary step: fused pull-stream + collision that computes phi
+// itself.  A block owns a TX x TY column tile and marches through BZ
+// consecutive z planes.  phi(s) = phi0 + sum_i e_i(s - c_i) needs the pulled
+// g of s, which the collision of s needs anyway: each lane gathers g for
+// plane z+1, sums it into the plane's phi tile in LDS and keeps the 19 values
+// in registers for the next plane's collision.  The x/y halo ring of the
+// tile (2 TX + 2 TY sites per plane) is summed by one lane each from its own
+// gather; the chunk's first and last plane need one extra plane of phi each.
+// Three phi planes (z-1, z, z+1) rotate in LDS.  Lanes outside the lattice
+// (ragged tiles) compute phi at the periodic image of their coordinates so
+// that every LDS slot holds the value its neighbours read.  The summation
+// order of phi is the same as in k_phi, so results equal the two-pass path.
+// ---------------------------------------------------------------------------
+
+// Site at wrapped coordinates (x, y in range), plane z.
+__device__ __forceinline__ Site site_wrapped(int x, int y, int z, const Geo& g) {
+    Site s;
+    s.x = x; s.y = y; s.z = z;
+    s.xm = x == 0 ? g.nx - 1 : x - 1;
+    s.xp = x + 1 >= g.nx ? 0 : x + 1;
+    s.ym = y == 0 ? g.ny - 1 : y - 1;
+    s.yp = y + 1 >= g.ny ? 0 : y + 1;
+    s.zm = z == 0 ? g.nz - 1 : z - 1;
+    s.zp = z + 1 >= g.nz ? 0 : z + 1;
+    s.active = true;
+    return s;
+}
+
+__device__ __forceinline__ int wrap_plane(int z, int nz) {
+    return z < 0 ? z + nz : (z >= nz ? z - nz : z);
+}
+
+template <class P, class S, class T>
+__device__ __forceinline__ T phi_of_gathered(const S* g, const Site& st, const Geo& geo, T phi0) {
+    T acc = T(0);
+    static_for<0, Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        acc = acc + static_cast<T>(ldg<P::nt_load>(g + i * geo.dstride, src_offset<i, true>(st, geo)));
+    });
+    return phi0 + acc;
+}
+
+// With GLDS the 19 pulled g of the next plane wait in LDS (each lane only
+// touches its own slots, so no barrier is involved) instead of registers,
+// which lowers register pressure and raises occupancy.  RING is the number of
+// phi planes kept in LDS: with 3 a second barrier per plane keeps the write of
+// plane z+2 from overtaking the reads of plane z-1; with 4 the slot written
+// next is never one still being read, so one barrier per plane suffices.
+template <class P, int BZ, class S, bool GLDS, int RING = 3>
+__global__ __launch_bounds__(P::TPB) void k_binary_march(const S* __restrict__ fsrc, const S* __restrict__ gsrc,
+                                                         S* __restrict__ fdst, S* __restrict__ gdst, Geo geo,
+                                                         CollParams<typename Compute<S>::T> cp) {
+    using T = typename Compute<S>::T;
+    constexpr int TX = P::TX, TY = P::TY, LX = TX + 2, LY = TY + 2;
+    constexpr int NHALO = 2 * TX + 2 * TY;
+    static_assert(NHALO <= P::TPB, "one halo site per lane");
+    static_assert(RING == 3 || RING == 4, "3 or 4 phi planes");
+    __shared__ T ring[RING][LY][LX];
+    __shared__ T gkeep[GLDS ? Q : 1][GLDS ? P::TPB : 1];
+
+    const int b = tile_index<P>(geo);
+    const int bx = b % geo.gx;
+    const int t = b / geo.gx;
+    const int by = t % geo.gy;
+    const int z0 = (t / geo.gy) * BZ;
+    const int z1 = min(z0 + BZ, geo.nz);
+    const int x0 = bx * TX, y0 = by * TY;
+    const int tx = (int)(threadIdx.x % TX), ty = (int)(threadIdx.x / TX);
+    const bool active = (x0 + tx < geo.nx) && (y0 + ty < geo.ny);
+    const int xw = (x0 + tx) % geo.nx, yw = (y0 + ty) % geo.ny;
+
+    // This lane's halo site (if any): LDS slot (hlx, hly) and its coordinates.
+    // Halo sites are dealt to the block's wavefronts in turn, so every
+    // wavefront carries the same extra gathers to each barrier.
+    constexpr int NWAVE = P::TPB / 64;
+    const int k = (int)(threadIdx.x % 64) * NWAVE + (int)(threadIdx.x / 64);
+    int hlx = 0, hly = 0;
+    if (k < TX) { hlx = k + 1; hly = 0; }
+    else if (k < 2 * TX) { hlx = k - TX + 1; hly = TY + 1; }
+    else if (k < 2 * TX + TY) { hlx = 0; hly = k - 2 * TX + 1; }
+    else if (k < NHALO) { hlx = TX + 1; hly = k - 2 * TX - TY + 1; }
+    int hx = (x0 - 1 + hlx) % geo.nx, hy = (y0 - 1 + hly) % geo.ny;
+    hx += hx < 0 ? geo.nx : 0;
+    hy += hy < 0 ? geo.ny : 0;
+    const bool has_halo = k < NHALO;
+
+    const int lx = tx + 1, ly = ty + 1;
+    auto slot = [&](int z) { return (z - z0 + RING) % RING; };
+
+    // Prologue: phi of planes z0-1 and z0; g of plane z0 kept for its collision.
+    T gc[Q];
+    {
+        const int zm = wrap_plane(z0 - 1, geo.nz);
+        ring[slot(z0 - 1)][ly][lx] = phi_of_gathered<P>(gsrc, site_wrapped(xw, yw, zm, geo), geo, cp.phi0);
+        if (has_halo)
+            ring[slot(z0 - 1)][hly][hlx] = phi_of_gathered<P>(gsrc, site_wrapped(hx, hy, zm, geo), geo, cp.phi0);
+        const Site s0 = site_wrapped(xw, yw, z0, geo);
+        load_site<P, true>(gsrc, s0, geo, gc);
+        T acc = T(0);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) acc = acc + gc[i];
+        ring[slot(z0)][ly][lx] = cp.phi0 + acc;
+        if constexpr (GLDS) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) gkeep[i][threadIdx.x] = gc[i];
+        }
+        if (has_halo)
+            ring[slot(z0)][hly][hlx] = phi_of_gathered<P>(gsrc, site_wrapped(hx, hy, z0, geo), geo, cp.phi0);
+    }
+
+    for (int z = z0; z < z1; ++z) {
+        const int zn = wrap_plane(z + 1, geo.nz);
+        const Site sc = site_wrapped(xw, yw, z, geo);
+        T fc[Q];
+        if (active) load_site<P, true>(fsrc, sc, geo, fc);
+        T gn[Q];
+        load_site<P, true>(gsrc, site_wrapped(xw, yw, zn, geo), geo, gn);
+        T acc = T(0);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) acc = acc + gn[i];
+        ring[slot(z + 1)][ly][lx] = cp.phi0 + acc;
+        if (has_halo)
+            ring[slot(z + 1)][hly][hlx] = phi_of_gathered<P>(gsrc, site_wrapped(hx, hy, zn, geo), geo, cp.phi0);
+        if constexpr (GLDS) {
+            // swap this plane's g out of LDS and park the next plane's
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                gc[i] = gkeep[i][threadIdx.x];
+                gkeep[i][threadIdx.x] = gn[i];
+            }
+        }
+        __syncthreads();
+        if (active) {
+            const int r = slot(z);
+            const T phic = ring[r][ly][lx];
+            const T pxm = ring[r][ly][lx - 1], pxp = ring[r][ly][lx + 1];
+            const T pym = ring[r][ly - 1][lx], pyp = ring[r][ly + 1][lx];
+            const T pzm = ring[slot(z - 1)][ly][lx], pzp = ring[slot(z + 1)][ly][lx];
+            const T gx = T(0.5) * (pxp - pxm);
+            const T gy = T(0.5) * (pyp - pym);
+            const T gz = T(0.5) * (pzp - pzm);
+            const T lap = (pxp + pxm) + (pyp + pym) + (pzp + pzm) - T(6) * phic;
+            relax_binary<P>(fc, gc, fdst, gdst, offset_at<0, 0, 0>(sc, geo), geo, cp, phic, gx, gy, gz, lap);
+        }
+        if constexpr (!GLDS) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) gc[i] = gn[i];
+        }
+        if constexpr (RING == 3) __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Stand-alone propagation (pull): dst_i(s) = src_i(s - c_i).  Also used to
 // materialise a pending buffer into caller memory of another stride.
 // ---------------------------------------------------------------------------
@@ -244,8 +397,8 @@ __global__ __launch_bounds__(P::TPB) void k_stream(const S* __restrict__ src, S*
         const uint32_t off = offset_at<0, 0, 0>(st, geo);
         static_for<0, Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            stg<P::nt_store>(dst + i * dst_stride + off,
-                             ldg<P::nt_load>(src + i * geo.dstride + src_offset<i, true>(st, geo)));
+            stg<P::nt_store>(dst + i * dst_stride, off,
+                             ldg<P::nt_load>(src + i * geo.dstride, src_offset<i, true>(st, geo)));
         });
     }
 }
@@ -279,9 +432,9 @@ __global__ __launch_bounds__(P::TPB) void k_init(const double* __restrict__ rho_
                 constexpr int i = decltype(I)::value;
                 const double cu = cdot<i>(ux, uy, uz);
                 const double base = 3.0 * cu + 4.5 * cu * cu - 1.5 * usq;
-                f[i * geo.dstride + off] =
+                *at(f + i * geo.dstride, off) =
                     static_cast<S>(weight<double>(i) * (drho + rho * base + fe.template stress_term<i>(cp)));
-                g[i * geo.dstride + off] =
+                *at(g + i * geo.dstride, off) =
                     static_cast<S>(weight<double>(i) * (dphi + p * base + fe.template mobility_term<i>(cp)));
             });
         } else {
@@ -289,7 +442,7 @@ __global__ __launch_bounds__(P::TPB) void k_init(const double* __restrict__ rho_
                 constexpr int i = decltype(I)::value;
                 const double cu = cdot<i>(ux, uy, uz);
                 const double base = 3.0 * cu + 4.5 * cu * cu - 1.5 * usq;
-                f[i * geo.dstride + off] = static_cast<S>(weight<double>(i) * (drho + rho * base));
+                *at(f + i * geo.dstride, off) = static_cast<S>(weight<double>(i) * (drho + rho * base));
             });
         }
     }
@@ -312,7 +465,7 @@ __global__ __launch_bounds__(P::TPB) void k_moments(const S* __restrict__ f, con
         double fv[Q];
         static_for<0, Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            fv[i] = static_cast<double>(f[i * geo.dstride + src_offset<i, GATHER>(st, geo)]);
+            fv[i] = static_cast<double>(*at(f + i * geo.dstride, src_offset<i, GATHER>(st, geo)));
         });
         double drho, jx, jy, jz;
         moments_of(fv, drho, jx, jy, jz);
@@ -328,7 +481,7 @@ __global__ __launch_bounds__(P::TPB) void k_moments(const S* __restrict__ f, con
                 double acc = 0.0;
                 static_for<0, Q>([&](auto I) {
                     constexpr int i = decltype(I)::value;
-                    acc = acc + static_cast<double>(g[i * geo.dstride + src_offset<i, GATHER>(st, geo)]);
+                    acc = acc + static_cast<double>(*at(g + i * geo.dstride, src_offset<i, GATHER>(st, geo)));
                 });
                 phi_out[off] = phi0 + acc;
             }
@@ -373,12 +526,12 @@ __global__ __launch_bounds__(P::TPB) void k_sums_partial(const S* __restrict__ f
         const uint32_t off = offset_at<0, 0, 0>(st, geo);
         static_for<0, Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            const double a = static_cast<double>(f[i * geo.dstride + off]);
+            const double a = static_cast<double>(*at(f + i * geo.dstride, off));
             v5[0] = v5[0] + a;
             if constexpr (cx(i) != 0) v5[1] = v5[1] + cx(i) * a;
             if constexpr (cy(i) != 0) v5[2] = v5[2] + cy(i) * a;
             if constexpr (cz(i) != 0) v5[3] = v5[3] + cz(i) * a;
-            if constexpr (MODEL == MODEL_BINARY) v5[4] = v5[4] + static_cast<double>(g[i * geo.dstride + off]);
+            if constexpr (MODEL == MODEL_BINARY) v5[4] = v5[4] + static_cast<double>(*at(g + i * geo.dstride, off));
         });
     }
     block_tree_sum<P::TPB, 5>(v5, sh);
@@ -430,8 +583,8 @@ __global__ __launch_bounds__(P::TPB) void k_adjoint(const double* __restrict__ f
         double f[Q], ls[Q];
         static_for<0, Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            f[i] = fn[i * geo.dstride + off];
-            ls[i] = lam_next[i * geo.dstride + offset_at<cx(i), cy(i), cz(i)>(st, geo)];
+            f[i] = *at(fn + i * geo.dstride, off);
+            ls[i] = *at(lam_next + i * geo.dstride, offset_at<cx(i), cy(i), cz(i)>(st, geo));
         });
         double rho, jx, jy, jz;
         moments_of(f, rho, jx, jy, jz);
@@ -461,7 +614,7 @@ __global__ __launch_bounds__(P::TPB) void k_adjoint(const double* __restrict__ f
         static_for<0, Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
             const double tc = cdot<i>(Tx, Ty, Tz);
-            lam_n[i * geo.dstride + off] = (1.0 - omega) * ls[i] + omega * (Ssum + tc - TU);
+            *at(lam_n + i * geo.dstride, off) = (1.0 - omega) * ls[i] + omega * (Ssum + tc - TU);
         });
         dw[0] = dw[0] + dom;
     }

@@ -24,6 +24,15 @@ namespace {
 // sites per lane (1, 2, 4), nontemporal loads/stores and direction padding
 // on 128^3 and 256^3 lattices; the differences were within 5%.
 using Pol = Tiling<64, 4, 1, false, true, true>;
+// Single-pass binary step (k_binary_march): planes per block (the chunk's
+// first and last plane cost one extra plane of phi each), and per storage
+// type the tile and whether the next plane's g waits in LDS (lower register
+// pressure) or in registers; chosen by a sweep on 128^3 and 256^3.
+constexpr int kMarchBZ = 16;
+template <class S> struct March;
+template <> struct March<double> { using P = Tiling<64, 4, 1, false, true, true>; static constexpr bool glds = true; };
+template <> struct March<float> { using P = Tiling<64, 4, 1, false, true, true>; static constexpr bool glds = false; };
+template <> struct March<_Float16> { using P = Tiling<64, 4, 1, false, true, true>; static constexpr bool glds = false; };
 
 constexpr size_t kAlign = 4096;
 // Extra bytes between consecutive direction arrays, so the 19 (38) streams of
@@ -51,7 +60,8 @@ int check_params(const lb_params* p) {
     if (!p) return LB_EINVAL;
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return LB_EINVAL;
     const int64_t n = (int64_t)p->nx * p->ny * p->nz;
-    if (n > (int64_t)INT32_MAX) return LB_EINVAL;
+    // Kernels form byte offsets of FP64 arrays in 32 bits: N * 8 < 2^32.
+    if (n >= ((int64_t)1 << 29)) return LB_EINVAL;
     if (p->model != LB_SINGLE && p->model != LB_BINARY) return LB_EINVAL;
     if (p->storage != LB_F64 && p->storage != LB_F32 && p->storage != LB_F16) return LB_EINVAL;
     if (p->reserved != 0) return LB_EINVAL;
@@ -118,6 +128,15 @@ struct lb_ctx {
         return g;
     }
     Geo canonical_geo() const { Geo g = geo(); g.dstride = L.nsite; return g; }
+    template <class MP>
+    Geo march_geo() const {
+        Geo g = geo();
+        g.gx = tiles(p.nx, MP::TX);
+        g.gy = tiles(p.ny, MP::TY);
+        g.gz = tiles(p.nz, kMarchBZ);
+        g.nblocks = g.gx * g.gy * g.gz;
+        return g;
+    }
     dim3 grid() const { return dim3(L.nblocks); }
     static dim3 block() { return dim3(Pol::TPB); }
     void* fbuf(int b) const { return ws + L.off_f[b]; }
@@ -191,10 +210,30 @@ int run_phi(lb_ctx* c) {
 }
 
 // One collision of the logical state; on return the state is direct.
+// Single-pass binary step from a pending buffer; on return the state is direct.
+template <class S>
+int run_binary_march(lb_ctx* c) {
+    using MP = typename March<S>::P;
+    const auto cp = coll_params<S>(c);
+    const int src = c->cur, dst = 1 - c->cur;
+    const Geo g = c->template march_geo<MP>();
+    {
+        Timed t(c, LB_K_COLLIDE);
+        k_binary_march<MP, kMarchBZ, S, March<S>::glds><<<dim3(g.nblocks), dim3(MP::TPB), 0, c->stream>>>(
+            (const S*)c->fbuf(src), (const S*)c->gbuf(src), (S*)c->fbuf(dst), (S*)c->gbuf(dst), g, cp);
+    }
+    int rc = launch_status();
+    if (rc) return rc;
+    c->cur = dst;
+    c->pending = false;
+    return LB_OK;
+}
+
 template <class S>
 int run_collide(lb_ctx* c) {
     using T = typename Compute<S>::T;
     const bool bin = c->p.model == LB_BINARY;
+    if (bin && c->pending) return run_binary_march<S>(c);
     if (bin) { int rc = run_phi<S>(c); if (rc) return rc; }
     const auto cp = coll_params<S>(c);
     const int src = c->cur, dst = c->pending ? 1 - c->cur : c->cur;

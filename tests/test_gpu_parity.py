@@ -47,7 +47,11 @@ def cpu(t):
     return t.detach().cpu().numpy() if t is not None else None
 
 
-SIZES = [(4, 4, 4), (16, 16, 16), (5, 6, 7), (67, 9, 5), (4, 8, 12), (1, 1, 3), (130, 3, 2)]
+# Several tiles and ragged tails in x (64-wide tiles) and y (4-high tiles),
+# and z extents below, at and above the single-pass kernel's chunk of 16
+# planes (37 = 16 + 16 + 5, 17 = 16 + 1).
+SIZES = [(4, 4, 4), (16, 16, 16), (5, 6, 7), (67, 9, 5), (4, 8, 12), (1, 1, 3), (130, 3, 2),
+         (5, 6, 37), (70, 5, 17)]
 
 
 @pytest.mark.parametrize("nx,ny,nz", SIZES)
