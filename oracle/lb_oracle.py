@@ -253,6 +253,30 @@ def collide_single(f, tau):
     return bgk(f, equilibrium_f(rho, u), tau)
 
 
+def trt(f, feq, tau_plus, tau_minus):
+    """Two-relaxation-time collision (Ginzburg): the parts of f - f^eq even
+    and odd under c -> -c relax with 1/tau_plus and 1/tau_minus,
+        f^{+-}_i = (f_i +- f_opp(i)) / 2,
+        f*_i = f_i - (f^+_i - f^eq+_i)/tau_plus - (f^-_i - f^eq-_i)/tau_minus.
+    tau_minus = tau_plus is BGK."""
+    fo, eo = f[OPP], feq[OPP]
+    fp, fm = 0.5 * (f + fo), 0.5 * (f - fo)
+    ep, em = 0.5 * (feq + eo), 0.5 * (feq - eo)
+    return f - (fp - ep) / tau_plus - (fm - em) / tau_minus
+
+
+def collide_single_trt(f, tau_plus, tau_minus):
+    """Single-fluid TRT collision of every site."""
+    u, rho = velocity(f)
+    return trt(f, equilibrium_f(rho, u), tau_plus, tau_minus)
+
+
+def step_single_trt(f, tau_plus, tau_minus, nsteps=1):
+    for _ in range(nsteps):
+        f = propagate(collide_single_trt(f, tau_plus, tau_minus))
+    return f
+
+
 def binary_fields(g, prm):
     """phi, grad phi, lap phi, mu and P of the current g (whole lattice first,
     because the stencils need phi at the neighbours)."""

@@ -456,3 +456,41 @@ def test_conserved_sums_of_one_hot():
     g[9, 0, 0, 0] = -0.5
     np.testing.assert_array_equal(O.conserved_sums(f, g),
                                   [3.0, 3.0 * O.C[5, 0], 3.0 * O.C[5, 1], 3.0 * O.C[5, 2], -0.5])
+
+
+# ---------------------------------------------------------------------------
+# Two-relaxation-time collision
+# ---------------------------------------------------------------------------
+
+def test_trt_with_equal_times_is_bgk():
+    f = _perturbed_single((3, 4, 5), 21)
+    np.testing.assert_allclose(O.collide_single_trt(f, 0.8, 0.8), O.collide_single(f, 0.8),
+                               rtol=0, atol=1e-15)
+
+
+def test_trt_conserves_and_fixes_equilibrium():
+    f = _perturbed_single((3, 4, 5), 22)
+    fs = O.collide_single_trt(f, 0.7, 1.3)
+    np.testing.assert_allclose(O.density(fs), O.density(f), rtol=1e-15)
+    np.testing.assert_allclose(O.momentum(fs), O.momentum(f), rtol=0, atol=1e-16)
+    rho, u = inputs.single_fluid_random(5, 4, 3, seed=23, u_max=0.05)
+    feq = O.equilibrium_f(rho, u)
+    np.testing.assert_allclose(O.collide_single_trt(feq, 0.7, 1.3), feq, rtol=0, atol=1e-15)
+    # the odd part of the non-equilibrium relaxes with tau_minus only
+    neq = fs - O.equilibrium_f(*O.velocity(f)[::-1])
+    neq0 = f - O.equilibrium_f(*O.velocity(f)[::-1])
+    odd = lambda a: 0.5 * (a - a[O.OPP])
+    np.testing.assert_allclose(odd(neq), (1 - 1 / 1.3) * odd(neq0), rtol=0, atol=1e-15)
+
+
+def test_trt_shear_wave_decay_depends_on_tau_plus():
+    """The viscosity of TRT is (tau_plus - 1/2)/3, whatever tau_minus."""
+    ny, tau_p, T, U = 32, 0.8, 200, 1e-4
+    rho, u = inputs.shear_wave(2, ny, 2, amplitude=U, noise=0.0)
+    nu, k = (tau_p - 0.5) / 3.0, 2 * np.pi / ny
+    s = np.sin(2 * np.pi * np.arange(ny) / ny)
+    for tau_m in (0.6, 1.25):
+        f = O.step_single_trt(O.init_single(rho, u), tau_p, tau_m, T)
+        ux = O.velocity(f)[0][0][0, :, 0]
+        amp = (ux * s).sum() / (s * s).sum()
+        assert abs(amp / (U * np.exp(-nu * k * k * T)) - 1.0) < 0.01
