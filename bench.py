@@ -262,6 +262,8 @@ def main():
     ap.add_argument("--workload", default="binary128_f64", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-copy", action="store_true", help="skip the copy-bandwidth probe")
+    ap.add_argument("--vvl", type=int, default=1, choices=(1, 2, 4),
+                    help="sites per lane of the fused single-fluid kernel (the paper's VVL)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -286,7 +288,7 @@ def main():
     scode = {"f64": lb.LB_F64, "f32": lb.LB_F32, "f16": lb.LB_F16}[storage]
     log("bench: %s, %d warmup + %d timed steps" % (desc, args.warmup, args.steps))
 
-    lat = lb.Lattice(n, n, n, model=mcode, storage=scode)
+    lat = lb.Lattice(n, n, n, model=mcode, storage=scode, vvl=args.vvl)
     if model == "binary":
         rho, u, phi = inputs.spinodal_quench(n, n, n, seed=0)
         lat.init_equilibrium(rho, u, phi)
@@ -341,7 +343,7 @@ def main():
         "dtype": storage,
         "data": "synthetic",
         "config": {"workload": desc, "nx": n, "ny": n, "nz": n, "fluid": model,
-                   "storage": storage, "seed": 0},
+                   "storage": storage, "seed": 0, "sites_per_lane": args.vvl},
         "roofline": {
             "bound": "hbm",
             "kernel": ("k_binary_march (single-pass pull-stream + phi + collision)" if model == "binary"

@@ -71,6 +71,12 @@ extern "C" {
 #define LB_SINGLE   0      /* one fluid, distribution f */
 #define LB_BINARY   1      /* binary mixture, distributions f and g (g carries phi) */
 
+/* Collision of f (single fluid).  LB_TRT: two-relaxation-time collision (the
+ * parts of f - f^eq even and odd under c -> -c relax with 1/tau_f and
+ * 1/tau_minus; tau_minus = tau_f is BGK). */
+#define LB_BGK      0
+#define LB_TRT      1
+
 /* Storage precision of the distributions.
  * LB_F64: f and g stored as IEEE double, FP64 arithmetic, stored directly.
  * LB_F32: stored as float deviations d_i = f_i - w_i*rho0 (g: g_i - w_i*phi0),
@@ -84,12 +90,17 @@ typedef struct lb_params {
     int32_t nx, ny, nz;   /* periodic extents, each >= 1, nx*ny*nz < 2^29     */
     int32_t model;        /* LB_SINGLE or LB_BINARY                           */
     int32_t storage;      /* LB_F64, LB_F32 or LB_F16                          */
+    int32_t vvl;          /* sites per lane along z of the fused collide and phi
+                             kernels (the virtual vector length of the targetDP
+                             execution model, Section III-C): 0 or 1 (default), 2, 4 */
+    int32_t collision;    /* LB_BGK (default) or LB_TRT (LB_SINGLE only)      */
     int32_t reserved;     /* must be 0                                        */
     double  tau_f;        /* BGK relaxation time of f, > 0.5                  */
     double  A, B, kappa;  /* free energy (binary only); kappa >= 0            */
     double  mobility;     /* Cahn-Hilliard mobility M > 0 (binary only)       */
     double  gamma;        /* mobility parameter Gamma > 0 (binary only)       */
     double  rho0, phi0;   /* deviation references for LB_F32/LB_F16; ignored for LB_F64 */
+    double  tau_minus;    /* LB_TRT: relaxation time of the odd part, > 0.5   */
 } lb_params;
 
 typedef struct lb_ctx lb_ctx;   /* opaque; created by lb_create */
@@ -145,14 +156,39 @@ int lb_set_state(lb_ctx* ctx, const void* f, const void* g);
 /* Change tau_f (> 0.5) for subsequent collisions. */
 int lb_set_tau(lb_ctx* ctx, double tau_f);
 
+/* nsteps x (collide; propagate) like lb_step, LB_SINGLE only, recording each
+ * step's post-collision field (before its propagation) in caller memory:
+ * step k (0-based) writes post[k*19*N + i*N + s] (canonical layout, storage
+ * dtype, nsteps*19*N elements in all).  The state afterwards equals that after
+ * lb_step(nsteps).  Used by the adjoint's segment recompute: post[k] holds f^{k+1}
+ * in pending (pull) form.  nsteps == 0 is a no-op. */
+int lb_step_record(lb_ctx* ctx, int32_t nsteps, void* post);
+
 /* Adjoint (reverse) of one single-fluid BGK step f^{n+1} = propagate(collide(f^n)),
- * LB_SINGLE + LB_F64 only.  f_n[19*N] is the pre-collision state of step n,
- * lam_next[19*N] = dL/df^{n+1}, both canonical FP64; lam_n[19*N] receives
- * dL/df^n (must not alias the inputs).  *domega (one device double) is
- * INCREMENTED by this step's dL/d(1/tau_f); the caller zeroes it first and
- * converts with dL/dtau = -dL/domega / tau^2.  Uses the context's tau_f. */
-int lb_adjoint_step(lb_ctx* ctx, const double* f_n, const double* lam_next,
+ * LB_SINGLE + LB_F64 only.  f (19*N, canonical FP64) is f^n itself when
+ * f_pending == 0, or the post-collision field of step n-1 (as written by
+ * lb_step_record) when f_pending != 0, in which case f^n_i(s) = f_i(s - c_i).
+ * lam_next[19*N] = dL/df^{n+1}, canonical FP64; lam_n[19*N] receives dL/df^n
+ * (must not alias the inputs).  *domega (one device double) is INCREMENTED by
+ * this step's dL/d(1/tau_f); the caller zeroes it first and converts with
+ * dL/dtau = -dL/domega / tau^2.  Uses the context's tau_f. */
+int lb_adjoint_step(lb_ctx* ctx, const double* f, int f_pending, const double* lam_next,
                     double* lam_n, double* domega);
+
+/* Masked transfer (the masked host/target copies of Section III-B, which pack
+ * the selected sites on the device so that only they cross to the host).
+ * lb_mask_index compacts mask[N] (device uint8, nonzero = site included) into
+ * index[0 .. *count) (device int32, capacity N): the included sites in
+ * increasing site order; *count is one device int64.  Deterministic.
+ * lb_get_sites gathers the current state at index[0 .. m) into f_packed and
+ * g_packed (device, storage dtype, direction-major: element (i, t) at
+ * i*m + t; g_packed only for LB_BINARY, else NULL); lb_set_sites writes them
+ * back into the state (sites outside [0, N) are skipped; listing a site twice
+ * leaves one of the two values).  m = 0 is a no-op; m < 0 or m > N is
+ * LB_EINVAL. */
+int lb_mask_index(lb_ctx* ctx, const uint8_t* mask, int32_t* index, int64_t* count);
+int lb_get_sites(lb_ctx* ctx, const int32_t* index, int64_t m, void* f_packed, void* g_packed);
+int lb_set_sites(lb_ctx* ctx, const int32_t* index, int64_t m, const void* f_packed, const void* g_packed);
 
 /* Per-kernel timing with HIP events on the context's stream.
  * lb_profile(ctx, 1) starts recording an event pair around every kernel

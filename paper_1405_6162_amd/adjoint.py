@@ -3,8 +3,11 @@ torch.autograd.Function whose backward runs the hand-written adjoint kernel
 (lb_adjoint_step) of the fused collide-stream step.
 
 Memory: the forward keeps only the states at steps 0, K, 2K, ...; the
-backward recomputes each segment of at most K states on the GPU and walks it
-in reverse, so a T-step rollout holds T/K + K states instead of T.
+backward recomputes each segment of at most K steps on the GPU, recording
+every step's post-collision field (lb_step_record), and walks it in reverse;
+the adjoint kernel pulls f^n from the recorded field, so the recompute costs
+one fused step per step and nothing else.  A T-step rollout holds T/K + K
+states instead of T.
 
 The loss is ordinary torch code on the returned f_T (for instance the mean
 of u.u over the lattice); its gradient arrives as grad_output.
@@ -59,18 +62,24 @@ class LBRollout(torch.autograd.Function):
             length = min(K, T - start)
             if length <= 0:
                 continue
-            # recompute the pre-collision states f^start .. f^{start+length-1}
-            lat.set_state(ctx.ckpts[seg])
-            states = [ctx.ckpts[seg]]
-            for _ in range(length - 1):
-                lat.step(1)
-                states.append(lat.get_state()[0])
+            # recompute the segment: the checkpoint is f^start; the recorded
+            # post-collision fields post[k] give f^{start+k+1} in pull form
+            ckpt = ctx.ckpts[seg]
+            lat.set_state(ckpt)
+            post = None
+            if length > 1:
+                post = torch.empty((length - 1,) + tuple(ckpt.shape), dtype=torch.float64, device=ckpt.device)
+                lb.lb_set_stream(lat.ctx, lb._stream())
+                lb.lb_step_record(lat.ctx, length - 1, post)
             for n in range(length - 1, -1, -1):
                 lam_prev = torch.empty_like(lam)
                 lb.lb_set_stream(lat.ctx, lb._stream())
-                lb.lb_adjoint_step(lat.ctx, states[n], lam, lam_prev, domega)
+                if n == 0:
+                    lb.lb_adjoint_step(lat.ctx, ckpt, lam, lam_prev, domega)
+                else:
+                    lb.lb_adjoint_step(lat.ctx, post[n - 1], lam, lam_prev, domega, f_pending=True)
                 lam = lam_prev
-            del states
+            del post
         grad_tau = (-domega[0] / (tau * tau)).reshape(())
         ctx.ckpts = None
         return lam, grad_tau, None, None, None

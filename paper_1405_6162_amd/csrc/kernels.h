@@ -27,6 +27,7 @@ struct CollParams {
     T omega_f, omega_g;        // 1/tau_f, 1/tau_g
     T A, B, kappa, gamma;      // free energy and mobility parameter
     T rho0, phi0;              // deviation references (0 for FP64 storage)
+    T omega_m;                 // 1/tau_minus of the two-relaxation-time collision
 };
 
 // ---------------------------------------------------------------------------
@@ -81,12 +82,15 @@ struct FreeEnergy {
     }
 };
 
-// Load the 19 populations of one site (pulled from s - c_i when GATHER).
+// Load the 19 populations of one site (pulled from s - c_i when GATHER) from
+// direction arrays `stride` elements apart (default: the lattice's own).
 template <class P, bool GATHER, class S, class T>
-__device__ __forceinline__ void load_site(const S* src, const Site& st, const Geo& geo, T (&v)[Q]) {
+__device__ __forceinline__ void load_site(const S* src, const Site& st, const Geo& geo, T (&v)[Q],
+                                          int64_t stride = -1) {
+    const int64_t ds = stride < 0 ? geo.dstride : stride;
     static_for<0, Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        v[i] = static_cast<T>(ldg<P::nt_load>(src + i * geo.dstride, src_offset<i, GATHER>(st, geo)));
+        v[i] = static_cast<T>(ldg<P::nt_load>(src + i * ds, src_offset<i, GATHER>(st, geo)));
     });
 }
 
@@ -137,21 +141,40 @@ __global__ __launch_bounds__(P::TPB) void k_phi(const S* __restrict__ g, typenam
 // their six neighbours from there.
 // ---------------------------------------------------------------------------
 
-template <class P, class S, class T>
+// BGK, or with TRT the two-relaxation-time collision: the parts of f - f^eq
+// even and odd under c -> -c relax with omega_f and omega_m.
+template <class P, bool TRT = false, class S, class T>
 __device__ __forceinline__ void relax_single(const T (&f)[Q], S* fdst, uint32_t off, const Geo& geo,
-                                             const CollParams<T>& cp) {
+                                             const CollParams<T>& cp, int64_t stride = -1) {
+    const int64_t ds = stride < 0 ? geo.dstride : stride;
     T drho, jx, jy, jz;
     moments_of(f, drho, jx, jy, jz);
     const T rho = cp.rho0 + drho;
     const T ux = jx / rho, uy = jy / rho, uz = jz / rho;
     const T usq = ux * ux + uy * uy + uz * uz;
-    static_for<0, Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        const T cu = cdot<i>(ux, uy, uz);
-        const T base = T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq;
-        const T feq = weight<T>(i) * (drho + rho * base);
-        stg<P::nt_store>(fdst + i * geo.dstride, off, static_cast<S>(f[i] - cp.omega_f * (f[i] - feq)));
-    });
+    if constexpr (TRT) {
+        T feq[Q];
+        static_for<0, Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            const T cu = cdot<i>(ux, uy, uz);
+            feq[i] = weight<T>(i) * (drho + rho * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq));
+        });
+        static_for<0, Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            constexpr int o = opp(i);
+            const T np = T(0.5) * ((f[i] + f[o]) - (feq[i] + feq[o]));
+            const T nm = T(0.5) * ((f[i] - f[o]) - (feq[i] - feq[o]));
+            stg<P::nt_store>(fdst + i * ds, off, static_cast<S>(f[i] - cp.omega_f * np - cp.omega_m * nm));
+        });
+    } else {
+        static_for<0, Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            const T cu = cdot<i>(ux, uy, uz);
+            const T base = T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq;
+            const T feq = weight<T>(i) * (drho + rho * base);
+            stg<P::nt_store>(fdst + i * ds, off, static_cast<S>(f[i] - cp.omega_f * (f[i] - feq)));
+        });
+    }
 }
 
 template <class P, class S, class T>
@@ -176,7 +199,7 @@ __device__ __forceinline__ void relax_binary(const T (&f)[Q], const T (&g)[Q], S
     });
 }
 
-template <class P, int MODEL, class S, bool GATHER>
+template <class P, int MODEL, class S, bool GATHER, bool TRT = false>
 __global__ __launch_bounds__(P::TPB) void k_collide(const S* fsrc, const S* gsrc, S* fdst, S* gdst,
                                                     const typename Compute<S>::T* __restrict__ phi, Geo geo,
                                                     CollParams<typename Compute<S>::T> cp) {
@@ -223,8 +246,26 @@ __global__ __launch_bounds__(P::TPB) void k_collide(const S* fsrc, const S* gsrc
             if (!st.active) continue;
             T f[Q];
             load_site<P, GATHER>(fsrc, st, geo, f);
-            relax_single<P>(f, fdst, offset_at<0, 0, 0>(st, geo), geo, cp);
+            relax_single<P, TRT>(f, fdst, offset_at<0, 0, 0>(st, geo), geo, cp);
         }
+    }
+}
+
+// Single-fluid collision from and into arrays of any direction stride (used
+// to record each step's post-collision field into caller memory).
+template <class P, class S, bool GATHER, bool TRT = false>
+__global__ __launch_bounds__(P::TPB) void k_collide_single_strided(const S* fsrc, int64_t src_stride, S* fdst,
+                                                                   int64_t dst_stride, Geo geo,
+                                                                   CollParams<typename Compute<S>::T> cp) {
+    using T = typename Compute<S>::T;
+    const Column col = column_of_thread<P>(geo);
+#pragma unroll
+    for (int v = 0; v < P::TZ; ++v) {
+        const Site st = site_at(col, v, geo);
+        if (!st.active) continue;
+        T f[Q];
+        load_site<P, GATHER>(fsrc, st, geo, f, src_stride);
+        relax_single<P, TRT>(f, fdst, offset_at<0, 0, 0>(st, geo), geo, cp, dst_stride);
     }
 }
 
@@ -569,7 +610,9 @@ __global__ __launch_bounds__(P::TPB) void k_sums_final(const double* __restrict_
 // lambda*_i(s) = lambda^{n+1}_i(s + c_i) is the transpose of the pull.
 // ---------------------------------------------------------------------------
 
-template <class P>
+// F_PENDING: fn holds the post-collision field of step n-1 and f^n is pulled
+// from it (f^n_i(s) = fn_i(s - c_i)); otherwise fn is f^n itself.
+template <class P, bool F_PENDING>
 __global__ __launch_bounds__(P::TPB) void k_adjoint(const double* __restrict__ fn, const double* __restrict__ lam_next,
                                                     double* __restrict__ lam_n, double* __restrict__ partial, Geo geo,
                                                     double omega) {
@@ -583,7 +626,7 @@ __global__ __launch_bounds__(P::TPB) void k_adjoint(const double* __restrict__ f
         double f[Q], ls[Q];
         static_for<0, Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            f[i] = *at(fn + i * geo.dstride, off);
+            f[i] = *at(fn + i * geo.dstride, src_offset<i, F_PENDING>(st, geo));
             ls[i] = *at(lam_next + i * geo.dstride, offset_at<cx(i), cy(i), cz(i)>(st, geo));
         });
         double rho, jx, jy, jz;
@@ -620,6 +663,112 @@ __global__ __launch_bounds__(P::TPB) void k_adjoint(const double* __restrict__ f
     }
     block_tree_sum<P::TPB, 1>(dw, sh);
     if (threadIdx.x == 0) partial[8 * (size_t)blockIdx.x] = sh[0][0];
+}
+
+// ---------------------------------------------------------------------------
+// Masked transfer (the masked copies of Section III-B): a mask over the sites
+// is compacted, in increasing site order, into a list of site indices; the
+// state at the listed sites is then gathered into or scattered from a packed
+// direction-major array [19][m].  Compaction is three deterministic passes
+// over blocks of CB consecutive sites: count, scan of the block counts, and
+// a scatter that scans each block's flags in LDS.
+// ---------------------------------------------------------------------------
+
+constexpr int CB = 256;
+
+__global__ __launch_bounds__(CB) void k_mask_count(const uint8_t* __restrict__ mask, uint32_t nsite,
+                                                   int64_t* __restrict__ counts) {
+    __shared__ int sh[CB];
+    const uint32_t s = blockIdx.x * CB + threadIdx.x;
+    sh[threadIdx.x] = (s < nsite && mask[s] != 0) ? 1 : 0;
+    __syncthreads();
+    for (int half = CB / 2; half > 0; half >>= 1) {
+        if ((int)threadIdx.x < half) sh[threadIdx.x] += sh[threadIdx.x + half];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) counts[blockIdx.x] = sh[0];
+}
+
+// Exclusive scan of counts[0..nb) in place (one block); total -> *total.
+__global__ __launch_bounds__(CB) void k_scan_counts(int64_t* counts, int nb, int64_t* total) {
+    __shared__ int64_t sh[CB];
+    const int t = threadIdx.x;
+    const int per = (nb + CB - 1) / CB;
+    const int b0 = t * per, b1 = min(b0 + per, nb);
+    int64_t sum = 0;
+    for (int b = b0; b < b1; ++b) sum += counts[b];
+    sh[t] = sum;
+    __syncthreads();
+    // inclusive Hillis-Steele scan of the per-thread sums
+    for (int d = 1; d < CB; d <<= 1) {
+        const int64_t v = t >= d ? sh[t - d] : 0;
+        __syncthreads();
+        sh[t] += v;
+        __syncthreads();
+    }
+    int64_t run = sh[t] - sum;
+    for (int b = b0; b < b1; ++b) {
+        const int64_t c = counts[b];
+        counts[b] = run;
+        run += c;
+    }
+    if (t == CB - 1) *total = sh[CB - 1];
+}
+
+__global__ __launch_bounds__(CB) void k_mask_scatter(const uint8_t* __restrict__ mask, uint32_t nsite,
+                                                     const int64_t* __restrict__ offsets,
+                                                     int32_t* __restrict__ index) {
+    __shared__ int sh[CB];
+    const uint32_t s = blockIdx.x * CB + threadIdx.x;
+    const int flag = (s < nsite && mask[s] != 0) ? 1 : 0;
+    sh[threadIdx.x] = flag;
+    __syncthreads();
+    for (int d = 1; d < CB; d <<= 1) {
+        const int v = (int)threadIdx.x >= d ? sh[threadIdx.x - d] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += v;
+        __syncthreads();
+    }
+    if (flag) index[offsets[blockIdx.x] + sh[threadIdx.x] - 1] = (int32_t)s;
+}
+
+// Site s as coordinates with periodic neighbours.
+__device__ __forceinline__ Site site_of_index(uint32_t s, const Geo& g) {
+    const int x = (int)(s % (uint32_t)g.nx);
+    const int y = (int)((s / (uint32_t)g.nx) % (uint32_t)g.ny);
+    const int z = (int)(s / g.plane);
+    return site_wrapped(x, y, z, g);
+}
+
+// packed[i*m + t] = state_i(index[t]); PENDING buffers are read by pull.
+template <class S, bool PENDING>
+__global__ __launch_bounds__(CB) void k_get_sites(const S* __restrict__ buf, const int32_t* __restrict__ index,
+                                                  int64_t m, S* __restrict__ packed, Geo geo) {
+    const int64_t t = (int64_t)blockIdx.x * CB + threadIdx.x;
+    if (t >= m) return;
+    const uint32_t s = (uint32_t)index[t];
+    if (s >= geo.nsite) return;                 // not a site: leave the slot alone
+    const Site st = site_of_index(s, geo);
+    static_for<0, Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        packed[i * m + t] = *at(buf + i * geo.dstride, src_offset<i, PENDING>(st, geo));
+    });
+}
+
+// state_i(index[t]) = packed[i*m + t]; for a PENDING buffer the value goes
+// where the next pull reads it (s - c_i).
+template <class S, bool PENDING>
+__global__ __launch_bounds__(CB) void k_set_sites(S* __restrict__ buf, const int32_t* __restrict__ index, int64_t m,
+                                                  const S* __restrict__ packed, Geo geo) {
+    const int64_t t = (int64_t)blockIdx.x * CB + threadIdx.x;
+    if (t >= m) return;
+    const uint32_t s = (uint32_t)index[t];
+    if (s >= geo.nsite) return;                 // not a site: ignored
+    const Site st = site_of_index(s, geo);
+    static_for<0, Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        *at(buf + i * geo.dstride, src_offset<i, PENDING>(st, geo)) = packed[i * m + t];
+    });
 }
 
 }  // namespace lbk

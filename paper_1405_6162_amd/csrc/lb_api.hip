@@ -24,15 +24,30 @@ namespace {
 // sites per lane (1, 2, 4), nontemporal loads/stores and direction padding
 // on 128^3 and 256^3 lattices; the differences were within 5%.
 using Pol = Tiling<64, 4, 1, false, true, true>;
-// Single-pass binary step (k_binary_march): planes per block (the chunk's
-// first and last plane cost one extra plane of phi each), and per storage
-// type the tile and whether the next plane's g waits in LDS (lower register
-// pressure) or in registers; chosen by a sweep on 128^3 and 256^3.
-constexpr int kMarchBZ = 16;
+// The same with 2 and 4 sites per lane along z (lb_params.vvl).
+using Pol2 = Tiling<64, 4, 2, false, true, true>;
+using Pol4 = Tiling<64, 4, 4, false, true, true>;
+// Single-pass binary step (k_binary_march), per storage type: the tile, the
+// planes per block (the chunk's first and last plane cost one extra plane of
+// phi each, while shorter chunks give more blocks to fill the CUs) and
+// whether the next plane's g waits in LDS (lower register pressure) or in
+// registers; chosen by sweeps on 128^3, 256^3 and 384^3.
 template <class S> struct March;
-template <> struct March<double> { using P = Tiling<64, 4, 1, false, true, true>; static constexpr bool glds = true; };
-template <> struct March<float> { using P = Tiling<64, 4, 1, false, true, true>; static constexpr bool glds = false; };
-template <> struct March<_Float16> { using P = Tiling<64, 4, 1, false, true, true>; static constexpr bool glds = false; };
+template <> struct March<double> {
+    using P = Tiling<64, 4, 1, false, true, true>;
+    static constexpr int bz = 16;
+    static constexpr bool glds = true;
+};
+template <> struct March<float> {
+    using P = Tiling<64, 4, 1, false, true, true>;
+    static constexpr int bz = 16;
+    static constexpr bool glds = false;
+};
+template <> struct March<_Float16> {
+    using P = Tiling<64, 4, 1, false, true, true>;
+    static constexpr int bz = 16;
+    static constexpr bool glds = false;
+};
 
 constexpr size_t kAlign = 4096;
 // Extra bytes between consecutive direction arrays, so the 19 (38) streams of
@@ -64,7 +79,13 @@ int check_params(const lb_params* p) {
     if (n >= ((int64_t)1 << 29)) return LB_EINVAL;
     if (p->model != LB_SINGLE && p->model != LB_BINARY) return LB_EINVAL;
     if (p->storage != LB_F64 && p->storage != LB_F32 && p->storage != LB_F16) return LB_EINVAL;
+    if (p->vvl != 0 && p->vvl != 1 && p->vvl != 2 && p->vvl != 4) return LB_EINVAL;
     if (p->reserved != 0) return LB_EINVAL;
+    if (p->collision != LB_BGK && p->collision != LB_TRT) return LB_EINVAL;
+    if (p->collision == LB_TRT) {
+        if (!std::isfinite(p->tau_minus) || !(p->tau_minus > 0.5)) return LB_EINVAL;
+        if (p->model != LB_SINGLE) return LB_ENOTSUP;
+    }
     if (!std::isfinite(p->tau_f) || !(p->tau_f > 0.5)) return LB_EINVAL;
     if (p->model == LB_BINARY) {
         if (!std::isfinite(p->A) || !std::isfinite(p->B) || !std::isfinite(p->kappa)) return LB_EINVAL;
@@ -128,12 +149,19 @@ struct lb_ctx {
         return g;
     }
     Geo canonical_geo() const { Geo g = geo(); g.dstride = L.nsite; return g; }
-    template <class MP>
+    template <class P>
+    Geo geo_for() const {
+        Geo g = geo();
+        g.gz = tiles(p.nz, P::TZ);
+        g.nblocks = g.gx * g.gy * g.gz;
+        return g;
+    }
+    template <class MP, int BZ>
     Geo march_geo() const {
         Geo g = geo();
         g.gx = tiles(p.nx, MP::TX);
         g.gy = tiles(p.ny, MP::TY);
-        g.gz = tiles(p.nz, kMarchBZ);
+        g.gz = tiles(p.nz, BZ);
         g.nblocks = g.gx * g.gy * g.gz;
         return g;
     }
@@ -193,10 +221,22 @@ CollParams<typename Compute<S>::T> coll_params(const lb_ctx* c) {
     const bool dev = c->p.storage != LB_F64;
     cp.rho0 = dev ? (T)c->p.rho0 : T(0);
     cp.phi0 = dev ? (T)c->p.phi0 : T(0);
+    cp.omega_m = c->p.collision == LB_TRT ? (T)(1.0 / c->p.tau_minus) : cp.omega_f;
     return cp;
 }
 
 // ----- typed launchers ------------------------------------------------------
+
+// Calls fn with the launch policy of the context's sites per lane.
+template <class F>
+int by_vvl(const lb_ctx* c, F&& fn) {
+    switch (c->p.vvl) {
+        case 0: case 1: return fn(Pol{});
+        case 2: return fn(Pol2{});
+        case 4: return fn(Pol4{});
+    }
+    return LB_EINVAL;
+}
 
 template <class S>
 int run_phi(lb_ctx* c) {
@@ -204,8 +244,13 @@ int run_phi(lb_ctx* c) {
     Timed t(c, LB_K_PHI);
     const S* g = (const S*)c->gbuf(c->cur);
     const T phi0 = coll_params<S>(c).phi0;
-    if (c->pending) k_phi<Pol, S, true><<<c->grid(), c->block(), 0, c->stream>>>(g, (T*)c->phi(), c->geo(), phi0);
-    else k_phi<Pol, S, false><<<c->grid(), c->block(), 0, c->stream>>>(g, (T*)c->phi(), c->geo(), phi0);
+    by_vvl(c, [&](auto pol) {
+        using P = decltype(pol);
+        const Geo geo = c->template geo_for<P>();
+        if (c->pending) k_phi<P, S, true><<<geo.nblocks, P::TPB, 0, c->stream>>>(g, (T*)c->phi(), geo, phi0);
+        else k_phi<P, S, false><<<geo.nblocks, P::TPB, 0, c->stream>>>(g, (T*)c->phi(), geo, phi0);
+        return 0;
+    });
     return launch_status();
 }
 
@@ -216,10 +261,11 @@ int run_binary_march(lb_ctx* c) {
     using MP = typename March<S>::P;
     const auto cp = coll_params<S>(c);
     const int src = c->cur, dst = 1 - c->cur;
-    const Geo g = c->template march_geo<MP>();
+    constexpr int BZ = March<S>::bz;
+    const Geo g = c->template march_geo<MP, BZ>();
     {
         Timed t(c, LB_K_COLLIDE);
-        k_binary_march<MP, kMarchBZ, S, March<S>::glds><<<dim3(g.nblocks), dim3(MP::TPB), 0, c->stream>>>(
+        k_binary_march<MP, BZ, S, March<S>::glds><<<dim3(g.nblocks), dim3(MP::TPB), 0, c->stream>>>(
             (const S*)c->fbuf(src), (const S*)c->gbuf(src), (S*)c->fbuf(dst), (S*)c->gbuf(dst), g, cp);
     }
     int rc = launch_status();
@@ -240,16 +286,24 @@ int run_collide(lb_ctx* c) {
     const S* fs = (const S*)c->fbuf(src); S* fd = (S*)c->fbuf(dst);
     const S* gs = (const S*)c->gbuf(src); S* gd = (S*)c->gbuf(dst);
     const T* phi = (const T*)c->phi();
-    const dim3 grid = c->grid(), block = c->block();
     {
         Timed t(c, LB_K_COLLIDE);
-        if (bin) {
-            if (c->pending) k_collide<Pol, MODEL_BINARY, S, true><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd, phi, c->geo(), cp);
-            else k_collide<Pol, MODEL_BINARY, S, false><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd, phi, c->geo(), cp);
-        } else {
-            if (c->pending) k_collide<Pol, MODEL_SINGLE, S, true><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd, phi, c->geo(), cp);
-            else k_collide<Pol, MODEL_SINGLE, S, false><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd, phi, c->geo(), cp);
-        }
+        by_vvl(c, [&](auto pol) {
+            using P = decltype(pol);
+            const Geo geo = c->template geo_for<P>();
+            const dim3 grid(geo.nblocks), block(P::TPB);
+            if (bin) {
+                if (c->pending) k_collide<P, MODEL_BINARY, S, true><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd, phi, geo, cp);
+                else k_collide<P, MODEL_BINARY, S, false><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd, phi, geo, cp);
+            } else if (c->p.collision == LB_TRT) {
+                if (c->pending) k_collide<P, MODEL_SINGLE, S, true, true><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd, phi, geo, cp);
+                else k_collide<P, MODEL_SINGLE, S, false, true><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd, phi, geo, cp);
+            } else {
+                if (c->pending) k_collide<P, MODEL_SINGLE, S, true><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd, phi, geo, cp);
+                else k_collide<P, MODEL_SINGLE, S, false><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd, phi, geo, cp);
+            }
+            return 0;
+        });
     }
     int rc = launch_status();
     if (rc) return rc;
@@ -365,6 +419,61 @@ int run_set_state(lb_ctx* c, const S* f, const S* g) {
         return LB_EDEVICE;
     c->pending = false;
     return LB_OK;
+}
+
+// nsteps single-fluid steps whose post-collision fields go to post[k] (canonical
+// stride N); afterwards the state is pending on a copy of the last of them.
+template <class S>
+int run_step_record(lb_ctx* c, int32_t n, S* post) {
+    const int64_t N = c->L.nsite;
+    const auto cp = coll_params<S>(c);
+    const dim3 grid = c->grid(), block = c->block();
+    for (int32_t k = 0; k < n; ++k) {
+        S* dst = post + (size_t)k * Q * N;
+        {
+            Timed t(c, LB_K_COLLIDE);
+            if (k == 0) {
+                const S* src = (const S*)c->fbuf(c->cur);
+                if (c->pending)
+                    k_collide_single_strided<Pol, S, true><<<grid, block, 0, c->stream>>>(src, c->L.dstride, dst, N,
+                                                                                         c->geo(), cp);
+                else
+                    k_collide_single_strided<Pol, S, false><<<grid, block, 0, c->stream>>>(src, c->L.dstride, dst, N,
+                                                                                          c->geo(), cp);
+            } else {
+                const S* src = post + (size_t)(k - 1) * Q * N;
+                k_collide_single_strided<Pol, S, true><<<grid, block, 0, c->stream>>>(src, N, dst, N, c->geo(), cp);
+            }
+        }
+        int rc = launch_status();
+        if (rc) return rc;
+    }
+    Timed t(c, LB_K_OTHER);
+    const size_t w = (size_t)N * sizeof(S), sp = (size_t)c->L.dstride * sizeof(S);
+    if (hipMemcpy2DAsync(c->fbuf(c->cur), sp, post + (size_t)(n - 1) * Q * N, w, w, Q, hipMemcpyDeviceToDevice,
+                         c->stream) != hipSuccess)
+        return LB_EDEVICE;
+    c->pending = true;
+    return LB_OK;
+}
+
+template <class S>
+int run_sites(lb_ctx* c, const int32_t* index, int64_t m, S* f, S* g, bool set) {
+    Timed t(c, LB_K_OTHER);
+    const int nb = (int)((m + CB - 1) / CB);
+    const Geo geo = c->geo();
+    S* bufs[2] = {(S*)c->fbuf(c->cur), (S*)c->gbuf(c->cur)};
+    S* packs[2] = {f, g};
+    for (int d = 0; d < (c->p.model == LB_BINARY ? 2 : 1); ++d) {
+        if (set) {
+            if (c->pending) k_set_sites<S, true><<<nb, CB, 0, c->stream>>>(bufs[d], index, m, packs[d], geo);
+            else k_set_sites<S, false><<<nb, CB, 0, c->stream>>>(bufs[d], index, m, packs[d], geo);
+        } else {
+            if (c->pending) k_get_sites<S, true><<<nb, CB, 0, c->stream>>>(bufs[d], index, m, packs[d], geo);
+            else k_get_sites<S, false><<<nb, CB, 0, c->stream>>>(bufs[d], index, m, packs[d], geo);
+        }
+    }
+    return launch_status();
 }
 
 // Dispatch on the storage type.
@@ -495,18 +604,68 @@ int lb_set_tau(lb_ctx* c, double tau_f) {
     return LB_OK;
 }
 
-int lb_adjoint_step(lb_ctx* c, const double* f_n, const double* lam_next, double* lam_n, double* domega) {
-    if (!c || !f_n || !lam_next || !lam_n || !domega) return LB_EINVAL;
-    if (c->p.model != LB_SINGLE || c->p.storage != LB_F64) return LB_ENOTSUP;
-    if (lam_n == lam_next || lam_n == f_n) return LB_EINVAL;
+int lb_step_record(lb_ctx* c, int32_t nsteps, void* post) {
+    if (!c || nsteps < 0) return LB_EINVAL;
+    if (nsteps == 0) return LB_OK;
+    if (!post) return LB_EINVAL;
+    if (c->p.model != LB_SINGLE || c->p.collision != LB_BGK) return LB_ENOTSUP;
+    return by_storage(c, [&](auto tag) {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        return run_step_record<S>(c, nsteps, (S*)post);
+    });
+}
+
+int lb_adjoint_step(lb_ctx* c, const double* f, int f_pending, const double* lam_next, double* lam_n,
+                    double* domega) {
+    if (!c || !f || !lam_next || !lam_n || !domega) return LB_EINVAL;
+    if (c->p.model != LB_SINGLE || c->p.storage != LB_F64 || c->p.collision != LB_BGK) return LB_ENOTSUP;
+    if (lam_n == lam_next || lam_n == f) return LB_EINVAL;
     c->launched = true;
     {
         Timed t(c, LB_K_ADJOINT);
-        k_adjoint<Pol><<<c->grid(), c->block(), 0, c->stream>>>(f_n, lam_next, lam_n, c->partial(), c->canonical_geo(),
-                                                           1.0 / c->p.tau_f);
+        if (f_pending)
+            k_adjoint<Pol, true><<<c->grid(), c->block(), 0, c->stream>>>(f, lam_next, lam_n, c->partial(),
+                                                                        c->canonical_geo(), 1.0 / c->p.tau_f);
+        else
+            k_adjoint<Pol, false><<<c->grid(), c->block(), 0, c->stream>>>(f, lam_next, lam_n, c->partial(),
+                                                                         c->canonical_geo(), 1.0 / c->p.tau_f);
     }
     k_sums_final<Pol, 1><<<1, c->block(), 0, c->stream>>>(c->partial(), c->L.nblocks, domega, 0.0, 0.0, 1);
     return launch_status();
+}
+
+int lb_mask_index(lb_ctx* c, const uint8_t* mask, int32_t* index, int64_t* count) {
+    if (!c || !mask || !index || !count) return LB_EINVAL;
+    c->launched = true;
+    const uint32_t n = (uint32_t)c->L.nsite;
+    const int nb = (int)((n + CB - 1) / CB);
+    int64_t* counts = reinterpret_cast<int64_t*>(c->partial());   // nb <= tiles of the launch grid
+    Timed t(c, LB_K_OTHER);
+    k_mask_count<<<nb, CB, 0, c->stream>>>(mask, n, counts);
+    k_scan_counts<<<1, CB, 0, c->stream>>>(counts, nb, count);
+    k_mask_scatter<<<nb, CB, 0, c->stream>>>(mask, n, counts, index);
+    return launch_status();
+}
+
+
+int lb_get_sites(lb_ctx* c, const int32_t* index, int64_t m, void* f, void* g) {
+    if (!c || m < 0 || m > c->L.nsite) return LB_EINVAL;
+    if (m == 0) return LB_OK;
+    if (!index || !f || ((c->p.model == LB_BINARY) != (g != nullptr))) return LB_EINVAL;
+    return by_storage(c, [&](auto tag) {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        return run_sites<S>(c, index, m, (S*)f, (S*)g, false);
+    });
+}
+
+int lb_set_sites(lb_ctx* c, const int32_t* index, int64_t m, const void* f, const void* g) {
+    if (!c || m < 0 || m > c->L.nsite) return LB_EINVAL;
+    if (m == 0) return LB_OK;
+    if (!index || !f || ((c->p.model == LB_BINARY) != (g != nullptr))) return LB_EINVAL;
+    return by_storage(c, [&](auto tag) {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        return run_sites<S>(c, index, m, (S*)f, (S*)g, true);
+    });
 }
 
 int lb_profile(lb_ctx* c, int enable) {

@@ -16,6 +16,7 @@ import torch
 LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_ENOTSUP = 0, -1, -2, -3, -4
 LB_SINGLE, LB_BINARY = 0, 1
 LB_F64, LB_F32, LB_F16 = 0, 1, 2
+LB_BGK, LB_TRT = 0, 1
 LB_K_COLLIDE, LB_K_PHI, LB_K_STREAM, LB_K_ADJOINT, LB_K_OTHER = 0, 1, 2, 3, 4
 Q = 19
 
@@ -34,17 +35,22 @@ class LBError(RuntimeError):
 class lb_params(ctypes.Structure):
     _fields_ = [
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
-        ("model", ctypes.c_int32), ("storage", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("model", ctypes.c_int32), ("storage", ctypes.c_int32), ("vvl", ctypes.c_int32),
+        ("collision", ctypes.c_int32), ("reserved", ctypes.c_int32),
         ("tau_f", ctypes.c_double),
         ("A", ctypes.c_double), ("B", ctypes.c_double), ("kappa", ctypes.c_double),
         ("mobility", ctypes.c_double), ("gamma", ctypes.c_double),
         ("rho0", ctypes.c_double), ("phi0", ctypes.c_double),
+        ("tau_minus", ctypes.c_double),
     ]
 
 
 def make_params(nx, ny, nz, model=LB_SINGLE, storage=LB_F64, tau_f=1.0, A=-0.0625, B=0.0625,
-                kappa=0.04, mobility=0.45, gamma=1.0, rho0=1.0, phi0=0.0):
-    return lb_params(nx, ny, nz, model, storage, 0, tau_f, A, B, kappa, mobility, gamma, rho0, phi0)
+                kappa=0.04, mobility=0.45, gamma=1.0, rho0=1.0, phi0=0.0, vvl=1, collision=LB_BGK,
+                tau_minus=None):
+    tm = tau_f if tau_minus is None else tau_minus
+    return lb_params(nx, ny, nz, model, storage, vvl, collision, 0, tau_f, A, B, kappa, mobility, gamma,
+                     rho0, phi0, tm)
 
 
 _lib = None
@@ -62,7 +68,11 @@ _SIGNATURES = {
     "lb_get_state": (_int, [_vp, _vp, _vp]),
     "lb_set_state": (_int, [_vp, _vp, _vp]),
     "lb_set_tau": (_int, [_vp, ctypes.c_double]),
-    "lb_adjoint_step": (_int, [_vp, _vp, _vp, _vp, _vp]),
+    "lb_step_record": (_int, [_vp, _i32, _vp]),
+    "lb_adjoint_step": (_int, [_vp, _vp, _int, _vp, _vp, _vp]),
+    "lb_mask_index": (_int, [_vp, _vp, _vp, _vp]),
+    "lb_get_sites": (_int, [_vp, _vp, ctypes.c_int64, _vp, _vp]),
+    "lb_set_sites": (_int, [_vp, _vp, ctypes.c_int64, _vp, _vp]),
     "lb_profile": (_int, [_vp, _int]),
     "lb_kernel_times": (_int, [_vp, _int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     "lb_destroy": (_int, [_vp]),
@@ -162,8 +172,25 @@ def lb_set_tau(ctx, tau_f):
     _check("lb_set_tau", _lib.lb_set_tau(ctx, float(tau_f)))
 
 
-def lb_adjoint_step(ctx, f_n, lam_next, lam_n, domega):
-    _check("lb_adjoint_step", _lib.lb_adjoint_step(ctx, _ptr(f_n), _ptr(lam_next), _ptr(lam_n), _ptr(domega)))
+def lb_step_record(ctx, nsteps, post):
+    _check("lb_step_record", _lib.lb_step_record(ctx, int(nsteps), _ptr(post)))
+
+
+def lb_adjoint_step(ctx, f, lam_next, lam_n, domega, f_pending=False):
+    _check("lb_adjoint_step", _lib.lb_adjoint_step(ctx, _ptr(f), 1 if f_pending else 0, _ptr(lam_next),
+                                                   _ptr(lam_n), _ptr(domega)))
+
+
+def lb_mask_index(ctx, mask, index, count):
+    _check("lb_mask_index", _lib.lb_mask_index(ctx, _ptr(mask), _ptr(index), _ptr(count)))
+
+
+def lb_get_sites(ctx, index, m, f_packed, g_packed=None):
+    _check("lb_get_sites", _lib.lb_get_sites(ctx, _ptr(index), int(m), _ptr(f_packed), _ptr(g_packed)))
+
+
+def lb_set_sites(ctx, index, m, f_packed, g_packed=None):
+    _check("lb_set_sites", _lib.lb_set_sites(ctx, _ptr(index), int(m), _ptr(f_packed), _ptr(g_packed)))
 
 
 def lb_profile(ctx, enable):
@@ -268,6 +295,59 @@ class Lattice:
         g = self._dev(g, Q * self.nsite, dt, "g") if g is not None else None
         lb_set_state(self.ctx, f, g)
         self._keep = (f, g)
+
+    def mask_index(self, mask):
+        """Included sites of a boolean (nz, ny, nx) mask, in site order, as a
+        device int32 tensor (the count is read back to size it)."""
+        lb_set_stream(self.ctx, _stream())
+        m = torch.as_tensor(mask, device=self.device).to(torch.uint8).contiguous()
+        if m.numel() != self.nsite:
+            raise ValueError("mask has %d elements, expected %d" % (m.numel(), self.nsite))
+        index = torch.empty(self.nsite, dtype=torch.int32, device=self.device)
+        count = torch.empty(1, dtype=torch.int64, device=self.device)
+        lb_mask_index(self.ctx, m, index, count)
+        return index[: int(count.item())]
+
+    def get_sites(self, index):
+        """State at the listed sites, packed (19, m) (and g for the binary model)."""
+        lb_set_stream(self.ctx, _stream())
+        index = index.to(torch.int32).contiguous()
+        m = index.numel()
+        dt = STORAGE_DTYPE[self.storage]
+        f = torch.empty((Q, m), dtype=dt, device=self.device)
+        g = torch.empty_like(f) if self.model == LB_BINARY else None
+        lb_get_sites(self.ctx, index, m, f, g)
+        return f, g
+
+    def set_sites(self, index, f, g=None):
+        lb_set_stream(self.ctx, _stream())
+        index = index.to(torch.int32).contiguous()
+        m = index.numel()
+        dt = STORAGE_DTYPE[self.storage]
+        if (g is None) != (self.model != LB_BINARY):
+            raise ValueError("g is required for the binary model and only for it")
+        f = self._dev(f, Q * m, dt, "f")
+        g = self._dev(g, Q * m, dt, "g") if g is not None else None
+        lb_set_sites(self.ctx, index, m, f, g)
+        self._keep = (index, f, g)
+
+    def copy_from_masked(self, mask, f_host, g_host=None):
+        """Update the host arrays (19, nz, ny, nx) at the masked sites only,
+        moving only those sites' values across (packed on the device)."""
+        index = self.mask_index(mask)
+        f, g = self.get_sites(index)
+        idx = index.cpu().numpy()
+        f_host.reshape(Q, -1)[:, idx] = f.cpu().numpy()
+        if g_host is not None:
+            g_host.reshape(Q, -1)[:, idx] = g.cpu().numpy()
+
+    def copy_to_masked(self, mask, f_host, g_host=None):
+        """Write the host arrays' values at the masked sites into the state."""
+        index = self.mask_index(mask)
+        idx = index.cpu().numpy()
+        f = f_host.reshape(Q, -1)[:, idx]
+        g = g_host.reshape(Q, -1)[:, idx] if g_host is not None else None
+        self.set_sites(index, f, g)
 
     def set_tau(self, tau_f):
         lb_set_tau(self.ctx, tau_f)

@@ -40,7 +40,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 def test_constants_match_header():
     text = open(HEADER).read()
-    for name in ("LB_OK", "LB_EINVAL", "LB_ENOMEM", "LB_EDEVICE", "LB_ENOTSUP", "LB_SINGLE",
+    for name in ("LB_OK", "LB_EINVAL", "LB_ENOMEM", "LB_EDEVICE", "LB_ENOTSUP", "LB_SINGLE", "LB_BGK", "LB_TRT",
                  "LB_BINARY", "LB_F64", "LB_F32", "LB_F16", "LB_K_COLLIDE", "LB_K_PHI",
                  "LB_K_STREAM", "LB_K_ADJOINT", "LB_K_OTHER"):
         m = re.search(r"#define\s+%s\s+\(?(-?\d+)\)?" % name, text)
@@ -102,10 +102,21 @@ def test_bad_parameters_rejected(lib, change):
     assert not ctx.value
 
 
-def test_reserved_field_must_be_zero(lib):
+def test_collision_values(lib):
+    assert _ws(lb.make_params(4, 4, 4, collision=lb.LB_TRT, tau_minus=1.2))[0] == lb.LB_OK
+    assert _ws(lb.make_params(4, 4, 4, collision=lb.LB_TRT, tau_minus=0.5))[0] == lb.LB_EINVAL
+    assert _ws(lb.make_params(4, 4, 4, collision=2))[0] == lb.LB_EINVAL
+    assert _ws(lb.make_params(4, 4, 4, model=lb.LB_BINARY, collision=lb.LB_TRT, tau_minus=1.2))[0] \
+        == lb.LB_ENOTSUP
     p = lb.make_params(4, 4, 4)
-    p.reserved = 1
+    p.reserved = 3
     assert _ws(p)[0] == lb.LB_EINVAL
+
+
+def test_vvl_values(lib):
+    for v, ok in ((0, True), (1, True), (2, True), (4, True), (3, False), (8, False), (-1, False)):
+        p = lb.make_params(4, 4, 4, vvl=v)
+        assert (_ws(p)[0] == lb.LB_OK) == ok, v
 
 
 def test_create_checks_workspace_without_device_work(lib):
@@ -127,7 +138,10 @@ def test_create_checks_workspace_without_device_work(lib):
         assert lib.lb_get_state(ctx, fake, None) == lb.LB_EINVAL               # binary needs g
         assert lib.lb_set_state(ctx, fake, None) == lb.LB_EINVAL
         assert lib.lb_conserved_sums(ctx, None) == lb.LB_EINVAL
-        assert lib.lb_adjoint_step(ctx, fake, fake, ctypes.c_void_p((1 << 21)), fake) == lb.LB_ENOTSUP
+        assert lib.lb_adjoint_step(ctx, fake, 0, fake, ctypes.c_void_p((1 << 21)), fake) == lb.LB_ENOTSUP
+        assert lib.lb_step_record(ctx, 2, fake) == lb.LB_ENOTSUP                 # single fluid only
+        assert lib.lb_step_record(ctx, -1, fake) == lb.LB_EINVAL
+        assert lib.lb_step_record(ctx, 0, None) == lb.LB_OK                      # no-op
         ms, n = ctypes.c_double(), ctypes.c_int64()
         assert lib.lb_kernel_times(ctx, 7, ctypes.byref(ms), ctypes.byref(n)) == lb.LB_EINVAL
         assert lib.lb_kernel_times(ctx, lb.LB_K_COLLIDE, ctypes.byref(ms), ctypes.byref(n)) == lb.LB_OK
@@ -146,7 +160,8 @@ def test_single_model_rejects_phi(lib):
         assert lib.lb_moments(ctx, None, None, fake) == lb.LB_EINVAL
         assert lib.lb_moments(ctx, None, None, None) == lb.LB_OK    # nothing requested
         assert lib.lb_get_state(ctx, fake, fake) == lb.LB_EINVAL
-        assert lib.lb_adjoint_step(ctx, fake, fake, fake, fake) == lb.LB_EINVAL   # lam_n aliases
+        assert lib.lb_adjoint_step(ctx, fake, 1, fake, fake, fake) == lb.LB_EINVAL   # lam_n aliases
+        assert lib.lb_step_record(ctx, 3, None) == lb.LB_EINVAL
     finally:
         assert lib.lb_destroy(ctx) == lb.LB_OK
 

@@ -42,6 +42,51 @@ def test_adjoint_step_kernel(lbgpu, nx, ny, nz):
     assert abs(dw.item() - 0.25 - want_dw) <= 1e-12 * max(abs(want_dw), np.abs(want).max())
 
 
+def test_adjoint_step_from_pending_field(lbgpu):
+    """f_pending: the kernel pulls f^n from the previous step's post-collision
+    field; same result as giving f^n itself."""
+    nx, ny, nz, tau = 9, 6, 5, 0.85
+    f = _state(nx, ny, nz, seed=7)
+    post = O.collide_single(f, tau)                  # f^{n} = propagate(post)
+    fn = O.propagate(post)
+    rng = np.random.default_rng(8)
+    lam_next = rng.standard_normal(f.shape)
+    want, want_dw = O.adjoint_step_single(fn, lam_next, tau)
+    lat = lbgpu.Lattice(nx, ny, nz, tau_f=tau)
+    dev = lambda a: torch.as_tensor(a, device="cuda").contiguous()
+    out = torch.empty_like(dev(lam_next))
+    dw = torch.zeros(1, dtype=torch.float64, device="cuda")
+    lbgpu.lb_set_stream(lat.ctx, lbgpu._stream())
+    lbgpu.lb_adjoint_step(lat.ctx, dev(post), dev(lam_next), out, dw, f_pending=True)
+    assert relerr(out.cpu().numpy(), want) < 1e-12
+    assert abs(dw.item() - want_dw) <= 1e-12 * max(abs(want_dw), np.abs(want).max())
+
+
+@pytest.mark.parametrize("pending_start", [False, True])
+def test_step_record(lbgpu, pending_start):
+    """lb_step_record leaves the state of lb_step and records, per step, the
+    post-collision field whose propagation is the next state."""
+    nx, ny, nz, tau, n = 7, 5, 6, 0.9, 4
+    f0 = _state(nx, ny, nz, seed=9)
+    lat = lbgpu.Lattice(nx, ny, nz, tau_f=tau)
+    lat.set_state(f0)
+    ref = f0
+    if pending_start:
+        lat.step(1)
+        ref = O.step_single(ref, tau, 1)
+    post = torch.empty((n, 19, nz, ny, nx), dtype=torch.float64, device="cuda")
+    lbgpu.lb_set_stream(lat.ctx, lbgpu._stream())
+    lbgpu.lb_step_record(lat.ctx, n, post)
+    p = post.cpu().numpy()
+    for k in range(n):
+        c = O.collide_single(ref, tau)
+        assert relerr(p[k], c) < 1e-12
+        ref = O.propagate(c)
+    assert relerr(lat.get_state()[0].cpu().numpy(), ref) < 1e-12
+    lat.step(2)
+    assert relerr(lat.get_state()[0].cpu().numpy(), O.step_single(ref, tau, 2)) < 1e-12
+
+
 @pytest.mark.parametrize("nsteps,every", [(7, 3), (7, 7), (7, 1), (6, 2), (0, 4)])
 def test_rollout_gradient_vs_oracle(lbgpu, nsteps, every):
     from paper_1405_6162_amd.adjoint import rollout, velocity_loss

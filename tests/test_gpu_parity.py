@@ -48,8 +48,8 @@ def cpu(t):
 
 
 # Several tiles and ragged tails in x (64-wide tiles) and y (4-high tiles),
-# and z extents below, at and above the single-pass kernel's chunk of 16
-# planes (37 = 16 + 16 + 5, 17 = 16 + 1).
+# and z extents below, at and above the single-pass kernel's chunks of 8
+# (FP64) and 16 planes (37 = 16 + 16 + 5 = 4 x 8 + 5, 17 = 16 + 1 = 2 x 8 + 1).
 SIZES = [(4, 4, 4), (16, 16, 16), (5, 6, 7), (67, 9, 5), (4, 8, 12), (1, 1, 3), (130, 3, 2),
          (5, 6, 37), (70, 5, 17)]
 
@@ -243,3 +243,45 @@ def test_binary_128_first_steps_vs_oracle_run(lbgpu):
     f, g = (cpu(a) for a in lat.get_state())
     ef, eg = O.step_binary(*O.init_binary(rho, u, phi, prm), prm, 3)
     assert relerr(f, ef) < TOL64 and relerr(g, eg) < TOL64
+
+
+@pytest.mark.parametrize("vvl", [2, 4])
+@pytest.mark.parametrize("nx,ny,nz", [(67, 9, 5), (5, 6, 37), (16, 16, 16)])
+def test_sites_per_lane(lbgpu, vvl, nx, ny, nz):
+    """2 and 4 sites per lane along z (ragged in z for nz = 5, 37): the
+    single-fluid step and the binary collide-only path (phi kernel + LDS
+    stencil collision) against the oracle."""
+    print("case vvl", vvl, nx, ny, nz, flush=True)
+    rho, u = single_case(nx, ny, nz, seed=11)
+    lat = lbgpu.Lattice(nx, ny, nz, tau_f=0.8, vvl=vvl)
+    lat.init_equilibrium(rho, u)
+    lat.step(3)
+    assert relerr(cpu(lat.get_state()[0]), O.step_single(O.init_single(rho, u), 0.8, 3)) < TOL64
+    prm = O.Params()
+    rho, u, phi = binary_case(nx, ny, nz, seed=12, phi_max=0.3, u_max=0.01)
+    lat = lbgpu.Lattice(nx, ny, nz, model=lbgpu.LB_BINARY, vvl=vvl, **params_of(prm))
+    lat.init_equilibrium(rho, u, phi)
+    lat.collide()
+    rf, rg = O.collide_binary(*O.init_binary(rho, u, phi, prm), prm)
+    f, g = (cpu(a) for a in lat.get_state())
+    assert relerr(f, rf) < TOL64 and relerr(g, rg) < TOL64
+
+
+@pytest.mark.parametrize("nx,ny,nz", [(4, 4, 4), (67, 9, 5), (5, 6, 37)])
+@pytest.mark.parametrize("vvl", [1, 2])
+def test_trt_single_fluid(lbgpu, nx, ny, nz, vvl):
+    """Two-relaxation-time collision against the oracle: fused steps and the
+    stand-alone collide-only path."""
+    print("case trt", nx, ny, nz, vvl, flush=True)
+    tp, tm = 0.8, 1.3
+    rho, u = single_case(nx, ny, nz, seed=13)
+    lat = lbgpu.Lattice(nx, ny, nz, tau_f=tp, collision=lbgpu.LB_TRT, tau_minus=tm, vvl=vvl)
+    lat.init_equilibrium(rho, u)
+    ref = O.init_single(rho, u)
+    lat.collide()
+    ref = O.collide_single_trt(ref, tp, tm)
+    assert relerr(cpu(lat.get_state()[0]), ref) < TOL64
+    lat.propagate()
+    lat.step(4)
+    ref = O.step_single_trt(O.propagate(ref), tp, tm, 4)
+    assert relerr(cpu(lat.get_state()[0]), ref) < TOL64
