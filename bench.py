@@ -42,6 +42,8 @@ WORKLOADS = {
                                                   "deviation storage against FP64"),
     "precision384_f16": ("precision", "f16", 384, "D3Q19 binary fluid 384^3 spinodal quench, 1000 steps: FP16 "
                                                   "deviation storage against FP32, and a 96^3 run against FP64"),
+    "precision256_single_f32": ("precision_single", "f32", 256, "D3Q19 single-fluid BGK 256^3, rho = 1 + "
+                                "0.01 N(0,1), u ~ U(-0.01, 0.01), 500 steps: FP32 deviation storage against FP64"),
 }
 
 ES = {"f64": 8, "f32": 4, "f16": 2}
@@ -186,7 +188,34 @@ def _moment_errors(lb, ref, other):
     r0, u0, p0 = ref.moments()
     r1, u1, p1 = other.moments()
     rel = lambda a, b: float((a - b).abs().max() / b.abs().max())
-    return {"rho": rel(r1, r0), "u": rel(u1, u0), "phi": rel(p1, p0)}, p0, p1
+    err = {"rho": rel(r1, r0), "u": rel(u1, u0)}
+    if p0 is not None:
+        err["phi"] = rel(p1, p0)
+    return err, p0, p1
+
+
+def _error_history(lb, make, checkpoints):
+    """Step three lattices in lock-step and record, at each checkpoint, the
+    per-moment errors against the FP64 one ("ref") of the reduced-precision
+    one ("low") and of an FP64 run whose initial fields were rounded to FP32
+    once ("perturbed": how far a single FP32 rounding of the initial state
+    moves the trajectory, the flow's own sensitivity)."""
+    lats = {k: make(k) for k in ("ref", "low", "perturbed")}
+    hist, done = [], 0
+    for c in checkpoints:
+        for lat in lats.values():
+            lat.step(c - done)
+        done = c
+        e_low, _, _ = _moment_errors(lb, lats["ref"], lats["low"])
+        e_pert, _, _ = _moment_errors(lb, lats["ref"], lats["perturbed"])
+        hist.append({"step": c, "low": e_low, "perturbed": e_pert})
+    for lat in lats.values():
+        lat.close()
+    return hist
+
+
+def _rounded(*a):
+    return tuple(x.astype("float32").astype("float64") for x in a)
 
 
 def coarsening_length(phi):
@@ -239,6 +268,16 @@ def bench_precision(args, storage, n, desc):
            "coarsening_length": {storage: coarsening_length(p_low), ref_storage: coarsening_length(p_ref)}}
     ref.close()
     low.close()
+    if storage == "f32":
+        def make(kind):
+            rho, u, phi = inputs.spinodal_quench(n, n, n, seed=0)
+            if kind == "perturbed":
+                rho, u, phi = _rounded(rho, u, phi)
+            lat = lb.Lattice(n, n, n, model=lb.LB_BINARY, storage=code["f32" if kind == "low" else "f64"],
+                             rho0=1.0, phi0=float(phi.mean()))
+            lat.init_equilibrium(rho, u, phi)
+            return lat
+        out["error_history"] = _error_history(lb, make, [1, 10, 100, steps])
     if storage == "f16":
         # 96^3 run of all three storages, errors against the FP64 one
         sub = {}
@@ -251,6 +290,51 @@ def bench_precision(args, storage, n, desc):
         sub["f64"] = {"drift": d64, "coarsening_length": coarsening_length(p64)}
         r64.close()
         out["sub_run_96"] = sub
+    print(json.dumps(out), flush=True)
+
+
+def bench_precision_single(args, n, desc, steps=500):
+    """Single fluid from the same random state in FP64 and FP32 storage;
+    per-moment errors of FP32 against FP64 after `steps` steps."""
+    import torch
+    from paper_1405_6162_amd import inputs, lb
+    log("bench: %s" % desc)
+    rho, u = inputs.single_fluid_random(n, n, n, seed=0)
+    res = {}
+    lats = {}
+    for sto, code in (("f64", lb.LB_F64), ("f32", lb.LB_F32)):
+        lat = lb.Lattice(n, n, n, storage=code, rho0=1.0)
+        lat.init_equilibrium(rho, u)
+        s0 = lat.conserved_sums().cpu()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        s1 = lat.conserved_sums().cpu()
+        res[sto] = {"MLUPS": n ** 3 * steps / dt / 1e6, "mass_drift": float(abs(s1[0] - s0[0]) / abs(s0[0]))}
+        lats[sto] = lat
+    r0, u0, _ = lats["f64"].moments()
+    r1, u1, _ = lats["f32"].moments()
+    rel = lambda a, b: float((a - b).abs().max() / b.abs().max())
+    out = {"metric": METRIC, "value": round(res["f32"]["MLUPS"], 2), "unit": "MLUPS", "n_gpus": 1,
+           "steps": steps, "warmup": 0, "ms_per_step": round(n ** 3 / res["f32"]["MLUPS"] / 1e3, 5),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic", "config": {"workload": desc, "nx": n, "ny": n, "nz": n, "seed": 0},
+           "reference": {"storage": "f64", "MLUPS": round(res["f64"]["MLUPS"], 2),
+                         "speedup": round(res["f32"]["MLUPS"] / res["f64"]["MLUPS"], 3)},
+           "errors_vs_reference": {"rho": rel(r1, r0), "u": rel(u1, u0)},
+           "drift": {"f32_mass_rel": res["f32"]["mass_drift"], "f64_mass_rel": res["f64"]["mass_drift"]}}
+    out["final_max_abs_u"] = {"f64": float(u0.abs().max())}
+    for lat in lats.values():
+        lat.close()
+
+    def make(kind):
+        r, v = (rho, u) if kind != "perturbed" else _rounded(rho, u)
+        lat = lb.Lattice(n, n, n, storage=lb.LB_F32 if kind == "low" else lb.LB_F64, rho0=1.0)
+        lat.init_equilibrium(r, v)
+        return lat
+    out["error_history"] = _error_history(lb, make, [1, 10, 100, steps])
     print(json.dumps(out), flush=True)
 
 
@@ -284,6 +368,8 @@ def main():
         return bench_adjoint(args, n, desc)
     if model == "precision":
         return bench_precision(args, storage, n, desc)
+    if model == "precision_single":
+        return bench_precision_single(args, n, desc)
     mcode = lb.LB_BINARY if model == "binary" else lb.LB_SINGLE
     scode = {"f64": lb.LB_F64, "f32": lb.LB_F32, "f16": lb.LB_F16}[storage]
     log("bench: %s, %d warmup + %d timed steps" % (desc, args.warmup, args.steps))

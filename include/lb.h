@@ -147,6 +147,14 @@ int lb_moments(lb_ctx* ctx, double* rho, double* u, double* phi);
  * given lattice and state).  sum phi is 0 for LB_SINGLE. */
 int lb_conserved_sums(lb_ctx* ctx, double* out);
 
+/* out[10] (device, FP64) = statistics of the current state, reduced in a
+ * fixed order (device reductions; the paper lists reductions as future work
+ * of its layer, Section V): 0 sum rho, 1-3 sum j, 4 sum phi, 5 sum rho u.u
+ * (twice the kinetic energy), 6 min phi, 7 max phi, 8 sum phi^2, 9 max u.u.
+ * Entries 4 and 6-8 are 0 for LB_SINGLE.  NaN anywhere in the state shows up
+ * in the sums. */
+int lb_field_stats(lb_ctx* ctx, double* out);
+
 /* Copy the current state out / in, canonical layout, storage dtype (double,
  * float or binary16), deviations for LB_F32/LB_F16.  f has 19*N elements; g
  * likewise (binary only; NULL otherwise). */

@@ -95,20 +95,36 @@ __device__ __forceinline__ void load_site(const S* src, const Site& st, const Ge
 }
 
 // Density deviation and momentum of 19 populations (deviation form:
-// rho = rho0 + sum d_i, j = sum d_i c_i).
-template <class T>
-__device__ __forceinline__ void moments_of(const T (&f)[Q], T& drho, T& jx, T& jy, T& jz) {
-    drho = T(0); jx = T(0); jy = T(0); jz = T(0);
+// rho = rho0 + sum d_i, j = sum d_i c_i), summed in A, returned in T.
+template <class A, class T>
+__device__ __forceinline__ void moments_in(const T (&f)[Q], T& drho, T& jx, T& jy, T& jz) {
+    A r = A(0), x = A(0), y = A(0), z = A(0);
     static_for<0, Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        drho = drho + f[i];
-        if constexpr (cx(i) > 0) jx = jx + f[i];
-        if constexpr (cx(i) < 0) jx = jx - f[i];
-        if constexpr (cy(i) > 0) jy = jy + f[i];
-        if constexpr (cy(i) < 0) jy = jy - f[i];
-        if constexpr (cz(i) > 0) jz = jz + f[i];
-        if constexpr (cz(i) < 0) jz = jz - f[i];
+        const A v = static_cast<A>(f[i]);
+        r = r + v;
+        if constexpr (cx(i) > 0) x = x + v;
+        if constexpr (cx(i) < 0) x = x - v;
+        if constexpr (cy(i) > 0) y = y + v;
+        if constexpr (cy(i) < 0) y = y - v;
+        if constexpr (cz(i) > 0) z = z + v;
+        if constexpr (cz(i) < 0) z = z - v;
     });
+    drho = static_cast<T>(r); jx = static_cast<T>(x); jy = static_cast<T>(y); jz = static_cast<T>(z);
+}
+
+template <class T>
+__device__ __forceinline__ void moments_of(const T (&f)[Q], T& drho, T& jx, T& jy, T& jz) {
+    moments_in<T>(f, drho, jx, jy, jz);
+}
+
+// phi = phi0 + sum_i e_i of 19 values already in registers, summed in A.
+template <class A, class T>
+__device__ __forceinline__ T phi_sum(const T (&e)[Q], T phi0) {
+    A acc = A(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) acc = acc + static_cast<A>(e[i]);
+    return static_cast<T>(static_cast<A>(phi0) + acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -124,12 +140,13 @@ __global__ __launch_bounds__(P::TPB) void k_phi(const S* __restrict__ g, typenam
     for (int v = 0; v < P::TZ; ++v) {
         const Site st = site_at(col, v, geo);
         if (!st.active) continue;
-        T acc = T(0);
+        using A = typename Accum<S>::T;
+        A acc = A(0);
         static_for<0, Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            acc = acc + static_cast<T>(ldg<P::nt_load>(g + i * geo.dstride, src_offset<i, GATHER>(st, geo)));
+            acc = acc + static_cast<A>(static_cast<T>(ldg<P::nt_load>(g + i * geo.dstride, src_offset<i, GATHER>(st, geo))));
         });
-        phi[offset_at<0, 0, 0>(st, geo)] = phi0 + acc;
+        phi[offset_at<0, 0, 0>(st, geo)] = static_cast<T>(static_cast<A>(phi0) + acc);
     }
 }
 
@@ -148,7 +165,7 @@ __device__ __forceinline__ void relax_single(const T (&f)[Q], S* fdst, uint32_t 
                                              const CollParams<T>& cp, int64_t stride = -1) {
     const int64_t ds = stride < 0 ? geo.dstride : stride;
     T drho, jx, jy, jz;
-    moments_of(f, drho, jx, jy, jz);
+    moments_in<typename Accum<S>::T>(f, drho, jx, jy, jz);
     const T rho = cp.rho0 + drho;
     const T ux = jx / rho, uy = jy / rho, uz = jz / rho;
     const T usq = ux * ux + uy * uy + uz * uz;
@@ -182,7 +199,7 @@ __device__ __forceinline__ void relax_binary(const T (&f)[Q], const T (&g)[Q], S
                                              const Geo& geo, const CollParams<T>& cp, T phic, T gx, T gy, T gz,
                                              T lap) {
     T drho, jx, jy, jz;
-    moments_of(f, drho, jx, jy, jz);
+    moments_in<typename Accum<S>::T>(f, drho, jx, jy, jz);
     const T rho = cp.rho0 + drho;
     const T ux = jx / rho, uy = jy / rho, uz = jz / rho;
     const T usq = ux * ux + uy * uy + uz * uz;
@@ -304,12 +321,13 @@ __device__ __forceinline__ int wrap_plane(int z, int nz) {
 
 template <class P, class S, class T>
 __device__ __forceinline__ T phi_of_gathered(const S* g, const Site& st, const Geo& geo, T phi0) {
-    T acc = T(0);
+    using A = typename Accum<S>::T;
+    A acc = A(0);
     static_for<0, Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        acc = acc + static_cast<T>(ldg<P::nt_load>(g + i * geo.dstride, src_offset<i, true>(st, geo)));
+        acc = acc + static_cast<A>(static_cast<T>(ldg<P::nt_load>(g + i * geo.dstride, src_offset<i, true>(st, geo))));
     });
-    return phi0 + acc;
+    return static_cast<T>(static_cast<A>(phi0) + acc);
 }
 
 // With GLDS the 19 pulled g of the next plane wait in LDS (each lane only
@@ -368,10 +386,7 @@ __global__ __launch_bounds__(P::TPB) void k_binary_march(const S* __restrict__ f
             ring[slot(z0 - 1)][hly][hlx] = phi_of_gathered<P>(gsrc, site_wrapped(hx, hy, zm, geo), geo, cp.phi0);
         const Site s0 = site_wrapped(xw, yw, z0, geo);
         load_site<P, true>(gsrc, s0, geo, gc);
-        T acc = T(0);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) acc = acc + gc[i];
-        ring[slot(z0)][ly][lx] = cp.phi0 + acc;
+        ring[slot(z0)][ly][lx] = phi_sum<typename Accum<S>::T>(gc, cp.phi0);
         if constexpr (GLDS) {
 #pragma unroll
             for (int i = 0; i < Q; ++i) gkeep[i][threadIdx.x] = gc[i];
@@ -387,10 +402,7 @@ __global__ __launch_bounds__(P::TPB) void k_binary_march(const S* __restrict__ f
         if (active) load_site<P, true>(fsrc, sc, geo, fc);
         T gn[Q];
         load_site<P, true>(gsrc, site_wrapped(xw, yw, zn, geo), geo, gn);
-        T acc = T(0);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) acc = acc + gn[i];
-        ring[slot(z + 1)][ly][lx] = cp.phi0 + acc;
+        ring[slot(z + 1)][ly][lx] = phi_sum<typename Accum<S>::T>(gn, cp.phi0);
         if (has_halo)
             ring[slot(z + 1)][hly][hlx] = phi_of_gathered<P>(gsrc, site_wrapped(hx, hy, zn, geo), geo, cp.phi0);
         if constexpr (GLDS) {
@@ -602,6 +614,90 @@ __global__ __launch_bounds__(P::TPB) void k_sums_final(const double* __restrict_
             if (k == 4) r = base4 + r;
             out[k] = accumulate ? out[k] + r : r;
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Field statistics of the current state (device reductions, fixed order):
+// 0 sum rho, 1-3 sum j, 4 sum phi, 5 sum rho u.u, 6 min phi, 7 max phi,
+// 8 sum phi^2, 9 max u.u.  Sums per block by an LDS tree, then one block over
+// the block partials in index order; min and max likewise.
+// ---------------------------------------------------------------------------
+
+constexpr int NSTAT = 10;
+
+template <int TPB>
+__device__ __forceinline__ void block_tree_stats(double (&v)[NSTAT], double (*sh)[TPB]) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < NSTAT; ++k) sh[k][t] = v[k];
+    __syncthreads();
+    for (int half = TPB / 2; half > 0; half >>= 1) {
+        if (t < half) {
+#pragma unroll
+            for (int k = 0; k < NSTAT; ++k) {
+                const double a = sh[k][t], b = sh[k][t + half];
+                sh[k][t] = k == 6 ? fmin(a, b) : (k == 7 || k == 9 ? fmax(a, b) : a + b);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <class P, int MODEL, class S, bool GATHER>
+__global__ __launch_bounds__(P::TPB) void k_stats_partial(const S* __restrict__ f, const S* __restrict__ g, Geo geo,
+                                                          double rho0, double phi0, double* __restrict__ partial) {
+    __shared__ double sh[NSTAT][P::TPB];
+    const Column col = column_of_thread<P>(geo);
+    double v[NSTAT] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, -INFINITY, 0.0, 0.0};
+    for (int z = 0; z < P::TZ; ++z) {
+        const Site st = site_at(col, z, geo);
+        if (!st.active) continue;
+        double fv[Q];
+        static_for<0, Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            fv[i] = static_cast<double>(*at(f + i * geo.dstride, src_offset<i, GATHER>(st, geo)));
+        });
+        double drho, jx, jy, jz;
+        moments_of(fv, drho, jx, jy, jz);
+        const double rho = rho0 + drho;
+        const double uu = (jx * jx + jy * jy + jz * jz) / (rho * rho);
+        v[0] += rho; v[1] += jx; v[2] += jy; v[3] += jz;
+        v[5] += rho * uu;
+        v[9] = fmax(v[9], uu);
+        if constexpr (MODEL == MODEL_BINARY) {
+            double acc = 0.0;
+            static_for<0, Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                acc = acc + static_cast<double>(*at(g + i * geo.dstride, src_offset<i, GATHER>(st, geo)));
+            });
+            const double phi = phi0 + acc;
+            v[4] += phi;
+            v[6] = fmin(v[6], phi);
+            v[7] = fmax(v[7], phi);
+            v[8] += phi * phi;
+        }
+    }
+    block_tree_stats<P::TPB>(v, sh);
+    if ((int)threadIdx.x < NSTAT) partial[16 * (size_t)blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+template <class P>
+__global__ __launch_bounds__(P::TPB) void k_stats_final(const double* __restrict__ partial, int nblocks,
+                                                        double* __restrict__ out, int binary) {
+    __shared__ double sh[NSTAT][P::TPB];
+    const int t = threadIdx.x;
+    double v[NSTAT] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, -INFINITY, 0.0, 0.0};
+    for (int b = t; b < nblocks; b += P::TPB) {
+        const double* q = partial + 16 * (size_t)b;
+#pragma unroll
+        for (int k = 0; k < NSTAT; ++k)
+            v[k] = k == 6 ? fmin(v[k], q[k]) : (k == 7 || k == 9 ? fmax(v[k], q[k]) : v[k] + q[k]);
+    }
+    block_tree_stats<P::TPB>(v, sh);
+    if (t == 0) {
+        for (int k = 0; k < NSTAT; ++k) out[k] = sh[k][0];
+        if (!binary) { out[4] = 0.0; out[6] = 0.0; out[7] = 0.0; out[8] = 0.0; }
     }
 }
 

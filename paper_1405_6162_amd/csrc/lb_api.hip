@@ -106,7 +106,7 @@ Layout layout_of(const lb_params* p) {
     L.dist_bytes = round_up(stride_bytes * Q, kAlign);
     L.phi_bytes = round_up((size_t)L.nsite * compute_size(p->storage), kAlign);
     L.nblocks = tiles(p->nx, Pol::TX) * tiles(p->ny, Pol::TY) * tiles(p->nz, Pol::TZ);
-    L.partial_bytes = round_up((size_t)L.nblocks * 8 * sizeof(double), kAlign);
+    L.partial_bytes = round_up((size_t)L.nblocks * 16 * sizeof(double), kAlign);
     size_t o = 0;
     for (int b = 0; b < 2; ++b) { L.off_f[b] = o; o += L.dist_bytes; }
     if (p->model == LB_BINARY) {
@@ -577,6 +577,30 @@ int lb_conserved_sums(lb_ctx* c, double* out) {
     return by_storage(c, [&](auto tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
         return run_sums<S>(c, out);
+    });
+}
+
+int lb_field_stats(lb_ctx* c, double* out) {
+    if (!c || !out) return LB_EINVAL;
+    return by_storage(c, [&](auto tag) {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        Timed t(c, LB_K_OTHER);
+        const S* f = (const S*)c->fbuf(c->cur);
+        const S* g = (const S*)c->gbuf(c->cur);
+        const bool dev = c->p.storage != LB_F64;
+        const double r0 = dev ? c->p.rho0 : 0.0, p0 = dev ? c->p.phi0 : 0.0;
+        const Geo geo = c->geo();
+        const bool bin = c->p.model == LB_BINARY;
+        if (bin && c->pending)
+            k_stats_partial<Pol, MODEL_BINARY, S, true><<<c->grid(), c->block(), 0, c->stream>>>(f, g, geo, r0, p0, c->partial());
+        else if (bin)
+            k_stats_partial<Pol, MODEL_BINARY, S, false><<<c->grid(), c->block(), 0, c->stream>>>(f, g, geo, r0, p0, c->partial());
+        else if (c->pending)
+            k_stats_partial<Pol, MODEL_SINGLE, S, true><<<c->grid(), c->block(), 0, c->stream>>>(f, g, geo, r0, p0, c->partial());
+        else
+            k_stats_partial<Pol, MODEL_SINGLE, S, false><<<c->grid(), c->block(), 0, c->stream>>>(f, g, geo, r0, p0, c->partial());
+        k_stats_final<Pol><<<1, c->block(), 0, c->stream>>>(c->partial(), c->L.nblocks, out, bin ? 1 : 0);
+        return launch_status();
     });
 }
 

@@ -65,6 +65,7 @@ _SIGNATURES = {
     "lb_step": (_int, [_vp, _i32]),
     "lb_moments": (_int, [_vp, _vp, _vp, _vp]),
     "lb_conserved_sums": (_int, [_vp, _vp]),
+    "lb_field_stats": (_int, [_vp, _vp]),
     "lb_get_state": (_int, [_vp, _vp, _vp]),
     "lb_set_state": (_int, [_vp, _vp, _vp]),
     "lb_set_tau": (_int, [_vp, ctypes.c_double]),
@@ -158,6 +159,10 @@ def lb_moments(ctx, rho, u, phi=None):
 
 def lb_conserved_sums(ctx, out):
     _check("lb_conserved_sums", _lib.lb_conserved_sums(ctx, _ptr(out)))
+
+
+def lb_field_stats(ctx, out):
+    _check("lb_field_stats", _lib.lb_field_stats(ctx, _ptr(out)))
 
 
 def lb_get_state(ctx, f, g=None):
@@ -276,6 +281,14 @@ class Lattice:
         lb_set_stream(self.ctx, _stream())
         out = torch.empty(5, dtype=torch.float64, device=self.device)
         lb_conserved_sums(self.ctx, out)
+        return out
+
+    def field_stats(self):
+        """(10,) device tensor: sum rho, sum j (3), sum phi, sum rho u.u,
+        min phi, max phi, sum phi^2, max u.u."""
+        lb_set_stream(self.ctx, _stream())
+        out = torch.empty(10, dtype=torch.float64, device=self.device)
+        lb_field_stats(self.ctx, out)
         return out
 
     def get_state(self):

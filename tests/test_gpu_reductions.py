@@ -1,0 +1,80 @@
+"""Device field statistics (lb_field_stats) against the same statistics taken
+from the oracle's state: sums, the kinetic-energy sum, the phi extremes and
+the largest u.u, in both state representations (direct and pending) and in
+reduced-precision storage; the result is bitwise reproducible."""
+
+import numpy as np
+import pytest
+
+from oracle import lb_oracle as O
+from paper_1405_6162_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _stats(f, g, rho0=0.0, phi0=0.0):
+    """The ten statistics of a (19, nz, ny, nx) state in FP64 numpy; rho0 and
+    phi0 are added back for deviation storage."""
+    f = f.astype(np.float64)
+    rho = rho0 + f.sum(0)
+    j = np.einsum("ia,i...->a...", O.C.astype(np.float64), f)
+    uu = (j * j).sum(0) / (rho * rho)
+    out = np.zeros(10)
+    out[0], out[1:4], out[5], out[9] = rho.sum(), j.reshape(3, -1).sum(1), (rho * uu).sum(), uu.max()
+    if g is not None:
+        phi = phi0 + g.astype(np.float64).sum(0)
+        out[4], out[6], out[7], out[8] = phi.sum(), phi.min(), phi.max(), (phi * phi).sum()
+    return out
+
+
+def _close(got, want, nsite):
+    # u.u carries an absolute rounding floor of about (1e-16 rho)^2 per site
+    scale = np.array([abs(want[0])] * 4 + [nsite] + [abs(want[5]) + 1e-20 * nsite, 1, 1, nsite, abs(want[9]) + 1e-20])
+    return np.abs(got - want) <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("model", ["single", "binary"])
+@pytest.mark.parametrize("pending", [False, True])
+def test_field_stats_fp64(lbgpu, model, pending):
+    nx, ny, nz = 37, 9, 7
+    prm = O.Params()
+    if model == "single":
+        rho, u = inputs.single_fluid_random(nx, ny, nz, seed=11)
+        lat = lbgpu.Lattice(nx, ny, nz)
+        lat.init_equilibrium(rho, u)
+        ref = (O.init_single(rho, u), None)
+        step = lambda s: (O.step_single(s[0], prm.tau_f, 1), None)
+    else:
+        rho, u, phi = inputs.spinodal_quench(nx, ny, nz, seed=11, phi_max=0.4)
+        _r, u = inputs.single_fluid_random(nx, ny, nz, seed=13)          # a flow, so u.u is not rounding
+        lat = lbgpu.Lattice(nx, ny, nz, model=lbgpu.LB_BINARY)
+        lat.init_equilibrium(rho, u, phi)
+        ref = O.init_binary(rho, u, phi, prm)
+        step = lambda s: O.step_binary(s[0], s[1], prm, 1)
+    if pending:
+        lat.step(3)
+        for _ in range(3):
+            ref = step(ref)
+    got = lat.field_stats().cpu().numpy()
+    want = _stats(*ref)
+    assert _close(got, want, nx * ny * nz).all(), (got, want)
+    if model == "single":
+        assert (got[[4, 6, 7, 8]] == 0).all()
+    assert np.array_equal(lat.field_stats().cpu().numpy(), got)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_field_stats_deviation_storage(lbgpu, storage):
+    """Reduced storage holds deviations; the statistics add rho0 and phi0 back
+    and accumulate in FP64 from the stored values."""
+    nx, ny, nz = 21, 13, 5
+    st = {"f32": lbgpu.LB_F32, "f16": lbgpu.LB_F16}[storage]
+    rho, u, phi = inputs.spinodal_quench(nx, ny, nz, seed=12, phi_max=0.4)
+    _r, u = inputs.single_fluid_random(nx, ny, nz, seed=14)
+    lat = lbgpu.Lattice(nx, ny, nz, model=lbgpu.LB_BINARY, storage=st)
+    lat.init_equilibrium(rho, u, phi)
+    lat.step(2)
+    f, g = (a.cpu().numpy() for a in lat.get_state())
+    got = lat.field_stats().cpu().numpy()
+    want = _stats(f, g, 1.0, 0.0)
+    assert _close(got, want, nx * ny * nz).all(), (got, want)
