@@ -432,3 +432,190 @@ def rollout_gradient(f0, tau, nsteps, seed=velocity_loss_seed):
         domega = domega + dw
     dtau = -domega / (tau * tau)           # omega = 1/tau
     return loss, lam, dtau
+
+
+# ---------------------------------------------------------------------------
+# Adjoint of the binary-fluid step
+# ---------------------------------------------------------------------------
+#
+# The step is f^{n+1} = propagate(f*), g^{n+1} = propagate(g*) with
+#   f*_i = f_i - omega_f (f_i - f^eq_i(rho, u, P)),
+#   g*_i = g_i - omega_g (g_i - g^eq_i(phi, u, mu)),
+# where rho, u come from f at the site, phi = sum_i g_i at the site, and P and
+# mu also read grad(phi) and lap(phi), i.e. phi at the six neighbours.  The
+# reverse sweep therefore has a local part (the transpose of the site's
+# Jacobian with respect to f, g and the three stencil inputs phi, grad phi,
+# lap phi) and a non-local part (the transpose of the two finite-difference
+# stencils, which scatters the stencil sensitivities back to the sites whose
+# phi they read, and then to every g_i there because phi = sum_i g_i).
+
+
+def binary_adjoint_sums(lf, lg, u, G):
+    """Weighted sums of the post-collision adjoints at every site that the
+    transpose of the local Jacobian is built from:
+        Lf = sum_i lf_i w_i,          Sf = sum_i lf_i w_i E_i,
+        Sg = sum_i lg_i w_i E_i,      Xf = 9/2 sum_i lf_i w_i (|c_i|^2 - 1),
+        Xg = 9/2 sum_i lg_i w_i (|c_i|^2 - 1),
+        Tf_a = sum_i lf_i w_i dE_i/du_a,  Tg_a = sum_i lg_i w_i dE_i/du_a,
+        YG_a = sum_i lf_i w_i c_ia (c_i.G)
+    with E_i = 1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u and
+    dE_i/du_a = 3 c_ia + 9 (c_i.u) c_ia - 3 u_a."""
+    uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2]
+    z = np.zeros_like(uu * lf[0])
+    Lf, Sf, Sg, Xf, Xg = z.copy(), z.copy(), z.copy(), z.copy(), z.copy()
+    Tf = [z.copy() for _ in range(3)]
+    Tg = [z.copy() for _ in range(3)]
+    YG = [z.copy() for _ in range(3)]
+    for i in range(NQ):
+        cu = C[i, 0] * u[0] + C[i, 1] * u[1] + C[i, 2] * u[2]
+        cG = C[i, 0] * G[0] + C[i, 1] * G[1] + C[i, 2] * G[2]
+        E = 1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu
+        a, b = lf[i] * W[i], lg[i] * W[i]
+        Lf = Lf + a
+        Sf = Sf + a * E
+        Sg = Sg + b * E
+        Xf = Xf + 4.5 * a * (_C2[i] - 1)
+        Xg = Xg + 4.5 * b * (_C2[i] - 1)
+        for k in range(3):
+            dE = 3.0 * C[i, k] + 9.0 * cu * C[i, k] - 3.0 * u[k]
+            Tf[k] = Tf[k] + a * dE
+            Tg[k] = Tg[k] + b * dE
+            YG[k] = YG[k] + a * C[i, k] * cG
+    return Lf, Sf, Sg, Xf, Xg, Tf, Tg, YG
+
+
+def binary_stencil_sensitivities(lf, lg, phi, G, lap, u, prm, omega_f, omega_g):
+    """Sensitivities of sum_i (lf_i f*_i + lg_i g*_i) at each site to the
+    site's own stencil inputs, at fixed f, g (hence fixed rho, u):
+        a_phi = omega_f Xf dIso/dphi + omega_g [Sg + Xg (Gamma dmu/dphi - 1/3)],
+        a_G_a = omega_f kappa [9 (YG_a - Lf G_a / 3) - Xf G_a],
+        a_lap = -kappa (omega_f phi Xf + omega_g Gamma Xg),
+    with Iso = A/2 phi^2 + 3B/4 phi^4 - kappa phi lap - kappa/2 |G|^2 the
+    isotropic part of P (dIso/dphi = A phi + 3 B phi^3 - kappa lap) and
+    dmu/dphi = A + 3 B phi^2.  f^eq carries P as
+    9/2 w_i [kappa ((c.G)^2 - |G|^2/3) + Iso (|c|^2 - 1)], g^eq carries mu as
+    9/2 w_i Gamma mu (|c|^2 - 1).  Also returns the sensitivity to kappa at
+    fixed phi, G, lap (summed over the lattice)."""
+    Lf, Sf, Sg, Xf, Xg, Tf, Tg, YG = binary_adjoint_sums(lf, lg, u, G)
+    k = prm.kappa
+    GG = G[0] * G[0] + G[1] * G[1] + G[2] * G[2]
+    diso = prm.A * phi + 3.0 * prm.B * phi ** 3 - k * lap
+    dmu = prm.A + 3.0 * prm.B * phi ** 2
+    a_phi = omega_f * Xf * diso + omega_g * (Sg + Xg * (prm.gamma * dmu - 1.0 / 3.0))
+    a_G = np.array([omega_f * k * (9.0 * (YG[a] - Lf * G[a] / 3.0) - Xf * G[a]) for a in range(3)])
+    a_lap = -k * (omega_f * phi * Xf + omega_g * prm.gamma * Xg)
+    # kappa: the anisotropic stress 9/2 kappa sum_i lf_i w_i ((c.G)^2 - |G|^2/3),
+    # Iso's -phi lap - |G|^2/2, and mu's -lap
+    GYG = G[0] * YG[0] + G[1] * YG[1] + G[2] * YG[2]
+    d_kappa = (omega_f * (4.5 * (GYG - Lf * GG / 3.0) + Xf * (-phi * lap - 0.5 * GG))
+               + omega_g * prm.gamma * Xg * (-lap)).sum()
+    return a_phi, a_G, a_lap, d_kappa, (Sf, Tf, Tg)
+
+
+def stencil_transpose(a_phi, a_G, a_lap):
+    """dL/dphi(s') from per-site sensitivities to phi(s), G(s) = grad phi(s)
+    and lap phi(s): the transposes of the central difference
+    G_a(s) = [phi(s+e_a) - phi(s-e_a)]/2 and of the 7-point Laplacian,
+        b(s') = a_phi(s') + sum_a [a_G_a(s'-e_a) - a_G_a(s'+e_a)] / 2
+                + sum_a [a_lap(s'+e_a) + a_lap(s'-e_a)] - 6 a_lap(s')."""
+    b = a_phi - 6.0 * a_lap
+    for a in range(3):
+        e = [0, 0, 0]
+        e[a] = 1
+        m = [-v for v in e]
+        b = b + 0.5 * (neighbour(a_G[a], m) - neighbour(a_G[a], e))
+        b = b + neighbour(a_lap, e) + neighbour(a_lap, m)
+    return b
+
+
+def adjoint_step_binary(f_n, g_n, lf_next, lg_next, prm):
+    """Reverse of one binary step.  With lambda*_i(s) = lambda^{n+1}_i(s + c_i)
+    for both distributions,
+        lf^n_j = (1 - omega_f) lf*_j + omega_f Sf
+                 + sum_a [omega_f Tf_a + omega_g (phi/rho) Tg_a] (c_ja - u_a),
+        lg^n_j = (1 - omega_g) lg*_j + b,
+    where the f-row comes from d rho/d f_j = 1 and d u_a/d f_j = (c_ja - u_a)/rho
+    (f^eq_i = w_i rho E_i + stress, g^eq_i = w_i phi E_i + ...), and b is the
+    transposed stencil of the sensitivities (stencil_transpose), the same for
+    every j because phi = sum_j g_j.  Also returns the parameter sensitivities
+    dL/domega_f = sum lf* (f^eq - f), dL/domega_g = sum lg* (g^eq - g) and
+    dL/dkappa (at fixed omega)."""
+    omega_f, omega_g = 1.0 / prm.tau_f, 1.0 / prm.tau_g
+    lf = np.empty_like(lf_next)
+    lg = np.empty_like(lg_next)
+    for i in range(NQ):
+        lf[i] = neighbour(lf_next[i], C[i])
+        lg[i] = neighbour(lg_next[i], C[i])
+    phi, G, lap, mu, P = binary_fields(g_n, prm)
+    u, rho = velocity(f_n)
+    a_phi, a_G, a_lap, d_kappa, (Sf, Tf, Tg) = binary_stencil_sensitivities(
+        lf, lg, phi, G, lap, u, prm, omega_f, omega_g)
+    b = stencil_transpose(a_phi, a_G, a_lap)
+    lf_n = np.empty_like(lf)
+    lg_n = np.empty_like(lg)
+    for j in range(NQ):
+        acc = omega_f * Sf
+        for a in range(3):
+            acc = acc + (omega_f * Tf[a] + omega_g * phi / rho * Tg[a]) * (C[j, a] - u[a])
+        lf_n[j] = (1.0 - omega_f) * lf[j] + acc
+        lg_n[j] = (1.0 - omega_g) * lg[j] + b
+    feq = equilibrium_f(rho, u, P)
+    geq = equilibrium_g(phi, u, mu, prm)
+    grads = {"omega_f": (lf * (feq - f_n)).sum(), "omega_g": (lg * (geq - g_n)).sum(), "kappa": d_kappa}
+    return lf_n, lg_n, grads
+
+
+def adjoint_init_binary(rho, u, phi, lf0, lg0, prm):
+    """Reverse of init_binary: f^0 = f^eq(rho, u, P(phi)), g^0 = g^eq(phi, u,
+    mu(phi)).  Given dL/df^0 and dL/dg^0 (no streaming here, so no shift),
+    returns dL/dphi (stencil sensitivities with unit relaxation, transposed),
+    dL/drho = Sf, dL/du_a = rho Tf_a + phi Tg_a, and dL/dkappa through the
+    initial state."""
+    G = gradient(phi)
+    lap = laplacian(phi)
+    a_phi, a_G, a_lap, d_kappa, (Sf, Tf, Tg) = binary_stencil_sensitivities(
+        lf0, lg0, phi, G, lap, u, prm, 1.0, 1.0)
+    dphi = stencil_transpose(a_phi, a_G, a_lap)
+    du = np.array([rho * Tf[a] + phi * Tg[a] for a in range(3)])
+    return dphi, Sf, du, d_kappa
+
+
+def binary_loss(f, g, beta=1.0):
+    """L = (1/N) sum_s [u.u + beta phi^2] (analytic, for complex steps)."""
+    u, _rho = velocity(f)
+    phi = order_parameter(g)
+    return (u[0] * u[0] + u[1] * u[1] + u[2] * u[2] + beta * phi * phi).mean()
+
+
+def binary_loss_seed(f, g, beta=1.0):
+    """(dL/df, dL/dg) of binary_loss: the velocity part as in
+    velocity_loss_seed, and 2 beta phi / N for every g_j."""
+    phi = order_parameter(g)
+    lg = np.empty_like(g)
+    for j in range(NQ):
+        lg[j] = 2.0 * beta * phi / phi.size
+    return velocity_loss_seed(f), lg
+
+
+def rollout_gradient_binary(rho, u, phi, prm, nsteps, beta=1.0):
+    """Gradient of binary_loss after nsteps binary steps from
+    init_binary(rho, u, phi) by a plain reverse sweep over every stored
+    state (small lattices only).  Returns (L, dL/dphi0, dL/drho0, dL/du0,
+    {tau_f, mobility, kappa})."""
+    f, g = init_binary(rho, u, phi, prm)
+    states = [(f, g)]
+    for _ in range(nsteps):
+        f, g = step_binary(f, g, prm)
+        states.append((f, g))
+    loss = binary_loss(f, g, beta)
+    lf, lg = binary_loss_seed(f, g, beta)
+    dw_f = dw_g = dk = 0.0
+    for n in range(nsteps - 1, -1, -1):
+        lf, lg, gr = adjoint_step_binary(states[n][0], states[n][1], lf, lg, prm)
+        dw_f, dw_g, dk = dw_f + gr["omega_f"], dw_g + gr["omega_g"], dk + gr["kappa"]
+    dphi, drho, du, dk0 = adjoint_init_binary(rho, u, phi, lf, lg, prm)
+    # omega = 1/tau; tau_g = M/Gamma + 1/2
+    grads = {"tau_f": -dw_f / prm.tau_f ** 2,
+             "mobility": -dw_g / prm.tau_g ** 2 / prm.gamma,
+             "kappa": dk + dk0}
+    return loss, dphi, drho, du, grads

@@ -106,6 +106,28 @@ def _mut_adjoint_T(f_n, lam_next, tau):
     return lam_n, (lam_star * (feq - f_n)).sum()
 
 
+def _mut_stencil_transpose_sign(a_phi, a_G, a_lap):
+    # the central difference transposed without its sign flip
+    return O.stencil_transpose.__wrapped__(a_phi, -a_G, a_lap)
+
+
+def _mut_alap_sign(lf, lg, phi, G, lap, u, prm, omega_f, omega_g):
+    a_phi, a_G, a_lap, d_kappa, rest = O.binary_stencil_sensitivities.__wrapped__(
+        lf, lg, phi, G, lap, u, prm, omega_f, omega_g)
+    return a_phi, a_G, -a_lap, d_kappa, rest
+
+
+def _mut_no_geq_velocity(lf, lg, u, G):
+    # g^eq's dependence on u forgotten in the reverse sweep
+    Lf, Sf, Sg, Xf, Xg, Tf, Tg, YG = O.binary_adjoint_sums.__wrapped__(lf, lg, u, G)
+    return Lf, Sf, Sg, Xf, Xg, Tf, [0.0 * t for t in Tg], YG
+
+
+def _mut_phi_seed_factor(f, g, beta=1.0):
+    lf, lg = O.binary_loss_seed.__wrapped__(f, g, beta)
+    return lf, 0.5 * lg
+
+
 def _swap_weights():
     w = O.W.copy()
     c2 = (O.C * O.C).sum(1)
@@ -134,6 +156,14 @@ MUTATIONS = {
     "momentum axes swapped": ("momentum", _mut_momentum_axes, [pins.test_moments_one_hot]),
     "loss seed factor": ("velocity_loss_seed", _mut_seed_factor, [pins.test_velocity_loss_seed_complex_step]),
     "adjoint T sign": ("adjoint_step_single", _mut_adjoint_T, [pins.test_adjoint_rollout_matches_complex_step]),
+    "binary adjoint: gradient stencil not negated": ("stencil_transpose", _mut_stencil_transpose_sign,
+                                                     [pins.test_binary_adjoint_rollout_matches_complex_step]),
+    "binary adjoint: Laplacian sensitivity sign": ("binary_stencil_sensitivities", _mut_alap_sign,
+                                                   [pins.test_binary_adjoint_step_matches_complex_step]),
+    "binary adjoint: g^eq velocity term dropped": ("binary_adjoint_sums", _mut_no_geq_velocity,
+                                                   [pins.test_binary_adjoint_step_matches_complex_step]),
+    "binary loss seed phi factor": ("binary_loss_seed", _mut_phi_seed_factor,
+                                    [pins.test_binary_loss_seed_complex_step]),
 }
 
 

@@ -494,3 +494,109 @@ def test_trt_shear_wave_decay_depends_on_tau_plus():
         ux = O.velocity(f)[0][0][0, :, 0]
         amp = (ux * s).sum() / (s * s).sum()
         assert abs(amp / (U * np.exp(-nu * k * k * T)) - 1.0) < 0.01
+
+
+# ---------------------------------------------------------------------------
+# Binary-fluid adjoint: complex-step derivatives of the oracle's own forward
+# map (exact to rounding) pin the hand-written reverse sweep
+# ---------------------------------------------------------------------------
+
+def _binary_adjoint_case():
+    nx, ny, nz = 4, 3, 5
+    rho, u, phi = inputs.spinodal_quench(nx, ny, nz, seed=3, phi_max=0.3)
+    rho = rho + 0.01 * np.cos(2 * np.pi * np.arange(nx) / nx)          # non-uniform density
+    _r, u = inputs.single_fluid_random(nx, ny, nz, seed=4, u_max=0.02)
+    return rho, u, phi
+
+
+def _binary_rollout_loss(rho, u, phi, prm, T, beta):
+    f, g = O.init_binary(rho, u, phi, prm)
+    return O.binary_loss(*O.step_binary(f, g, prm, T), beta)
+
+
+def test_binary_loss_seed_complex_step():
+    rho, u, phi = _binary_adjoint_case()
+    f, g = O.step_binary(*O.init_binary(rho, u, phi, O.Params()), O.Params(), 2)
+    lf, lg = O.binary_loss_seed(f, g, beta=0.7)
+    h = 1e-30
+    for which, lam, arr in (("f", lf, f), ("g", lg, g)):
+        for (i, s) in inputs.sample_components(arr[0].size, 8, seed=5):
+            fc, gc = f.astype(np.complex128), g.astype(np.complex128)
+            (fc if which == "f" else gc).reshape(19, -1)[i, s] += 1j * h
+            d = O.binary_loss(fc, gc, beta=0.7).imag / h
+            assert abs(d - lam.reshape(19, -1)[i, s]) <= 1e-13 * abs(d) + 1e-20
+
+
+def test_binary_adjoint_step_matches_complex_step():
+    """One step: the vector-Jacobian product with random adjoints equals the
+    complex-step derivative of <lambda, step(f, g)> for f and g components."""
+    rho, u, phi = _binary_adjoint_case()
+    prm = O.Params()
+    f, g = O.init_binary(rho, u, phi, prm)
+    f, g = O.step_binary(f, g, prm, 1)                       # a state off equilibrium
+    rng = np.random.default_rng(6)
+    lf1, lg1 = rng.standard_normal(f.shape), rng.standard_normal(g.shape)
+    lf0, lg0, grads = O.adjoint_step_binary(f, g, lf1, lg1, prm)
+    h = 1e-30
+
+    def proj(fc, gc, p=prm):
+        a, b = O.step_binary(fc, gc, p, 1)
+        return (lf1 * a).sum() + (lg1 * b).sum()
+    for which, lam in (("f", lf0), ("g", lg0)):
+        for (i, s) in inputs.sample_components(f[0].size, 10, seed=7):
+            fc, gc = f.astype(np.complex128), g.astype(np.complex128)
+            (fc if which == "f" else gc).reshape(19, -1)[i, s] += 1j * h
+            d = proj(fc, gc).imag / h
+            assert abs(d - lam.reshape(19, -1)[i, s]) <= 1e-12 * np.abs(lam).max()
+    import dataclasses
+    pk = dataclasses.replace(prm, kappa=prm.kappa + 1j * h)
+    d = proj(f.astype(np.complex128), g.astype(np.complex128), pk).imag / h
+    assert abs(d - grads["kappa"]) <= 1e-12 * abs(d)
+
+
+def test_binary_adjoint_rollout_matches_complex_step():
+    """Whole rollout from (rho, u, phi): dL/dphi0 at every site, dL/drho0 and
+    dL/du0 at sampled sites, and dL/dkappa, dL/dM, dL/dtau_f."""
+    import dataclasses
+    rho, u, phi = _binary_adjoint_case()
+    prm, T, beta, h = O.Params(), 3, 0.5, 1e-30
+    loss, dphi, drho, du, grads = O.rollout_gradient_binary(rho, u, phi, prm, T, beta)
+    assert loss > 0
+    cx = lambda a: a.astype(np.complex128)
+    for s in np.ndindex(phi.shape):
+        p = cx(phi)
+        p[s] += 1j * h
+        d = _binary_rollout_loss(cx(rho), cx(u), p, prm, T, beta).imag / h
+        assert abs(d - dphi[s]) <= 1e-12 * np.abs(dphi).max()
+    for s in [(0, 0, 0), (2, 1, 3), (4, 2, 1)]:
+        r = cx(rho)
+        r[s] += 1j * h
+        d = _binary_rollout_loss(r, cx(u), cx(phi), prm, T, beta).imag / h
+        assert abs(d - drho[s]) <= 1e-12 * np.abs(drho).max()
+        for a in range(3):
+            v = cx(u)
+            v[(a,) + s] += 1j * h
+            d = _binary_rollout_loss(cx(rho), v, cx(phi), prm, T, beta).imag / h
+            assert abs(d - du[(a,) + s]) <= 1e-12 * np.abs(du).max()
+    for name in ("kappa", "mobility", "tau_f"):
+        p2 = dataclasses.replace(prm, **{name: getattr(prm, name) + 1j * h})
+        d = _binary_rollout_loss(cx(rho), cx(u), cx(phi), p2, T, beta).imag / h
+        assert abs(d - grads[name]) <= 1e-11 * abs(d), name
+
+
+def test_binary_adjoint_central_differences():
+    """Independent of complex arithmetic: central differences (eps 1e-6) on
+    phi0 components and kappa."""
+    import dataclasses
+    rho, u, phi = _binary_adjoint_case()
+    prm, T, eps = O.Params(), 2, 1e-6
+    _loss, dphi, _dr, _du, grads = O.rollout_gradient_binary(rho, u, phi, prm, T)
+    L = lambda p, q=prm: _binary_rollout_loss(rho, u, p, q, T, 1.0)
+    for s in [(0, 1, 2), (3, 0, 3)]:
+        pp, pm = phi.copy(), phi.copy()
+        pp[s] += eps
+        pm[s] -= eps
+        assert abs((L(pp) - L(pm)) / (2 * eps) - dphi[s]) <= 1e-6 * np.abs(dphi).max()
+    kp = dataclasses.replace(prm, kappa=prm.kappa + eps)
+    km = dataclasses.replace(prm, kappa=prm.kappa - eps)
+    assert abs((L(phi, kp) - L(phi, km)) / (2 * eps) - grads["kappa"]) <= 1e-6 * abs(grads["kappa"])
