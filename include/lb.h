@@ -164,12 +164,14 @@ int lb_set_state(lb_ctx* ctx, const void* f, const void* g);
 /* Change tau_f (> 0.5) for subsequent collisions. */
 int lb_set_tau(lb_ctx* ctx, double tau_f);
 
-/* nsteps x (collide; propagate) like lb_step, LB_SINGLE only, recording each
- * step's post-collision field (before its propagation) in caller memory:
- * step k (0-based) writes post[k*19*N + i*N + s] (canonical layout, storage
- * dtype, nsteps*19*N elements in all).  The state afterwards equals that after
- * lb_step(nsteps).  Used by the adjoint's segment recompute: post[k] holds f^{k+1}
- * in pending (pull) form.  nsteps == 0 is a no-op. */
+/* nsteps x (collide; propagate) like lb_step (BGK), recording each step's
+ * post-collision field (before its propagation) in caller memory, canonical
+ * layout, storage dtype.  LB_SINGLE: step k (0-based) writes
+ * post[k*19*N + i*N + s] (nsteps*19*N elements).  LB_BINARY: step k writes f*
+ * at post[k*38*N + i*N + s] and g* at post[k*38*N + 19*N + i*N + s]
+ * (nsteps*38*N elements).  The state afterwards equals that after
+ * lb_step(nsteps).  Used by the adjoints' segment recompute: post[k] holds
+ * the state of step k+1 in pending (pull) form.  nsteps == 0 is a no-op. */
 int lb_step_record(lb_ctx* ctx, int32_t nsteps, void* post);
 
 /* Adjoint (reverse) of one single-fluid BGK step f^{n+1} = propagate(collide(f^n)),
@@ -182,6 +184,40 @@ int lb_step_record(lb_ctx* ctx, int32_t nsteps, void* post);
  * dL/dtau = -dL/domega / tau^2.  Uses the context's tau_f. */
 int lb_adjoint_step(lb_ctx* ctx, const double* f, int f_pending, const double* lam_next,
                     double* lam_n, double* domega);
+
+/* Replace the physical parameters (tau_f, A, B, kappa, mobility, gamma,
+ * tau_minus) for subsequent calls.  Every other field (sizes, model,
+ * storage, vvl, collision, rho0, phi0) must equal the context's, else
+ * LB_EINVAL; values are validated as by lb_create.  The state is kept. */
+int lb_set_params(lb_ctx* ctx, const lb_params* p);
+
+/* Adjoint (reverse) of one binary-fluid BGK step, LB_BINARY + LB_F64 only.
+ * The step is the one of lb_step: f and g relax to their equilibria, whose
+ * pressure tensor and chemical potential read phi = sum g at the site and
+ * its six neighbours (central-difference gradient and 7-point Laplacian,
+ * Section II-A's finite-difference order-parameter model), then both
+ * propagate.  f, g (19*N each, canonical FP64) are f^n and g^n when
+ * pending == 0, or the recorded post-collision fields of step n-1 (as written
+ * by lb_step_record) when pending != 0, in which case f^n_i(s) = f_i(s - c_i).
+ * lf_next, lg_next = dL/df^{n+1}, dL/dg^{n+1}; lf_n, lg_n receive dL/df^n and
+ * dL/dg^n (must not alias the inputs or each other).  grads (3 device
+ * doubles) is INCREMENTED by dL/d(1/tau_f), dL/d(1/tau_g) and dL/dkappa of
+ * this step (tau_g = mobility/gamma + 1/2).  Uses the context's parameters;
+ * uses the context's spare state buffer and phi buffer as scratch, so calls
+ * on one context must not overlap; the lattice state itself is unchanged. */
+int lb_adjoint_step_binary(lb_ctx* ctx, const double* f, const double* g, int pending,
+                           const double* lf_next, const double* lg_next, double* lf_n,
+                           double* lg_n, double* grads);
+
+/* Reverse of lb_init_equilibrium for LB_BINARY + LB_F64: given rho[N],
+ * u[3*N], phi[N] (the initial fields, as passed to lb_init_equilibrium) and
+ * lf0, lg0 = dL/df^0, dL/dg^0 (19*N each), writes dphi[N] = dL/dphi,
+ * drho[N] = dL/drho, du[3*N] = dL/du and INCREMENTS *dkappa (one device
+ * double) by the dependence of the initial state on kappa.  Same scratch
+ * rule as lb_adjoint_step_binary. */
+int lb_adjoint_init_binary(lb_ctx* ctx, const double* rho, const double* u, const double* phi,
+                           const double* lf0, const double* lg0, double* dphi, double* drho,
+                           double* du, double* dkappa);
 
 /* Masked transfer (the masked host/target copies of Section III-B, which pack
  * the selected sites on the device so that only they cross to the host).

@@ -1,6 +1,8 @@
-"""Differentiable single-fluid rollout: f_T = step^T(f_0; tau) as a
-torch.autograd.Function whose backward runs the hand-written adjoint kernel
-(lb_adjoint_step) of the fused collide-stream step.
+"""Differentiable rollouts: the single fluid, f_T = step^T(f_0; tau), and the
+binary fluid, (f_T, g_T) from the equilibrium on (rho0, u0, phi0) with
+kappa, mobility and tau_f, as torch.autograd.Functions whose backward runs
+the hand-written adjoint kernels (lb_adjoint_step, lb_adjoint_step_binary,
+lb_adjoint_init_binary) of the fused collide-stream step.
 
 Memory: the forward keeps only the states at steps 0, K, 2K, ...; the
 backward recomputes each segment of at most K steps on the GPU, recording
@@ -83,6 +85,111 @@ class LBRollout(torch.autograd.Function):
         grad_tau = (-domega[0] / (tau * tau)).reshape(())
         ctx.ckpts = None
         return lam, grad_tau, None, None, None
+
+
+class LBBinaryRollout(torch.autograd.Function):
+    """(f_T, g_T) = LBBinaryRollout.apply(rho0, u0, phi0, kappa, mobility,
+    tau_f, lattice, nsteps, every).
+
+    Binary-fluid rollout from the equilibrium built on (rho0, u0, phi0)
+    (float64 device tensors of shapes (nz, ny, nx), (3, nz, ny, nx),
+    (nz, ny, nx)), with kappa, mobility and tau_f as 0-d float64 tensors.
+    lattice: an lb.Lattice with model LB_BINARY and storage LB_F64, whose
+    state and parameters this call overwrites.  Gradients flow to rho0, u0,
+    phi0, kappa, mobility and tau_f.  The backward recomputes each segment of
+    at most `every` steps from its checkpoint, recording every step's
+    post-collision f and g, and runs the two adjoint kernels per step
+    (lb_adjoint_step_binary), then the reverse of the initialisation
+    (lb_adjoint_init_binary).
+    """
+
+    @staticmethod
+    def forward(ctx, rho0, u0, phi0, kappa, mobility, tau_f, lattice, nsteps, every):
+        if lattice.model != lb.LB_BINARY or lattice.storage != lb.LB_F64:
+            raise ValueError("the binary adjoint is implemented for the binary fluid in FP64")
+        if nsteps < 0 or every < 1:
+            raise ValueError("nsteps must be >= 0 and every >= 1")
+        lattice.set_params(kappa=float(kappa), mobility=float(mobility), tau_f=float(tau_f))
+        fields = tuple(t.detach().to(torch.float64).contiguous() for t in (rho0, u0, phi0))
+        lattice.init_equilibrium(*fields)
+        ckpts = [lattice.get_state()]
+        done = 0
+        while done < nsteps:
+            k = min(every, nsteps - done)
+            lattice.step(k)
+            done += k
+            if done < nsteps:
+                ckpts.append(lattice.get_state())
+        fT, gT = lattice.get_state() if nsteps > 0 else (ckpts[0][0].clone(), ckpts[0][1].clone())
+        ctx.lattice, ctx.nsteps, ctx.every = lattice, nsteps, every
+        ctx.ckpts, ctx.fields = ckpts, fields
+        ctx.params = (float(kappa), float(mobility), float(tau_f))
+        return fT, gT
+
+    @staticmethod
+    def backward(ctx, grad_f, grad_g):
+        lat, T, K = ctx.lattice, ctx.nsteps, ctx.every
+        kappa, mobility, tau_f = ctx.params
+        lat.set_params(kappa=kappa, mobility=mobility, tau_f=tau_f)
+        shape = ctx.ckpts[0][0].shape
+        dev = ctx.ckpts[0][0].device
+        zero = lambda: torch.zeros(shape, dtype=torch.float64, device=dev)
+        lf = grad_f.detach().to(torch.float64).contiguous() if grad_f is not None else zero()
+        lg = grad_g.detach().to(torch.float64).contiguous() if grad_g is not None else zero()
+        grads = torch.zeros(3, dtype=torch.float64, device=dev)
+        for seg in range(len(ctx.ckpts) - 1, -1, -1):
+            start = seg * K
+            length = min(K, T - start)
+            if length <= 0:
+                continue
+            f_ck, g_ck = ctx.ckpts[seg]
+            lat.set_state(f_ck, g_ck)
+            post = None
+            if length > 1:
+                post = torch.empty((length - 1, 2 * lb.Q) + tuple(shape[1:]), dtype=torch.float64, device=dev)
+                lb.lb_set_stream(lat.ctx, lb._stream())
+                lb.lb_step_record(lat.ctx, length - 1, post)
+            for n in range(length - 1, -1, -1):
+                lf_n, lg_n = torch.empty_like(lf), torch.empty_like(lg)
+                lb.lb_set_stream(lat.ctx, lb._stream())
+                if n == 0:
+                    lb.lb_adjoint_step_binary(lat.ctx, f_ck, g_ck, lf, lg, lf_n, lg_n, grads)
+                else:
+                    lb.lb_adjoint_step_binary(lat.ctx, post[n - 1, :lb.Q], post[n - 1, lb.Q:], lf, lg, lf_n, lg_n,
+                                              grads, pending=True)
+                lf, lg = lf_n, lg_n
+            del post
+        rho0, u0, phi0 = ctx.fields
+        dphi, drho, du = torch.empty_like(phi0), torch.empty_like(rho0), torch.empty_like(u0)
+        dkappa0 = torch.zeros(1, dtype=torch.float64, device=dev)
+        lb.lb_set_stream(lat.ctx, lb._stream())
+        lb.lb_adjoint_init_binary(lat.ctx, rho0, u0, phi0, lf, lg, dphi, drho, du, dkappa0)
+        tau_g = mobility / lat.params.gamma + 0.5
+        g_kappa = (grads[2] + dkappa0[0]).reshape(())
+        g_mob = (-grads[1] / (tau_g * tau_g) / lat.params.gamma).reshape(())
+        g_tau = (-grads[0] / (tau_f * tau_f)).reshape(())
+        ctx.ckpts = ctx.fields = None
+        return drho, du, dphi, g_kappa, g_mob, g_tau, None, None, None
+
+
+def rollout_binary(rho0, u0, phi0, lattice, nsteps, every=20, kappa=None, mobility=None, tau_f=None):
+    """Convenience wrapper: LBBinaryRollout.apply with tensor parameters
+    (defaults: the lattice's current values)."""
+    dev = phi0.device
+    as_t = lambda v, d: v if torch.is_tensor(v) else torch.tensor(float(d if v is None else v),
+                                                                   dtype=torch.float64, device=dev)
+    return LBBinaryRollout.apply(rho0, u0, phi0, as_t(kappa, lattice.params.kappa),
+                                 as_t(mobility, lattice.params.mobility), as_t(tau_f, lattice.params.tau_f),
+                                 lattice, int(nsteps), int(every))
+
+
+def binary_loss(f, g, beta=1.0):
+    """Mean over the lattice of u.u + beta phi^2, as torch ops."""
+    c = velocity_table(f.device, f.dtype)
+    rho = f.sum(0)
+    u = torch.tensordot(c.t(), f, dims=1) / rho
+    phi = g.sum(0)
+    return ((u * u).sum(0) + beta * phi * phi).mean()
 
 
 def rollout(f0, tau, lattice, nsteps, every=20):

@@ -762,6 +762,249 @@ __global__ __launch_bounds__(P::TPB) void k_adjoint(const double* __restrict__ f
 }
 
 // ---------------------------------------------------------------------------
+// Adjoint of one binary-fluid FP64 step.  The step reads, at each site, f and
+// g and three stencil inputs built from phi = sum g at the site and its six
+// neighbours (phi, grad phi, lap phi).  The reverse sweep is split the same
+// way: a local kernel applies the transpose of the site's Jacobian (giving
+// dL/df^n directly, and the site's sensitivities to its stencil inputs), and
+// a stencil kernel applies the transposes of the central difference and of
+// the 7-point Laplacian to those sensitivities, which gives dL/dphi at each
+// site and hence the same addition to every dL/dg^n_j there.
+//
+// With lambda* the post-collision adjoints of a site, w_i their weights,
+// E_i = 1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u and X = 9/2 sum lambda* w (|c|^2 - 1):
+//   a_phi = omega_f Xf (A phi + 3 B phi^3 - kappa lap)
+//           + omega_g [Sg + Xg (Gamma (A + 3 B phi^2) - 1/3)],
+//   a_G   = omega_f kappa [9 (YG - Lf G / 3) - Xf G],   YG_a = sum lf* w c_a (c.G),
+//   a_lap = -kappa (omega_f phi Xf + omega_g Gamma Xg),
+// Sf, Sg = sum lambda* w E, Lf = sum lf* w, and T_a = sum lambda* w dE/du_a.
+// ---------------------------------------------------------------------------
+
+struct BinAdj {
+    double Sf, Tf[3], Tg[3];     // f-row of the transpose, and dL/drho, dL/du
+    double a_phi, a_G[3], a_lap; // sensitivities to the stencil inputs
+    double dkappa;               // sensitivity to kappa at fixed phi, G, lap
+};
+
+__device__ __forceinline__ BinAdj binary_adjoint_site(const double (&lf)[Q], const double (&lg)[Q], double ux,
+                                                      double uy, double uz, double phi, double Gx, double Gy,
+                                                      double Gz, double lap, const CollParams<double>& cp,
+                                                      double omega_f, double omega_g) {
+    const double usq = ux * ux + uy * uy + uz * uz;
+    double Lf = 0.0, Lg = 0.0, Sf = 0.0, Sg = 0.0, Xf = 0.0, Xg = 0.0;
+    double tf[3] = {0.0, 0.0, 0.0}, tg[3] = {0.0, 0.0, 0.0}, yg[3] = {0.0, 0.0, 0.0};
+    static_for<0, Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        const double cu = cdot<i>(ux, uy, uz);
+        const double cG = cdot<i>(Gx, Gy, Gz);
+        const double E = 1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq;
+        const double a = lf[i] * weight<double>(i), b = lg[i] * weight<double>(i);
+        Lf = Lf + a;
+        Lg = Lg + b;
+        Sf = Sf + a * E;
+        Sg = Sg + b * E;
+        if constexpr (csq(i) == 0) { Xf = Xf - a; Xg = Xg - b; }
+        if constexpr (csq(i) == 2) { Xf = Xf + a; Xg = Xg + b; }
+        const double hf = a * (3.0 + 9.0 * cu), hg = b * (3.0 + 9.0 * cu), y = a * cG;
+        if constexpr (cx(i) > 0) { tf[0] = tf[0] + hf; tg[0] = tg[0] + hg; yg[0] = yg[0] + y; }
+        if constexpr (cx(i) < 0) { tf[0] = tf[0] - hf; tg[0] = tg[0] - hg; yg[0] = yg[0] - y; }
+        if constexpr (cy(i) > 0) { tf[1] = tf[1] + hf; tg[1] = tg[1] + hg; yg[1] = yg[1] + y; }
+        if constexpr (cy(i) < 0) { tf[1] = tf[1] - hf; tg[1] = tg[1] - hg; yg[1] = yg[1] - y; }
+        if constexpr (cz(i) > 0) { tf[2] = tf[2] + hf; tg[2] = tg[2] + hg; yg[2] = yg[2] + y; }
+        if constexpr (cz(i) < 0) { tf[2] = tf[2] - hf; tg[2] = tg[2] - hg; yg[2] = yg[2] - y; }
+    });
+    Xf = 4.5 * Xf;
+    Xg = 4.5 * Xg;
+    const double u[3] = {ux, uy, uz}, G[3] = {Gx, Gy, Gz};
+    const double k = cp.kappa;
+    const double GG = Gx * Gx + Gy * Gy + Gz * Gz;
+    BinAdj r;
+    r.Sf = Sf;
+    for (int a = 0; a < 3; ++a) {
+        r.Tf[a] = tf[a] - 3.0 * u[a] * Lf;
+        r.Tg[a] = tg[a] - 3.0 * u[a] * Lg;
+        r.a_G[a] = omega_f * k * (9.0 * (yg[a] - Lf * G[a] / 3.0) - Xf * G[a]);
+    }
+    const double diso = cp.A * phi + 3.0 * cp.B * phi * phi * phi - k * lap;
+    const double dmu = cp.A + 3.0 * cp.B * phi * phi;
+    r.a_phi = omega_f * Xf * diso + omega_g * (Sg + Xg * (cp.gamma * dmu - 1.0 / 3.0));
+    r.a_lap = -k * (omega_f * phi * Xf + omega_g * cp.gamma * Xg);
+    const double GYG = Gx * yg[0] + Gy * yg[1] + Gz * yg[2];
+    r.dkappa = omega_f * (4.5 * (GYG - Lf * GG / 3.0) + Xf * (-phi * lap - 0.5 * GG))
+               + omega_g * cp.gamma * Xg * (-lap);
+    return r;
+}
+
+// phi and its central-difference gradient and Laplacian at a site, from a
+// scalar field in canonical layout.
+__device__ __forceinline__ void phi_stencil(const double* __restrict__ phi, const Site& st, const Geo& geo,
+                                            double& p, double& Gx, double& Gy, double& Gz, double& lap) {
+    p = phi[offset_at<0, 0, 0>(st, geo)];
+    const double pxm = phi[offset_at<-1, 0, 0>(st, geo)], pxp = phi[offset_at<1, 0, 0>(st, geo)];
+    const double pym = phi[offset_at<0, -1, 0>(st, geo)], pyp = phi[offset_at<0, 1, 0>(st, geo)];
+    const double pzm = phi[offset_at<0, 0, -1>(st, geo)], pzp = phi[offset_at<0, 0, 1>(st, geo)];
+    Gx = 0.5 * (pxp - pxm);
+    Gy = 0.5 * (pyp - pym);
+    Gz = 0.5 * (pzp - pzm);
+    lap = (pxp + pxm) + (pyp + pym) + (pzp + pzm) - 6.0 * p;
+}
+
+// Local part of the binary adjoint step.  fn, gn: f^n and g^n (canonical,
+// or the recorded post-collision fields of the previous step when
+// F_PENDING, pulled); phi: phi^n (canonical); lf_next, lg_next: lambda^{n+1}.
+// Writes lambda_f^n and the five sensitivity fields afield[k*N + s]
+// (a_phi, a_Gx, a_Gy, a_Gz, a_lap); block partials of dL/domega_f,
+// dL/domega_g and dL/dkappa go to partial[8 b + 0..2].
+template <class P, bool F_PENDING>
+__global__ __launch_bounds__(P::TPB) void k_adjoint_binary(const double* __restrict__ fn,
+                                                           const double* __restrict__ gn,
+                                                           const double* __restrict__ phi,
+                                                           const double* __restrict__ lf_next,
+                                                           const double* __restrict__ lg_next,
+                                                           double* __restrict__ lf_n, double* __restrict__ afield,
+                                                           double* __restrict__ partial, Geo geo,
+                                                           CollParams<double> cp) {
+    __shared__ double sh[3][P::TPB];
+    const Column col = column_of_thread<P>(geo);
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int v = 0; v < P::TZ; ++v) {
+        const Site st = site_at(col, v, geo);
+        if (!st.active) continue;
+        const uint32_t off = offset_at<0, 0, 0>(st, geo);
+        double f[Q], g[Q], lf[Q], lg[Q];
+        static_for<0, Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            f[i] = *at(fn + i * geo.dstride, src_offset<i, F_PENDING>(st, geo));
+            g[i] = *at(gn + i * geo.dstride, src_offset<i, F_PENDING>(st, geo));
+            lf[i] = *at(lf_next + i * geo.dstride, offset_at<cx(i), cy(i), cz(i)>(st, geo));
+            lg[i] = *at(lg_next + i * geo.dstride, offset_at<cx(i), cy(i), cz(i)>(st, geo));
+        });
+        double p, Gx, Gy, Gz, lap;
+        phi_stencil(phi, st, geo, p, Gx, Gy, Gz, lap);
+        double rho, jx, jy, jz;
+        moments_of(f, rho, jx, jy, jz);
+        const double ux = jx / rho, uy = jy / rho, uz = jz / rho;
+        const BinAdj r = binary_adjoint_site(lf, lg, ux, uy, uz, p, Gx, Gy, Gz, lap, cp, cp.omega_f, cp.omega_g);
+        // relaxation-rate sensitivities sum lambda* (eq - current)
+        const double usq = ux * ux + uy * uy + uz * uz;
+        const FreeEnergy<double> fe(p, Gx, Gy, Gz, lap, cp);
+        double dwf = 0.0, dwg = 0.0;
+        static_for<0, Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            const double cu = cdot<i>(ux, uy, uz);
+            const double E = 1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq;
+            const double feq = weight<double>(i) * (rho * E + fe.template stress_term<i>(cp));
+            const double geq = weight<double>(i) * (p * E + fe.template mobility_term<i>(cp));
+            dwf = dwf + lf[i] * (feq - f[i]);
+            dwg = dwg + lg[i] * (geq - g[i]);
+        });
+        const double wg = cp.omega_g * p / rho;
+        const double V[3] = {cp.omega_f * r.Tf[0] + wg * r.Tg[0], cp.omega_f * r.Tf[1] + wg * r.Tg[1],
+                             cp.omega_f * r.Tf[2] + wg * r.Tg[2]};
+        const double base = cp.omega_f * r.Sf - (V[0] * ux + V[1] * uy + V[2] * uz);
+        static_for<0, Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            *at(lf_n + i * geo.dstride, off) = (1.0 - cp.omega_f) * lf[i] + base + cdot<i>(V[0], V[1], V[2]);
+        });
+        afield[off] = r.a_phi;
+        afield[(size_t)geo.nsite + off] = r.a_G[0];
+        afield[2 * (size_t)geo.nsite + off] = r.a_G[1];
+        afield[3 * (size_t)geo.nsite + off] = r.a_G[2];
+        afield[4 * (size_t)geo.nsite + off] = r.a_lap;
+        acc[0] = acc[0] + dwf;
+        acc[1] = acc[1] + dwg;
+        acc[2] = acc[2] + r.dkappa;
+    }
+    block_tree_sum<P::TPB, 3>(acc, sh);
+    if ((int)threadIdx.x < 3) partial[8 * (size_t)blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// Local part of the reverse of the equilibrium initialisation
+// f^0 = f^eq(rho, u, P(phi)), g^0 = g^eq(phi, u, mu(phi)): unit relaxation,
+// unshifted adjoints.  Writes the sensitivity fields, dL/drho = Sf and
+// dL/du_a = rho Tf_a + phi Tg_a; partial[8 b + 0] = dL/dkappa.
+template <class P>
+__global__ __launch_bounds__(P::TPB) void k_adjoint_binary_init(const double* __restrict__ rho_in,
+                                                                const double* __restrict__ u_in,
+                                                                const double* __restrict__ phi,
+                                                                const double* __restrict__ lf0,
+                                                                const double* __restrict__ lg0,
+                                                                double* __restrict__ afield,
+                                                                double* __restrict__ drho,
+                                                                double* __restrict__ du,
+                                                                double* __restrict__ partial, Geo geo,
+                                                                CollParams<double> cp) {
+    __shared__ double sh[1][P::TPB];
+    const Column col = column_of_thread<P>(geo);
+    double acc[1] = {0.0};
+    for (int v = 0; v < P::TZ; ++v) {
+        const Site st = site_at(col, v, geo);
+        if (!st.active) continue;
+        const uint32_t off = offset_at<0, 0, 0>(st, geo);
+        double lf[Q], lg[Q];
+        static_for<0, Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            lf[i] = lf0[i * geo.dstride + off];
+            lg[i] = lg0[i * geo.dstride + off];
+        });
+        double p, Gx, Gy, Gz, lap;
+        phi_stencil(phi, st, geo, p, Gx, Gy, Gz, lap);
+        const double rho = rho_in[off];
+        const double ux = u_in[off], uy = u_in[(size_t)geo.nsite + off], uz = u_in[2 * (size_t)geo.nsite + off];
+        const BinAdj r = binary_adjoint_site(lf, lg, ux, uy, uz, p, Gx, Gy, Gz, lap, cp, 1.0, 1.0);
+        afield[off] = r.a_phi;
+        afield[(size_t)geo.nsite + off] = r.a_G[0];
+        afield[2 * (size_t)geo.nsite + off] = r.a_G[1];
+        afield[3 * (size_t)geo.nsite + off] = r.a_G[2];
+        afield[4 * (size_t)geo.nsite + off] = r.a_lap;
+        drho[off] = r.Sf;
+        for (int a = 0; a < 3; ++a) du[(size_t)a * geo.nsite + off] = rho * r.Tf[a] + p * r.Tg[a];
+        acc[0] = acc[0] + r.dkappa;
+    }
+    block_tree_sum<P::TPB, 1>(acc, sh);
+    if (threadIdx.x == 0) partial[8 * (size_t)blockIdx.x] = sh[0][0];
+}
+
+// Stencil part: b(s) = a_phi(s) - 6 a_lap(s) + sum_a [a_G_a(s - e_a) - a_G_a(s + e_a)] / 2
+//                      + sum_a [a_lap(s + e_a) + a_lap(s - e_a)]   (= dL/dphi(s)).
+// INIT: out[s] = b.  Otherwise out is lambda_g^n: out_j(s) = (1 - omega_g)
+// lambda_g^{n+1}_j(s + c_j) + b(s).
+template <class P, bool INIT>
+__global__ __launch_bounds__(P::TPB) void k_adjoint_binary_stencil(const double* __restrict__ afield,
+                                                                   const double* __restrict__ lg_next,
+                                                                   double* __restrict__ out, Geo geo,
+                                                                   double omega_g) {
+    const Column col = column_of_thread<P>(geo);
+    const size_t N = geo.nsite;
+    for (int v = 0; v < P::TZ; ++v) {
+        const Site st = site_at(col, v, geo);
+        if (!st.active) continue;
+        const uint32_t off = offset_at<0, 0, 0>(st, geo);
+        const double* ap = afield;
+        const double* ax = afield + N;
+        const double* ay = afield + 2 * N;
+        const double* az = afield + 3 * N;
+        const double* al = afield + 4 * N;
+        double b = ap[off] - 6.0 * al[off];
+        b = b + 0.5 * (ax[offset_at<-1, 0, 0>(st, geo)] - ax[offset_at<1, 0, 0>(st, geo)]);
+        b = b + 0.5 * (ay[offset_at<0, -1, 0>(st, geo)] - ay[offset_at<0, 1, 0>(st, geo)]);
+        b = b + 0.5 * (az[offset_at<0, 0, -1>(st, geo)] - az[offset_at<0, 0, 1>(st, geo)]);
+        b = b + (al[offset_at<1, 0, 0>(st, geo)] + al[offset_at<-1, 0, 0>(st, geo)]);
+        b = b + (al[offset_at<0, 1, 0>(st, geo)] + al[offset_at<0, -1, 0>(st, geo)]);
+        b = b + (al[offset_at<0, 0, 1>(st, geo)] + al[offset_at<0, 0, -1>(st, geo)]);
+        if constexpr (INIT) {
+            out[off] = b;
+        } else {
+            static_for<0, Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                *at(out + i * geo.dstride, off) =
+                    (1.0 - omega_g) * *at(lg_next + i * geo.dstride, offset_at<cx(i), cy(i), cz(i)>(st, geo)) + b;
+            });
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Masked transfer (the masked copies of Section III-B): a mask over the sites
 // is compacted, in increasing site order, into a list of site indices; the
 // state at the listed sites is then gathered into or scattered from a packed

@@ -423,8 +423,53 @@ int run_set_state(lb_ctx* c, const S* f, const S* g) {
 
 // nsteps single-fluid steps whose post-collision fields go to post[k] (canonical
 // stride N); afterwards the state is pending on a copy of the last of them.
+// Binary: step k writes post-collision f then g at post + k*38*N.  Step 0
+// collides the context's state in its own buffers and copies the result out;
+// later steps march from post[k-1] to post[k] (both of direction stride N).
+template <class S>
+int run_step_record_binary(lb_ctx* c, int32_t n, S* post) {
+    const int64_t N = c->L.nsite;
+    const size_t w = (size_t)N * sizeof(S), sp = (size_t)c->L.dstride * sizeof(S);
+    int rc = run_collide<S>(c);                       // state now direct: the post-collision field
+    if (rc) return rc;
+    {
+        Timed t(c, LB_K_OTHER);
+        if (hipMemcpy2DAsync(post, w, c->fbuf(c->cur), sp, w, Q, hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
+            hipMemcpy2DAsync(post + Q * N, w, c->gbuf(c->cur), sp, w, Q, hipMemcpyDeviceToDevice, c->stream) !=
+                hipSuccess)
+            return LB_EDEVICE;
+    }
+    c->pending = true;
+    using MP = typename March<S>::P;
+    constexpr int BZ = March<S>::bz;
+    Geo g = c->template march_geo<MP, BZ>();
+    g.dstride = N;
+    const auto cp = coll_params<S>(c);
+    for (int32_t k = 1; k < n; ++k) {
+        const S* src = post + (size_t)(k - 1) * 2 * Q * N;
+        S* dst = post + (size_t)k * 2 * Q * N;
+        {
+            Timed t(c, LB_K_COLLIDE);
+            k_binary_march<MP, BZ, S, March<S>::glds><<<dim3(g.nblocks), dim3(MP::TPB), 0, c->stream>>>(
+                src, src + Q * N, dst, dst + Q * N, g, cp);
+        }
+        rc = launch_status();
+        if (rc) return rc;
+    }
+    if (n > 1) {
+        Timed t(c, LB_K_OTHER);
+        const S* last = post + (size_t)(n - 1) * 2 * Q * N;
+        if (hipMemcpy2DAsync(c->fbuf(c->cur), sp, last, w, w, Q, hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
+            hipMemcpy2DAsync(c->gbuf(c->cur), sp, last + Q * N, w, w, Q, hipMemcpyDeviceToDevice, c->stream) !=
+                hipSuccess)
+            return LB_EDEVICE;
+    }
+    return LB_OK;
+}
+
 template <class S>
 int run_step_record(lb_ctx* c, int32_t n, S* post) {
+    if (c->p.model == LB_BINARY) return run_step_record_binary<S>(c, n, post);
     const int64_t N = c->L.nsite;
     const auto cp = coll_params<S>(c);
     const dim3 grid = c->grid(), block = c->block();
@@ -632,11 +677,79 @@ int lb_step_record(lb_ctx* c, int32_t nsteps, void* post) {
     if (!c || nsteps < 0) return LB_EINVAL;
     if (nsteps == 0) return LB_OK;
     if (!post) return LB_EINVAL;
-    if (c->p.model != LB_SINGLE || c->p.collision != LB_BGK) return LB_ENOTSUP;
+    if (c->p.collision != LB_BGK) return LB_ENOTSUP;
     return by_storage(c, [&](auto tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
         return run_step_record<S>(c, nsteps, (S*)post);
     });
+}
+
+int lb_set_params(lb_ctx* c, const lb_params* p) {
+    if (!c || !p) return LB_EINVAL;
+    int rc = check_params(p);
+    if (rc) return rc;
+    const lb_params& q = c->p;
+    if (p->nx != q.nx || p->ny != q.ny || p->nz != q.nz || p->model != q.model || p->storage != q.storage ||
+        p->vvl != q.vvl || p->collision != q.collision || p->rho0 != q.rho0 || p->phi0 != q.phi0)
+        return LB_EINVAL;
+    c->p = *p;
+    return LB_OK;
+}
+
+int lb_adjoint_step_binary(lb_ctx* c, const double* f, const double* g, int pending, const double* lf_next,
+                           const double* lg_next, double* lf_n, double* lg_n, double* grads) {
+    if (!c || !f || !g || !lf_next || !lg_next || !lf_n || !lg_n || !grads) return LB_EINVAL;
+    if (c->p.model != LB_BINARY || c->p.storage != LB_F64) return LB_ENOTSUP;
+    const double* outs[2] = {lf_n, lg_n};
+    const double* ins[4] = {f, g, lf_next, lg_next};
+    for (const double* o : outs)
+        for (const double* i : ins)
+            if (o == i) return LB_EINVAL;
+    if (lf_n == lg_n) return LB_EINVAL;
+    c->launched = true;
+    const Geo geo = c->canonical_geo();
+    const auto cp = coll_params<double>(c);
+    double* phi = (double*)c->phi();
+    double* afield = (double*)c->fbuf(1 - c->cur);       // spare state buffer: 19 dstride >= 5 N doubles
+    {
+        Timed t(c, LB_K_PHI);
+        if (pending) k_phi<Pol, double, true><<<c->grid(), c->block(), 0, c->stream>>>(g, phi, geo, 0.0);
+        else k_phi<Pol, double, false><<<c->grid(), c->block(), 0, c->stream>>>(g, phi, geo, 0.0);
+    }
+    {
+        Timed t(c, LB_K_ADJOINT);
+        if (pending)
+            k_adjoint_binary<Pol, true><<<c->grid(), c->block(), 0, c->stream>>>(f, g, phi, lf_next, lg_next, lf_n,
+                                                                               afield, c->partial(), geo, cp);
+        else
+            k_adjoint_binary<Pol, false><<<c->grid(), c->block(), 0, c->stream>>>(f, g, phi, lf_next, lg_next, lf_n,
+                                                                                afield, c->partial(), geo, cp);
+    }
+    {
+        Timed t(c, LB_K_ADJOINT);
+        k_adjoint_binary_stencil<Pol, false><<<c->grid(), c->block(), 0, c->stream>>>(afield, lg_next, lg_n, geo,
+                                                                                     cp.omega_g);
+    }
+    k_sums_final<Pol, 3><<<1, c->block(), 0, c->stream>>>(c->partial(), c->L.nblocks, grads, 0.0, 0.0, 1);
+    return launch_status();
+}
+
+int lb_adjoint_init_binary(lb_ctx* c, const double* rho, const double* u, const double* phi, const double* lf0,
+                           const double* lg0, double* dphi, double* drho, double* du, double* dkappa) {
+    if (!c || !rho || !u || !phi || !lf0 || !lg0 || !dphi || !drho || !du || !dkappa) return LB_EINVAL;
+    if (c->p.model != LB_BINARY || c->p.storage != LB_F64) return LB_ENOTSUP;
+    c->launched = true;
+    const Geo geo = c->canonical_geo();
+    const auto cp = coll_params<double>(c);
+    double* afield = (double*)c->fbuf(1 - c->cur);
+    {
+        Timed t(c, LB_K_ADJOINT);
+        k_adjoint_binary_init<Pol><<<c->grid(), c->block(), 0, c->stream>>>(rho, u, phi, lf0, lg0, afield, drho, du,
+                                                                           c->partial(), geo, cp);
+        k_adjoint_binary_stencil<Pol, true><<<c->grid(), c->block(), 0, c->stream>>>(afield, nullptr, dphi, geo, 1.0);
+    }
+    k_sums_final<Pol, 1><<<1, c->block(), 0, c->stream>>>(c->partial(), c->L.nblocks, dkappa, 0.0, 0.0, 1);
+    return launch_status();
 }
 
 int lb_adjoint_step(lb_ctx* c, const double* f, int f_pending, const double* lam_next, double* lam_n,

@@ -66,6 +66,9 @@ _SIGNATURES = {
     "lb_moments": (_int, [_vp, _vp, _vp, _vp]),
     "lb_conserved_sums": (_int, [_vp, _vp]),
     "lb_field_stats": (_int, [_vp, _vp]),
+    "lb_set_params": (_int, [_vp, _vp]),
+    "lb_adjoint_step_binary": (_int, [_vp, _vp, _vp, ctypes.c_int, _vp, _vp, _vp, _vp, _vp]),
+    "lb_adjoint_init_binary": (_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "lb_get_state": (_int, [_vp, _vp, _vp]),
     "lb_set_state": (_int, [_vp, _vp, _vp]),
     "lb_set_tau": (_int, [_vp, ctypes.c_double]),
@@ -184,6 +187,22 @@ def lb_step_record(ctx, nsteps, post):
 def lb_adjoint_step(ctx, f, lam_next, lam_n, domega, f_pending=False):
     _check("lb_adjoint_step", _lib.lb_adjoint_step(ctx, _ptr(f), 1 if f_pending else 0, _ptr(lam_next),
                                                    _ptr(lam_n), _ptr(domega)))
+
+
+def lb_set_params(ctx, params):
+    _check("lb_set_params", _lib.lb_set_params(ctx, ctypes.byref(params)))
+
+
+def lb_adjoint_step_binary(ctx, f, g, lf_next, lg_next, lf_n, lg_n, grads, pending=False):
+    _check("lb_adjoint_step_binary", _lib.lb_adjoint_step_binary(
+        ctx, _ptr(f), _ptr(g), 1 if pending else 0, _ptr(lf_next), _ptr(lg_next), _ptr(lf_n), _ptr(lg_n),
+        _ptr(grads)))
+
+
+def lb_adjoint_init_binary(ctx, rho, u, phi, lf0, lg0, dphi, drho, du, dkappa):
+    _check("lb_adjoint_init_binary", _lib.lb_adjoint_init_binary(
+        ctx, _ptr(rho), _ptr(u), _ptr(phi), _ptr(lf0), _ptr(lg0), _ptr(dphi), _ptr(drho), _ptr(du),
+        _ptr(dkappa)))
 
 
 def lb_mask_index(ctx, mask, index, count):
@@ -365,6 +384,20 @@ class Lattice:
     def set_tau(self, tau_f):
         lb_set_tau(self.ctx, tau_f)
         self.params.tau_f = float(tau_f)
+
+    def set_params(self, **phys):
+        """Change physical parameters (tau_f, A, B, kappa, mobility, gamma,
+        tau_minus) for subsequent calls; the state is kept."""
+        allowed = {"tau_f", "A", "B", "kappa", "mobility", "gamma", "tau_minus"}
+        bad = set(phys) - allowed
+        if bad:
+            raise ValueError("cannot change %s after creation" % ", ".join(sorted(bad)))
+        p = lb_params()
+        ctypes.memmove(ctypes.byref(p), ctypes.byref(self.params), ctypes.sizeof(lb_params))
+        for k, v in phys.items():
+            setattr(p, k, float(v))
+        lb_set_params(self.ctx, p)
+        self.params = p
 
     def close(self):
         if self.ctx is not None:

@@ -1,0 +1,194 @@
+"""Adjoint of the binary-fluid FP64 step on the GPU: the two adjoint kernels
+against the oracle's hand-derived reverse sweep (itself pinned by
+complex-step derivatives), the recorded recompute, the reverse of the
+initialisation, the checkpointed autograd rollout against the oracle's full
+reverse sweep, and central finite differences of the GPU forward."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import lb_oracle as O
+from paper_1405_6162_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def relerr(a, ref):
+    return float(np.abs(np.asarray(a) - ref).max() / np.abs(ref).max())
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+
+
+def _fields(nx, ny, nz, seed, phi_max=0.3):
+    rho, u, phi = inputs.spinodal_quench(nx, ny, nz, seed=seed, phi_max=phi_max)
+    _r, u = inputs.single_fluid_random(nx, ny, nz, seed=seed + 1, u_max=0.02)
+    rho = rho + 0.01 * np.cos(2 * np.pi * np.arange(nx) / nx)
+    return rho, u, phi
+
+
+def _state(nx, ny, nz, seed):
+    """A binary state off equilibrium (one oracle step from the fields)."""
+    prm = O.Params()
+    f, g = O.init_binary(*_fields(nx, ny, nz, seed), prm)
+    return O.step_binary(f, g, prm, 1)
+
+
+def _params(prm):
+    return dict(tau_f=prm.tau_f, A=prm.A, B=prm.B, kappa=prm.kappa, mobility=prm.mobility, gamma=prm.gamma)
+
+
+@pytest.mark.parametrize("nx,ny,nz", [(4, 4, 4), (5, 6, 7), (67, 9, 5), (16, 16, 16)])
+def test_binary_adjoint_step_kernels(lbgpu, nx, ny, nz):
+    print("case binary adjoint step", nx, ny, nz, flush=True)
+    prm = O.Params(tau_f=0.9, kappa=0.05, mobility=0.3)
+    f, g = _state(nx, ny, nz, seed=1)
+    rng = np.random.default_rng(2)
+    lf1, lg1 = rng.standard_normal(f.shape), rng.standard_normal(g.shape)
+    want_f, want_g, want = O.adjoint_step_binary(f, g, lf1, lg1, prm)
+    lat = lbgpu.Lattice(nx, ny, nz, model=lbgpu.LB_BINARY, **_params(prm))
+    lf, lg = torch.empty_like(dev(lf1)), torch.empty_like(dev(lg1))
+    grads = torch.full((3,), 0.5, dtype=torch.float64, device="cuda")     # the call increments it
+    lbgpu.lb_set_stream(lat.ctx, lbgpu._stream())
+    lbgpu.lb_adjoint_step_binary(lat.ctx, dev(f), dev(g), dev(lf1), dev(lg1), lf, lg, grads)
+    assert relerr(lf.cpu().numpy(), want_f) < 1e-12
+    assert relerr(lg.cpu().numpy(), want_g) < 1e-12
+    got = grads.cpu().numpy() - 0.5
+    for k, name in enumerate(("omega_f", "omega_g", "kappa")):
+        assert abs(got[k] - want[name]) <= 1e-12 * max(abs(want[name]), 1.0), name
+
+
+def test_binary_adjoint_from_pending_fields(lbgpu):
+    """pending: f^n and g^n are pulled from the previous step's recorded
+    post-collision fields; same result as giving them directly."""
+    nx, ny, nz = 9, 6, 5
+    prm = O.Params()
+    f, g = _state(nx, ny, nz, seed=3)
+    pf, pg = O.collide_binary(f, g, prm)
+    fn, gn = O.propagate(pf), O.propagate(pg)
+    rng = np.random.default_rng(4)
+    lf1, lg1 = rng.standard_normal(f.shape), rng.standard_normal(g.shape)
+    want_f, want_g, want = O.adjoint_step_binary(fn, gn, lf1, lg1, prm)
+    lat = lbgpu.Lattice(nx, ny, nz, model=lbgpu.LB_BINARY)
+    lf, lg = torch.empty_like(dev(lf1)), torch.empty_like(dev(lg1))
+    grads = torch.zeros(3, dtype=torch.float64, device="cuda")
+    lbgpu.lb_set_stream(lat.ctx, lbgpu._stream())
+    lbgpu.lb_adjoint_step_binary(lat.ctx, dev(pf), dev(pg), dev(lf1), dev(lg1), lf, lg, grads, pending=True)
+    assert relerr(lf.cpu().numpy(), want_f) < 1e-12
+    assert relerr(lg.cpu().numpy(), want_g) < 1e-12
+    got = grads.cpu().numpy()
+    for k, name in enumerate(("omega_f", "omega_g", "kappa")):
+        assert abs(got[k] - want[name]) <= 1e-12 * max(abs(want[name]), 1.0), name
+
+
+@pytest.mark.parametrize("pending_start", [False, True])
+@pytest.mark.parametrize("n", [1, 4])
+def test_binary_step_record(lbgpu, pending_start, n):
+    """lb_step_record (binary) leaves the state of lb_step and records, per
+    step, the post-collision f and g whose propagation is the next state."""
+    nx, ny, nz = 7, 5, 6
+    prm = O.Params()
+    f, g = _state(nx, ny, nz, seed=5)
+    lat = lbgpu.Lattice(nx, ny, nz, model=lbgpu.LB_BINARY)
+    lat.set_state(f, g)
+    if pending_start:
+        lat.step(1)
+        f, g = O.step_binary(f, g, prm, 1)
+    post = torch.empty((n, 38, nz, ny, nx), dtype=torch.float64, device="cuda")
+    lbgpu.lb_set_stream(lat.ctx, lbgpu._stream())
+    lbgpu.lb_step_record(lat.ctx, n, post)
+    p = post.cpu().numpy()
+    for k in range(n):
+        pf, pg = O.collide_binary(f, g, prm)
+        assert relerr(p[k, :19], pf) < 1e-12
+        assert relerr(p[k, 19:], pg) < 1e-12
+        f, g = O.propagate(pf), O.propagate(pg)
+    sf, sg = (a.cpu().numpy() for a in lat.get_state())
+    assert relerr(sf, f) < 1e-12 and relerr(sg, g) < 1e-12
+    lat.step(1)                                      # and the library carries on from there
+    f, g = O.step_binary(f, g, prm, 1)
+    sf, sg = (a.cpu().numpy() for a in lat.get_state())
+    assert relerr(sf, f) < 1e-12 and relerr(sg, g) < 1e-12
+
+
+def test_binary_adjoint_init(lbgpu):
+    nx, ny, nz = 11, 6, 5
+    prm = O.Params(kappa=0.03)
+    rho, u, phi = _fields(nx, ny, nz, seed=6)
+    rng = np.random.default_rng(7)
+    lf0, lg0 = rng.standard_normal((19, nz, ny, nx)), rng.standard_normal((19, nz, ny, nx))
+    want_phi, want_rho, want_u, want_k = O.adjoint_init_binary(rho, u, phi, lf0, lg0, prm)
+    lat = lbgpu.Lattice(nx, ny, nz, model=lbgpu.LB_BINARY, kappa=prm.kappa)
+    dphi, drho, du = (torch.empty(s, dtype=torch.float64, device="cuda")
+                      for s in (phi.shape, rho.shape, u.shape))
+    dk = torch.full((1,), 2.0, dtype=torch.float64, device="cuda")
+    lbgpu.lb_set_stream(lat.ctx, lbgpu._stream())
+    lbgpu.lb_adjoint_init_binary(lat.ctx, dev(rho), dev(u), dev(phi), dev(lf0), dev(lg0), dphi, drho, du, dk)
+    assert relerr(dphi.cpu().numpy(), want_phi) < 1e-12
+    assert relerr(drho.cpu().numpy(), want_rho) < 1e-12
+    assert relerr(du.cpu().numpy(), want_u) < 1e-12
+    assert abs(dk.item() - 2.0 - want_k) <= 1e-12 * max(abs(want_k), 1.0)
+
+
+@pytest.mark.parametrize("T,K", [(6, 4), (5, 1), (5, 5), (7, 3)])
+def test_binary_rollout_gradient_matches_oracle(lbgpu, T, K):
+    """The checkpointed autograd rollout (recompute per segment, recorded
+    post-collision fields) against the oracle's reverse sweep over every
+    stored state: dL/dphi0, dL/drho0, dL/du0 and dL/d(kappa, M, tau_f)."""
+    from paper_1405_6162_amd.adjoint import binary_loss, rollout_binary
+    print("case binary rollout T=%d K=%d" % (T, K), flush=True)
+    nx, ny, nz = 12, 10, 8
+    prm = O.Params(tau_f=0.95, kappa=0.04, mobility=0.45)
+    rho, u, phi = _fields(nx, ny, nz, seed=8)
+    beta = 0.5
+    loss_o, dphi_o, drho_o, du_o, g_o = O.rollout_gradient_binary(rho, u, phi, prm, T, beta)
+    lat = lbgpu.Lattice(nx, ny, nz, model=lbgpu.LB_BINARY, **_params(prm))
+    r0, u0, p0 = (dev(a).requires_grad_(True) for a in (rho, u, phi))
+    params = [torch.tensor(v, dtype=torch.float64, device="cuda", requires_grad=True)
+              for v in (prm.kappa, prm.mobility, prm.tau_f)]
+    fT, gT = rollout_binary(r0, u0, p0, lat, T, K, *params)
+    loss = binary_loss(fT, gT, beta)
+    assert abs(loss.item() - loss_o) <= 1e-12 * abs(loss_o)
+    loss.backward()
+    assert relerr(p0.grad.cpu().numpy(), dphi_o) < 1e-11
+    assert relerr(r0.grad.cpu().numpy(), drho_o) < 1e-11
+    assert relerr(u0.grad.cpu().numpy(), du_o) < 1e-11
+    for t, name in zip(params, ("kappa", "mobility", "tau_f")):
+        assert abs(t.grad.item() - g_o[name]) <= 1e-11 * abs(g_o[name]), name
+
+
+def test_binary_rollout_central_differences_32(lbgpu):
+    """32^3 spinodal quench, 20 steps, checkpoints every 5: gradient against
+    central differences (eps 1e-6) of the GPU forward on sampled phi0
+    components and on kappa and M."""
+    from paper_1405_6162_amd.adjoint import binary_loss, rollout_binary
+    n, T, K, eps = 32, 20, 5, 1e-6
+    prm = O.Params()
+    rho, u, phi = inputs.spinodal_quench(n, n, n, seed=9, phi_max=0.1)
+    lat = lbgpu.Lattice(n, n, n, model=lbgpu.LB_BINARY, **_params(prm))
+    p0 = dev(phi).requires_grad_(True)
+    kap = torch.tensor(prm.kappa, dtype=torch.float64, device="cuda", requires_grad=True)
+    mob = torch.tensor(prm.mobility, dtype=torch.float64, device="cuda", requires_grad=True)
+    loss = binary_loss(*rollout_binary(dev(rho), dev(u), p0, lat, T, K, kap, mob), 1.0)
+    loss.backward()
+    grad = p0.grad.cpu().numpy()
+    gk, gm = kap.grad.item(), mob.grad.item()
+
+    def L(ph, kappa=prm.kappa, mobility=prm.mobility):
+        with torch.no_grad():
+            f, g = rollout_binary(dev(rho), dev(u), dev(ph), lat, T, K, kappa, mobility)
+            return binary_loss(f, g, 1.0).item()
+    floor = 1e-3 * np.abs(grad).max()
+    for (_i, s) in inputs.sample_components(n ** 3, 5, seed=10):
+        idx = np.unravel_index(s, phi.shape)
+        pp, pm = phi.copy(), phi.copy()
+        pp[idx] += eps
+        pm[idx] -= eps
+        fd = (L(pp) - L(pm)) / (2 * eps)
+        assert abs(fd - grad[idx]) <= 1e-6 * max(abs(grad[idx]), floor), (fd, grad[idx])
+    fd_k = (L(phi, kappa=prm.kappa + eps) - L(phi, kappa=prm.kappa - eps)) / (2 * eps)
+    fd_m = (L(phi, mobility=prm.mobility + eps) - L(phi, mobility=prm.mobility - eps)) / (2 * eps)
+    assert abs(fd_k - gk) <= 1e-6 * abs(gk), (fd_k, gk)
+    assert abs(fd_m - gm) <= 1e-6 * abs(gm), (fd_m, gm)

@@ -1,0 +1,160 @@
+"""Host logic of the differentiable rollouts (checkpoints every K steps,
+segment recompute with recorded post-collision fields, reverse walk, the
+reverse of the initialisation), checked on the CPU: the library calls that
+paper_1405_6162_amd.adjoint makes are replaced, inside this test only, by
+stand-ins built from the oracle, and the gradients must equal the oracle's
+plain reverse sweep over every stored state.  The GPU kernels themselves
+are covered by the gpu-marked tests."""
+
+import types
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import lb_oracle as O
+from paper_1405_6162_amd import adjoint, inputs, lb
+
+
+class _Lattice:
+    """Oracle-backed stand-in for lb.Lattice (FP64, CPU tensors)."""
+
+    def __init__(self, model, prm):
+        self.model, self.storage = model, lb.LB_F64
+        self.prm = prm
+        self.params = types.SimpleNamespace(kappa=prm.kappa, mobility=prm.mobility, tau_f=prm.tau_f,
+                                            gamma=prm.gamma)
+        self.ctx = self
+        self.f = self.g = None
+        self.calls = {"record": 0, "adjoint": 0}
+
+    def set_params(self, **kw):
+        for k, v in kw.items():
+            setattr(self.prm, k, float(v))
+            setattr(self.params, k, float(v))
+
+    def set_tau(self, tau):
+        self.set_params(tau_f=tau)
+
+    def init_equilibrium(self, rho, u, phi=None):
+        a = [t.numpy() for t in (rho, u)]
+        if self.model == lb.LB_BINARY:
+            self.f, self.g = O.init_binary(*a, phi.numpy(), self.prm)
+        else:
+            self.f = O.init_single(*a)
+
+    def _step(self):
+        if self.model == lb.LB_BINARY:
+            self.f, self.g = O.step_binary(self.f, self.g, self.prm, 1)
+        else:
+            self.f = O.step_single(self.f, self.prm.tau_f, 1)
+
+    def step(self, n=1):
+        for _ in range(n):
+            self._step()
+
+    def get_state(self):
+        t = lambda a: torch.from_numpy(a.copy()) if a is not None else None
+        return (t(self.f), t(self.g)) if self.model == lb.LB_BINARY else (t(self.f), None)
+
+    def set_state(self, f, g=None):
+        self.f = f.detach().numpy().copy()
+        self.g = g.detach().numpy().copy() if g is not None else None
+
+
+def _record(ctx, n, post):
+    ctx.calls["record"] += 1
+    for k in range(n):
+        if ctx.model == lb.LB_BINARY:
+            pf, pg = O.collide_binary(ctx.f, ctx.g, ctx.prm)
+            post[k, :19] = torch.from_numpy(pf)
+            post[k, 19:] = torch.from_numpy(pg)
+            ctx.f, ctx.g = O.propagate(pf), O.propagate(pg)
+        else:
+            pf = O.collide_single(ctx.f, ctx.prm.tau_f)
+            post[k] = torch.from_numpy(pf)
+            ctx.f = O.propagate(pf)
+
+
+def _adjoint_binary(ctx, f, g, lf, lg, lf_n, lg_n, grads, pending=False):
+    ctx.calls["adjoint"] += 1
+    fn, gn = f.numpy(), g.numpy()
+    if pending:
+        fn, gn = O.propagate(fn), O.propagate(gn)
+    a, b, gr = O.adjoint_step_binary(fn, gn, lf.numpy(), lg.numpy(), ctx.prm)
+    lf_n.copy_(torch.from_numpy(a))
+    lg_n.copy_(torch.from_numpy(b))
+    grads += torch.tensor([gr["omega_f"], gr["omega_g"], gr["kappa"]], dtype=torch.float64)
+
+
+def _adjoint_init_binary(ctx, rho, u, phi, lf, lg, dphi, drho, du, dkappa):
+    p, r, v, k = O.adjoint_init_binary(rho.numpy(), u.numpy(), phi.numpy(), lf.numpy(), lg.numpy(), ctx.prm)
+    dphi.copy_(torch.from_numpy(p))
+    drho.copy_(torch.from_numpy(r))
+    du.copy_(torch.from_numpy(v))
+    dkappa += k
+
+
+def _adjoint_single(ctx, f, lam, lam_n, domega, f_pending=False):
+    ctx.calls["adjoint"] += 1
+    fn = O.propagate(f.numpy()) if f_pending else f.numpy()
+    a, dw = O.adjoint_step_single(fn, lam.numpy(), ctx.prm.tau_f)
+    lam_n.copy_(torch.from_numpy(a))
+    domega += dw
+
+
+@pytest.fixture
+def fake_lib(monkeypatch):
+    monkeypatch.setattr(lb, "_stream", lambda: None)
+    monkeypatch.setattr(lb, "lb_set_stream", lambda ctx, s: None)
+    monkeypatch.setattr(lb, "lb_step_record", _record)
+    monkeypatch.setattr(lb, "lb_adjoint_step_binary", _adjoint_binary)
+    monkeypatch.setattr(lb, "lb_adjoint_init_binary", _adjoint_init_binary)
+    monkeypatch.setattr(lb, "lb_adjoint_step", _adjoint_single)
+
+
+@pytest.mark.parametrize("T,K", [(0, 3), (1, 1), (5, 1), (5, 5), (5, 8), (7, 3), (6, 2)])
+def test_binary_rollout_checkpoint_logic(fake_lib, T, K):
+    nx, ny, nz = 4, 3, 5
+    rho, u, phi = inputs.spinodal_quench(nx, ny, nz, seed=3, phi_max=0.3)
+    _r, u = inputs.single_fluid_random(nx, ny, nz, seed=4, u_max=0.02)
+    prm = O.Params(tau_f=0.9, kappa=0.05, mobility=0.4)
+    loss_o, dphi_o, drho_o, du_o, g_o = O.rollout_gradient_binary(rho, u, phi, O.Params(**vars(prm)), T, 0.5)
+    lat = _Lattice(lb.LB_BINARY, O.Params())
+    r0, u0, p0 = (torch.from_numpy(a.copy()).requires_grad_(True) for a in (rho, u, phi))
+    params = [torch.tensor(v, dtype=torch.float64, requires_grad=True)
+              for v in (prm.kappa, prm.mobility, prm.tau_f)]
+    fT, gT = adjoint.rollout_binary(r0, u0, p0, lat, T, K, *params)
+    loss = adjoint.binary_loss(fT, gT, 0.5)
+    assert abs(loss.item() - loss_o) <= 1e-14 * abs(loss_o)
+    loss.backward()
+    assert lat.calls["adjoint"] == T                       # one adjoint step per step
+    assert lat.calls["record"] == sum(1 for s in range(0, T, K) if min(K, T - s) > 1)
+    scale = max(np.abs(a).max() for a in (dphi_o, drho_o, du_o))     # dL/drho0 vanishes at T = 0
+    np.testing.assert_allclose(p0.grad.numpy(), dphi_o, rtol=0, atol=1e-13 * scale)
+    np.testing.assert_allclose(r0.grad.numpy(), drho_o, rtol=0, atol=1e-13 * scale)
+    np.testing.assert_allclose(u0.grad.numpy(), du_o, rtol=0, atol=1e-13 * scale)
+    for t, name in zip(params, ("kappa", "mobility", "tau_f")):
+        if T == 0:          # the initial moments are the inputs: no parameter enters the loss
+            assert abs(t.grad.item()) <= 1e-15 and abs(g_o[name]) <= 1e-15
+            continue
+        assert abs(t.grad.item() - g_o[name]) <= 1e-12 * abs(g_o[name]), name
+
+
+@pytest.mark.parametrize("T,K", [(0, 2), (1, 1), (6, 1), (6, 6), (6, 9), (7, 3)])
+def test_single_rollout_checkpoint_logic(fake_lib, T, K):
+    nx, ny, nz = 5, 4, 3
+    rho, u = inputs.shear_wave(nx, ny, nz, amplitude=0.01, noise=1e-3, seed=13)
+    f0 = O.init_single(rho, u)
+    tau = 0.8
+    loss_o, g_o, dtau_o = O.rollout_gradient(f0, tau, T)
+    lat = _Lattice(lb.LB_SINGLE, O.Params(tau_f=tau))
+    f = torch.from_numpy(f0.copy()).requires_grad_(True)
+    t = torch.tensor(tau, dtype=torch.float64, requires_grad=True)
+    loss = adjoint.velocity_loss(adjoint.rollout(f, t, lat, T, K))
+    assert abs(loss.item() - loss_o) <= 1e-14 * abs(loss_o)
+    loss.backward()
+    assert lat.calls["adjoint"] == T
+    np.testing.assert_allclose(f.grad.numpy(), g_o, rtol=0, atol=1e-13 * np.abs(g_o).max())
+    if T > 0:
+        assert abs(t.grad.item() - dtau_o) <= 1e-12 * abs(dtau_o)
