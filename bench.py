@@ -38,6 +38,12 @@ WORKLOADS = {
                                             "+ adjoint with checkpoints every 20 steps"),
     "adjoint128_f64": ("adjoint", "f64", 128, "D3Q19 single-fluid BGK 128^3 shear wave, FP64, 200-step rollout "
                                               "+ adjoint with checkpoints every 20 steps"),
+    "adjoint_binary64_f64": ("adjoint_binary", "f64", 64, "D3Q19 binary fluid 64^3 spinodal quench, FP64, "
+                             "200-step rollout + adjoint (gradients w.r.t. phi0, rho0, u0, kappa, M, tau_f) "
+                             "with checkpoints every 20 steps"),
+    "adjoint_binary128_f64": ("adjoint_binary", "f64", 128, "D3Q19 binary fluid 128^3 spinodal quench, FP64, "
+                              "200-step rollout + adjoint (gradients w.r.t. phi0, rho0, u0, kappa, M, tau_f) "
+                              "with checkpoints every 20 steps"),
     "precision256_f32": ("precision", "f32", 256, "D3Q19 binary fluid 256^3 spinodal quench, 500 steps: FP32 "
                                                   "deviation storage against FP64"),
     "precision384_f16": ("precision", "f16", 384, "D3Q19 binary fluid 384^3 spinodal quench, 1000 steps: FP16 "
@@ -63,6 +69,9 @@ def algorithmic_bytes(model, storage):
         return {"collide": 2 * 19 * es}
     if model == "adjoint":
         return {"collide": 2 * 19 * es, "adjoint": 3 * 19 * es}
+    if model == "adjoint_binary":
+        # reads f^n, g^n, lambda_f^{n+1}, lambda_g^{n+1}; writes lambda_f^n, lambda_g^n
+        return {"collide": 2 * 38 * es, "adjoint": 6 * 19 * es}
     return {"collide": 2 * 38 * es}
 
 
@@ -176,6 +185,70 @@ def bench_adjoint(args, n, desc, T=200, K=20):
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(args.workload),
                      "bytes_per_site": alg["adjoint"], "avg_launch_ms": round(avg, 5), "launches": adj_n},
+    }
+    if not args.no_copy:
+        out["copy_probe"] = copy_probe(torch)
+    print(json.dumps(out), flush=True)
+
+
+def bench_adjoint_binary(args, n, desc, T=200, K=20):
+    """Binary fluid: forward rollout from the spinodal fields + backward
+    (recorded recompute, the three adjoint kernels per step, the reverse of
+    the initialisation) per timed iteration; a step is one forward step plus
+    one adjoint step."""
+    import torch
+    from paper_1405_6162_amd import inputs, lb
+    from paper_1405_6162_amd.adjoint import binary_loss, rollout_binary
+    log("bench: %s" % desc)
+    rho, u, phi = (torch.as_tensor(a, device="cuda") for a in inputs.spinodal_quench(n, n, n, seed=0))
+    lat = lb.Lattice(n, n, n, model=lb.LB_BINARY)
+    par = lambda v: torch.tensor(v, dtype=torch.float64, device="cuda", requires_grad=True)
+
+    def once():
+        p0 = phi.clone().requires_grad_(True)
+        kap, mob, tau = par(0.04), par(0.45), par(1.0)
+        loss = binary_loss(*rollout_binary(rho, u, p0, lat, T, K, kap, mob, tau), 1.0)
+        loss.backward()
+        return p0.grad, torch.stack([kap.grad, mob.grad, tau.grad])
+
+    for _ in range(max(args.warmup // 10, 1)):
+        once()
+    torch.cuda.synchronize()
+    iters = max(args.steps // 100, 1)
+    lb.lb_profile(lat.ctx, True)
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        gphi, gpar = once()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lb.lb_profile(lat.ctx, False)
+    adj_ms, adj_n = lb.lb_kernel_times(lat.ctx, lb.LB_K_ADJOINT)
+    finite = bool(torch.isfinite(gphi).all()) and bool(torch.isfinite(gpar).all())
+    lat.close()
+    if not finite:
+        print("non-finite gradient", file=sys.stderr)
+        sys.exit(1)
+    nsite = n ** 3
+    alg = algorithmic_bytes("adjoint_binary", "f64")
+    # each adjoint step is three launches (phi, local transpose, stencil
+    # transpose) plus one launch per rollout for the reverse initialisation
+    per_step_ms = adj_ms / (iters * T) if adj_n else 0.0
+    achieved = alg["adjoint"] * nsite / (per_step_ms * 1e-3) / 1e9 if per_step_ms else 0.0
+    out = {
+        "metric": METRIC, "value": round(nsite * T * iters / wall / 1e6, 2), "unit": "MLUPS",
+        "n_gpus": 1, "steps": T * iters, "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / (T * iters), 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": desc, "nx": n, "ny": n, "nz": n, "rollout_steps": T, "checkpoint_every": K,
+                   "seed": 0},
+        "roofline": {"bound": "hbm",
+                     "kernel": "adjoint step: k_phi + k_adjoint_binary + k_adjoint_binary_stencil",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_site": alg["adjoint"], "bytes_per_site_moved": 1312,
+                     "avg_step_ms": round(per_step_ms, 5), "launches": adj_n},
+        "gradients": {"kappa": float(gpar[0]), "mobility": float(gpar[1]), "tau_f": float(gpar[2]),
+                      "max_abs_dphi0": float(gphi.abs().max())},
     }
     if not args.no_copy:
         out["copy_probe"] = copy_probe(torch)
@@ -366,6 +439,8 @@ def main():
     torch.cuda.set_device(0)
     if model == "adjoint":
         return bench_adjoint(args, n, desc)
+    if model == "adjoint_binary":
+        return bench_adjoint_binary(args, n, desc)
     if model == "precision":
         return bench_precision(args, storage, n, desc)
     if model == "precision_single":

@@ -169,10 +169,13 @@ int lb_set_tau(lb_ctx* ctx, double tau_f);
  * layout, storage dtype.  LB_SINGLE: step k (0-based) writes
  * post[k*19*N + i*N + s] (nsteps*19*N elements).  LB_BINARY: step k writes f*
  * at post[k*38*N + i*N + s] and g* at post[k*38*N + 19*N + i*N + s]
- * (nsteps*38*N elements).  The state afterwards equals that after
- * lb_step(nsteps).  Used by the adjoints' segment recompute: post[k] holds
- * the state of step k+1 in pending (pull) form.  nsteps == 0 is a no-op. */
-int lb_step_record(lb_ctx* ctx, int32_t nsteps, void* post);
+ * (nsteps*38*N elements); if phi is not NULL, phi[k*N + s] also receives the
+ * order parameter of the state step k collides (compute dtype: double for
+ * LB_F64, float otherwise).  phi must be NULL for LB_SINGLE.  The state
+ * afterwards equals that after lb_step(nsteps).  Used by the adjoints'
+ * segment recompute: post[k] holds the state of step k+1 in pending (pull)
+ * form.  nsteps == 0 is a no-op. */
+int lb_step_record(lb_ctx* ctx, int32_t nsteps, void* post, void* phi);
 
 /* Adjoint (reverse) of one single-fluid BGK step f^{n+1} = propagate(collide(f^n)),
  * LB_SINGLE + LB_F64 only.  f (19*N, canonical FP64) is f^n itself when
@@ -199,15 +202,17 @@ int lb_set_params(lb_ctx* ctx, const lb_params* p);
  * propagate.  f, g (19*N each, canonical FP64) are f^n and g^n when
  * pending == 0, or the recorded post-collision fields of step n-1 (as written
  * by lb_step_record) when pending != 0, in which case f^n_i(s) = f_i(s - c_i).
+ * phi_n[N] = sum_i g^n_i (as lb_step_record writes it for step n), or NULL to
+ * have it computed from g.
  * lf_next, lg_next = dL/df^{n+1}, dL/dg^{n+1}; lf_n, lg_n receive dL/df^n and
  * dL/dg^n (must not alias the inputs or each other).  grads (3 device
  * doubles) is INCREMENTED by dL/d(1/tau_f), dL/d(1/tau_g) and dL/dkappa of
  * this step (tau_g = mobility/gamma + 1/2).  Uses the context's parameters;
  * uses the context's spare state buffer and phi buffer as scratch, so calls
  * on one context must not overlap; the lattice state itself is unchanged. */
-int lb_adjoint_step_binary(lb_ctx* ctx, const double* f, const double* g, int pending,
-                           const double* lf_next, const double* lg_next, double* lf_n,
-                           double* lg_n, double* grads);
+int lb_adjoint_step_binary(lb_ctx* ctx, const double* f, const double* g, const double* phi_n,
+                           int pending, const double* lf_next, const double* lg_next,
+                           double* lf_n, double* lg_n, double* grads);
 
 /* Reverse of lb_init_equilibrium for LB_BINARY + LB_F64: given rho[N],
  * u[3*N], phi[N] (the initial fields, as passed to lb_init_equilibrium) and
@@ -242,7 +247,7 @@ int lb_set_sites(lb_ctx* ctx, const int32_t* index, int64_t m, const void* f_pac
 #define LB_K_COLLIDE  0   /* collide / fused pull-stream + collide */
 #define LB_K_PHI      1   /* order-parameter kernel (binary) */
 #define LB_K_STREAM   2   /* stand-alone propagation */
-#define LB_K_ADJOINT  3   /* adjoint step */
+#define LB_K_ADJOINT  3   /* adjoint step (binary: its phi, local and stencil kernels) */
 #define LB_K_OTHER    4   /* init, moments, sums, copies */
 int lb_profile(lb_ctx* ctx, int enable);
 int lb_kernel_times(lb_ctx* ctx, int kind, double* total_ms, int64_t* launches);

@@ -144,21 +144,25 @@ class LBBinaryRollout(torch.autograd.Function):
                 continue
             f_ck, g_ck = ctx.ckpts[seg]
             lat.set_state(f_ck, g_ck)
-            post = None
+            post = phi = None
             if length > 1:
+                # post[k] and phi[k] (phi of the state step k collides) for k < length - 1;
+                # the last step's phi is computed by the adjoint call itself
                 post = torch.empty((length - 1, 2 * lb.Q) + tuple(shape[1:]), dtype=torch.float64, device=dev)
+                phi = torch.empty((length - 1,) + tuple(shape[1:]), dtype=torch.float64, device=dev)
                 lb.lb_set_stream(lat.ctx, lb._stream())
-                lb.lb_step_record(lat.ctx, length - 1, post)
+                lb.lb_step_record(lat.ctx, length - 1, post, phi)
             for n in range(length - 1, -1, -1):
                 lf_n, lg_n = torch.empty_like(lf), torch.empty_like(lg)
+                phi_n = phi[n] if phi is not None and n < length - 1 else None
                 lb.lb_set_stream(lat.ctx, lb._stream())
                 if n == 0:
-                    lb.lb_adjoint_step_binary(lat.ctx, f_ck, g_ck, lf, lg, lf_n, lg_n, grads)
+                    lb.lb_adjoint_step_binary(lat.ctx, f_ck, g_ck, lf, lg, lf_n, lg_n, grads, phi=phi_n)
                 else:
                     lb.lb_adjoint_step_binary(lat.ctx, post[n - 1, :lb.Q], post[n - 1, lb.Q:], lf, lg, lf_n, lg_n,
-                                              grads, pending=True)
+                                              grads, pending=True, phi=phi_n)
                 lf, lg = lf_n, lg_n
-            del post
+            del post, phi
         rho0, u0, phi0 = ctx.fields
         dphi, drho, du = torch.empty_like(phi0), torch.empty_like(rho0), torch.empty_like(u0)
         dkappa0 = torch.zeros(1, dtype=torch.float64, device=dev)

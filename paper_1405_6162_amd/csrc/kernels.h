@@ -336,10 +336,13 @@ __device__ __forceinline__ T phi_of_gathered(const S* g, const Site& st, const G
 // phi planes kept in LDS: with 3 a second barrier per plane keeps the write of
 // plane z+2 from overtaking the reads of plane z-1; with 4 the slot written
 // next is never one still being read, so one barrier per plane suffices.
-template <class P, int BZ, class S, bool GLDS, int RING = 3>
+// With PHI_OUT the kernel also stores the phi it computes for its own sites
+// (phi_out[s], canonical), i.e. phi of the state this step collides.
+template <class P, int BZ, class S, bool GLDS, int RING = 3, bool PHI_OUT = false>
 __global__ __launch_bounds__(P::TPB) void k_binary_march(const S* __restrict__ fsrc, const S* __restrict__ gsrc,
                                                          S* __restrict__ fdst, S* __restrict__ gdst, Geo geo,
-                                                         CollParams<typename Compute<S>::T> cp) {
+                                                         CollParams<typename Compute<S>::T> cp,
+                                                         typename Compute<S>::T* __restrict__ phi_out = nullptr) {
     using T = typename Compute<S>::T;
     constexpr int TX = P::TX, TY = P::TY, LX = TX + 2, LY = TY + 2;
     constexpr int NHALO = 2 * TX + 2 * TY;
@@ -387,6 +390,8 @@ __global__ __launch_bounds__(P::TPB) void k_binary_march(const S* __restrict__ f
         const Site s0 = site_wrapped(xw, yw, z0, geo);
         load_site<P, true>(gsrc, s0, geo, gc);
         ring[slot(z0)][ly][lx] = phi_sum<typename Accum<S>::T>(gc, cp.phi0);
+        if constexpr (PHI_OUT)
+            if (active) phi_out[offset_at<0, 0, 0>(s0, geo)] = ring[slot(z0)][ly][lx];
         if constexpr (GLDS) {
 #pragma unroll
             for (int i = 0; i < Q; ++i) gkeep[i][threadIdx.x] = gc[i];
@@ -403,6 +408,9 @@ __global__ __launch_bounds__(P::TPB) void k_binary_march(const S* __restrict__ f
         T gn[Q];
         load_site<P, true>(gsrc, site_wrapped(xw, yw, zn, geo), geo, gn);
         ring[slot(z + 1)][ly][lx] = phi_sum<typename Accum<S>::T>(gn, cp.phi0);
+        if constexpr (PHI_OUT)
+            if (active && z + 1 < z1) phi_out[offset_at<0, 0, 0>(site_wrapped(xw, yw, zn, geo), geo)] =
+                ring[slot(z + 1)][ly][lx];
         if (has_halo)
             ring[slot(z + 1)][hly][hlx] = phi_of_gathered<P>(gsrc, site_wrapped(hx, hy, zn, geo), geo, cp.phi0);
         if constexpr (GLDS) {
@@ -593,10 +601,9 @@ __global__ __launch_bounds__(P::TPB) void k_sums_partial(const S* __restrict__ f
 }
 
 // out[k] = base[k] + sum_b partial[8 b + k], k < K; one block of P::TPB threads.
-template <class P, int K>
-__global__ __launch_bounds__(P::TPB) void k_sums_final(const double* __restrict__ partial, int nblocks, double* out,
-                                                       double base0, double base4, int accumulate) {
-    constexpr int TPB = P::TPB;
+template <int TPB, int K>
+__device__ __forceinline__ void final_sums(const double* __restrict__ partial, int nblocks, double* out,
+                                           double base0, double base4, int accumulate) {
     __shared__ double sh[K][TPB];
     const int t = threadIdx.x;
     double v[K];
@@ -615,6 +622,12 @@ __global__ __launch_bounds__(P::TPB) void k_sums_final(const double* __restrict_
             out[k] = accumulate ? out[k] + r : r;
         }
     }
+}
+
+template <class P, int K>
+__global__ __launch_bounds__(P::TPB) void k_sums_final(const double* __restrict__ partial, int nblocks, double* out,
+                                                       double base0, double base4, int accumulate) {
+    final_sums<P::TPB, K>(partial, nblocks, out, base0, base4, accumulate);
 }
 
 // ---------------------------------------------------------------------------
@@ -786,53 +799,80 @@ struct BinAdj {
     double dkappa;               // sensitivity to kappa at fixed phi, G, lap
 };
 
+// Running weighted sums of one distribution's post-collision adjoints l_i:
+// L = sum l w, S = sum l w E, X = sum l w (|c|^2 - 1) (times 9/2 later),
+// t_a = sum l w c_a (3 + 9 c.u) and y_a = sum l w c_a (c.G).
+// (y only for f: g^eq does not depend on grad phi.)
+template <bool WITH_Y>
+struct BinSums {
+    double L = 0.0, S = 0.0, X = 0.0, t[3] = {0.0, 0.0, 0.0}, y[3] = {0.0, 0.0, 0.0};
+    template <int i>
+    __device__ __forceinline__ void add(double l, double cu, double E, double cG) {
+        const double a = l * weight<double>(i);
+        L = L + a;
+        S = S + a * E;
+        if constexpr (csq(i) == 0) X = X - a;
+        if constexpr (csq(i) == 2) X = X + a;
+        const double h = a * (3.0 + 9.0 * cu);
+        if constexpr (cx(i) > 0) t[0] = t[0] + h;
+        if constexpr (cx(i) < 0) t[0] = t[0] - h;
+        if constexpr (cy(i) > 0) t[1] = t[1] + h;
+        if constexpr (cy(i) < 0) t[1] = t[1] - h;
+        if constexpr (cz(i) > 0) t[2] = t[2] + h;
+        if constexpr (cz(i) < 0) t[2] = t[2] - h;
+        if constexpr (WITH_Y) {
+            const double yy = a * cG;
+            if constexpr (cx(i) > 0) y[0] = y[0] + yy;
+            if constexpr (cx(i) < 0) y[0] = y[0] - yy;
+            if constexpr (cy(i) > 0) y[1] = y[1] + yy;
+            if constexpr (cy(i) < 0) y[1] = y[1] - yy;
+            if constexpr (cz(i) > 0) y[2] = y[2] + yy;
+            if constexpr (cz(i) < 0) y[2] = y[2] - yy;
+        }
+    }
+};
+
+__device__ __forceinline__ BinAdj binary_adjoint_finish(const BinSums<true>& fs, const BinSums<false>& gs, double ux,
+                                                        double uy,
+                                                        double uz, double phi, double Gx, double Gy, double Gz,
+                                                        double lap, const CollParams<double>& cp, double omega_f,
+                                                        double omega_g) {
+    const double Xf = 4.5 * fs.X, Xg = 4.5 * gs.X;
+    const double u[3] = {ux, uy, uz}, G[3] = {Gx, Gy, Gz};
+    const double k = cp.kappa;
+    const double GG = Gx * Gx + Gy * Gy + Gz * Gz;
+    BinAdj r;
+    r.Sf = fs.S;
+    for (int a = 0; a < 3; ++a) {
+        r.Tf[a] = fs.t[a] - 3.0 * u[a] * fs.L;
+        r.Tg[a] = gs.t[a] - 3.0 * u[a] * gs.L;
+        r.a_G[a] = omega_f * k * (9.0 * (fs.y[a] - fs.L * G[a] / 3.0) - Xf * G[a]);
+    }
+    const double diso = cp.A * phi + 3.0 * cp.B * phi * phi * phi - k * lap;
+    const double dmu = cp.A + 3.0 * cp.B * phi * phi;
+    r.a_phi = omega_f * Xf * diso + omega_g * (gs.S + Xg * (cp.gamma * dmu - 1.0 / 3.0));
+    r.a_lap = -k * (omega_f * phi * Xf + omega_g * cp.gamma * Xg);
+    const double GYG = Gx * fs.y[0] + Gy * fs.y[1] + Gz * fs.y[2];
+    r.dkappa = omega_f * (4.5 * (GYG - fs.L * GG / 3.0) + Xf * (-phi * lap - 0.5 * GG))
+               + omega_g * cp.gamma * Xg * (-lap);
+    return r;
+}
+
 __device__ __forceinline__ BinAdj binary_adjoint_site(const double (&lf)[Q], const double (&lg)[Q], double ux,
                                                       double uy, double uz, double phi, double Gx, double Gy,
                                                       double Gz, double lap, const CollParams<double>& cp,
                                                       double omega_f, double omega_g) {
     const double usq = ux * ux + uy * uy + uz * uz;
-    double Lf = 0.0, Lg = 0.0, Sf = 0.0, Sg = 0.0, Xf = 0.0, Xg = 0.0;
-    double tf[3] = {0.0, 0.0, 0.0}, tg[3] = {0.0, 0.0, 0.0}, yg[3] = {0.0, 0.0, 0.0};
+    BinSums<true> fs;
+    BinSums<false> gs;
     static_for<0, Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         const double cu = cdot<i>(ux, uy, uz);
-        const double cG = cdot<i>(Gx, Gy, Gz);
         const double E = 1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq;
-        const double a = lf[i] * weight<double>(i), b = lg[i] * weight<double>(i);
-        Lf = Lf + a;
-        Lg = Lg + b;
-        Sf = Sf + a * E;
-        Sg = Sg + b * E;
-        if constexpr (csq(i) == 0) { Xf = Xf - a; Xg = Xg - b; }
-        if constexpr (csq(i) == 2) { Xf = Xf + a; Xg = Xg + b; }
-        const double hf = a * (3.0 + 9.0 * cu), hg = b * (3.0 + 9.0 * cu), y = a * cG;
-        if constexpr (cx(i) > 0) { tf[0] = tf[0] + hf; tg[0] = tg[0] + hg; yg[0] = yg[0] + y; }
-        if constexpr (cx(i) < 0) { tf[0] = tf[0] - hf; tg[0] = tg[0] - hg; yg[0] = yg[0] - y; }
-        if constexpr (cy(i) > 0) { tf[1] = tf[1] + hf; tg[1] = tg[1] + hg; yg[1] = yg[1] + y; }
-        if constexpr (cy(i) < 0) { tf[1] = tf[1] - hf; tg[1] = tg[1] - hg; yg[1] = yg[1] - y; }
-        if constexpr (cz(i) > 0) { tf[2] = tf[2] + hf; tg[2] = tg[2] + hg; yg[2] = yg[2] + y; }
-        if constexpr (cz(i) < 0) { tf[2] = tf[2] - hf; tg[2] = tg[2] - hg; yg[2] = yg[2] - y; }
+        fs.template add<i>(lf[i], cu, E, cdot<i>(Gx, Gy, Gz));
+        gs.template add<i>(lg[i], cu, E, 0.0);
     });
-    Xf = 4.5 * Xf;
-    Xg = 4.5 * Xg;
-    const double u[3] = {ux, uy, uz}, G[3] = {Gx, Gy, Gz};
-    const double k = cp.kappa;
-    const double GG = Gx * Gx + Gy * Gy + Gz * Gz;
-    BinAdj r;
-    r.Sf = Sf;
-    for (int a = 0; a < 3; ++a) {
-        r.Tf[a] = tf[a] - 3.0 * u[a] * Lf;
-        r.Tg[a] = tg[a] - 3.0 * u[a] * Lg;
-        r.a_G[a] = omega_f * k * (9.0 * (yg[a] - Lf * G[a] / 3.0) - Xf * G[a]);
-    }
-    const double diso = cp.A * phi + 3.0 * cp.B * phi * phi * phi - k * lap;
-    const double dmu = cp.A + 3.0 * cp.B * phi * phi;
-    r.a_phi = omega_f * Xf * diso + omega_g * (Sg + Xg * (cp.gamma * dmu - 1.0 / 3.0));
-    r.a_lap = -k * (omega_f * phi * Xf + omega_g * cp.gamma * Xg);
-    const double GYG = Gx * yg[0] + Gy * yg[1] + Gz * yg[2];
-    r.dkappa = omega_f * (4.5 * (GYG - Lf * GG / 3.0) + Xf * (-phi * lap - 0.5 * GG))
-               + omega_g * cp.gamma * Xg * (-lap);
-    return r;
+    return binary_adjoint_finish(fs, gs, ux, uy, uz, phi, Gx, Gy, Gz, lap, cp, omega_f, omega_g);
 }
 
 // phi and its central-difference gradient and Laplacian at a site, from a
@@ -854,7 +894,9 @@ __device__ __forceinline__ void phi_stencil(const double* __restrict__ phi, cons
 // F_PENDING, pulled); phi: phi^n (canonical); lf_next, lg_next: lambda^{n+1}.
 // Writes lambda_f^n and the five sensitivity fields afield[k*N + s]
 // (a_phi, a_Gx, a_Gy, a_Gz, a_lap); block partials of dL/domega_f,
-// dL/domega_g and dL/dkappa go to partial[8 b + 0..2].
+// dL/domega_g and dL/dkappa go to partial[8 b + 0..2].  Only lambda_f stays
+// in registers: f is reduced to its moments (and sum lambda_f f) as it
+// loads, and g with lambda_g are consumed in one pass once u is known.
 template <class P, bool F_PENDING>
 __global__ __launch_bounds__(P::TPB) void k_adjoint_binary(const double* __restrict__ fn,
                                                            const double* __restrict__ gn,
@@ -865,53 +907,73 @@ __global__ __launch_bounds__(P::TPB) void k_adjoint_binary(const double* __restr
                                                            double* __restrict__ partial, Geo geo,
                                                            CollParams<double> cp) {
     __shared__ double sh[3][P::TPB];
+    __shared__ double lf[Q][P::TPB];         // this lane's lambda_f waits here (own slots only: no barrier)
+    const int t = threadIdx.x;
     const Column col = column_of_thread<P>(geo);
     double acc[3] = {0.0, 0.0, 0.0};
     for (int v = 0; v < P::TZ; ++v) {
         const Site st = site_at(col, v, geo);
         if (!st.active) continue;
         const uint32_t off = offset_at<0, 0, 0>(st, geo);
-        double f[Q], g[Q], lf[Q], lg[Q];
+        // f: moments and sum lambda_f f; lambda_f kept
+        double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0, lff = 0.0;
         static_for<0, Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            f[i] = *at(fn + i * geo.dstride, src_offset<i, F_PENDING>(st, geo));
-            g[i] = *at(gn + i * geo.dstride, src_offset<i, F_PENDING>(st, geo));
-            lf[i] = *at(lf_next + i * geo.dstride, offset_at<cx(i), cy(i), cz(i)>(st, geo));
-            lg[i] = *at(lg_next + i * geo.dstride, offset_at<cx(i), cy(i), cz(i)>(st, geo));
+            const double fi = *at(fn + i * geo.dstride, src_offset<i, F_PENDING>(st, geo));
+            const double li = *at(lf_next + i * geo.dstride, offset_at<cx(i), cy(i), cz(i)>(st, geo));
+            lf[i][t] = li;
+            rho = rho + fi;
+            if constexpr (cx(i) > 0) jx = jx + fi;
+            if constexpr (cx(i) < 0) jx = jx - fi;
+            if constexpr (cy(i) > 0) jy = jy + fi;
+            if constexpr (cy(i) < 0) jy = jy - fi;
+            if constexpr (cz(i) > 0) jz = jz + fi;
+            if constexpr (cz(i) < 0) jz = jz - fi;
+            lff = lff + li * fi;
         });
+        const double ux = jx / rho, uy = jy / rho, uz = jz / rho;
+        const double usq = ux * ux + uy * uy + uz * uz;
         double p, Gx, Gy, Gz, lap;
         phi_stencil(phi, st, geo, p, Gx, Gy, Gz, lap);
-        double rho, jx, jy, jz;
-        moments_of(f, rho, jx, jy, jz);
-        const double ux = jx / rho, uy = jy / rho, uz = jz / rho;
-        const BinAdj r = binary_adjoint_site(lf, lg, ux, uy, uz, p, Gx, Gy, Gz, lap, cp, cp.omega_f, cp.omega_g);
-        // relaxation-rate sensitivities sum lambda* (eq - current)
-        const double usq = ux * ux + uy * uy + uz * uz;
         const FreeEnergy<double> fe(p, Gx, Gy, Gz, lap, cp);
-        double dwf = 0.0, dwg = 0.0;
+        // g and lambda_g in one pass
+        BinSums<false> gs;
+        double dwg = 0.0;
+        static_for<0, Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            const double gi = *at(gn + i * geo.dstride, src_offset<i, F_PENDING>(st, geo));
+            const double l = *at(lg_next + i * geo.dstride, offset_at<cx(i), cy(i), cz(i)>(st, geo));
+            const double cu = cdot<i>(ux, uy, uz);
+            const double E = 1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq;
+            gs.template add<i>(l, cu, E, 0.0);
+            dwg = dwg + l * (weight<double>(i) * (p * E + fe.template mobility_term<i>(cp)) - gi);
+        });
+        // lambda_f pass
+        BinSums<true> fs;
+        double lfeq = 0.0;
         static_for<0, Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
             const double cu = cdot<i>(ux, uy, uz);
             const double E = 1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq;
-            const double feq = weight<double>(i) * (rho * E + fe.template stress_term<i>(cp));
-            const double geq = weight<double>(i) * (p * E + fe.template mobility_term<i>(cp));
-            dwf = dwf + lf[i] * (feq - f[i]);
-            dwg = dwg + lg[i] * (geq - g[i]);
+            const double li = lf[i][t];
+            fs.template add<i>(li, cu, E, cdot<i>(Gx, Gy, Gz));
+            lfeq = lfeq + li * weight<double>(i) * (rho * E + fe.template stress_term<i>(cp));
         });
+        const BinAdj r = binary_adjoint_finish(fs, gs, ux, uy, uz, p, Gx, Gy, Gz, lap, cp, cp.omega_f, cp.omega_g);
         const double wg = cp.omega_g * p / rho;
         const double V[3] = {cp.omega_f * r.Tf[0] + wg * r.Tg[0], cp.omega_f * r.Tf[1] + wg * r.Tg[1],
                              cp.omega_f * r.Tf[2] + wg * r.Tg[2]};
         const double base = cp.omega_f * r.Sf - (V[0] * ux + V[1] * uy + V[2] * uz);
         static_for<0, Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            *at(lf_n + i * geo.dstride, off) = (1.0 - cp.omega_f) * lf[i] + base + cdot<i>(V[0], V[1], V[2]);
+            *at(lf_n + i * geo.dstride, off) = (1.0 - cp.omega_f) * lf[i][t] + base + cdot<i>(V[0], V[1], V[2]);
         });
         afield[off] = r.a_phi;
         afield[(size_t)geo.nsite + off] = r.a_G[0];
         afield[2 * (size_t)geo.nsite + off] = r.a_G[1];
         afield[3 * (size_t)geo.nsite + off] = r.a_G[2];
         afield[4 * (size_t)geo.nsite + off] = r.a_lap;
-        acc[0] = acc[0] + dwf;
+        acc[0] = acc[0] + (lfeq - lff);
         acc[1] = acc[1] + dwg;
         acc[2] = acc[2] + r.dkappa;
     }
@@ -968,12 +1030,16 @@ __global__ __launch_bounds__(P::TPB) void k_adjoint_binary_init(const double* __
 // Stencil part: b(s) = a_phi(s) - 6 a_lap(s) + sum_a [a_G_a(s - e_a) - a_G_a(s + e_a)] / 2
 //                      + sum_a [a_lap(s + e_a) + a_lap(s - e_a)]   (= dL/dphi(s)).
 // INIT: out[s] = b.  Otherwise out is lambda_g^n: out_j(s) = (1 - omega_g)
-// lambda_g^{n+1}_j(s + c_j) + b(s).
-template <class P, bool INIT>
+// lambda_g^{n+1}_j(s + c_j) + b(s).  Block 0 also adds the K block partials
+// the local kernel left (partial[8 b + k], b < nblocks) into sums[0..K), in
+// block order, which saves the step a separate reduction launch.
+template <class P, bool INIT, int K>
 __global__ __launch_bounds__(P::TPB) void k_adjoint_binary_stencil(const double* __restrict__ afield,
                                                                    const double* __restrict__ lg_next,
                                                                    double* __restrict__ out, Geo geo,
-                                                                   double omega_g) {
+                                                                   double omega_g,
+                                                                   const double* __restrict__ partial,
+                                                                   int nblocks, double* __restrict__ sums) {
     const Column col = column_of_thread<P>(geo);
     const size_t N = geo.nsite;
     for (int v = 0; v < P::TZ; ++v) {
@@ -1002,6 +1068,7 @@ __global__ __launch_bounds__(P::TPB) void k_adjoint_binary_stencil(const double*
             });
         }
     }
+    if (blockIdx.x == 0) final_sums<P::TPB, K>(partial, nblocks, sums, 0.0, 0.0, 1);
 }
 
 // ---------------------------------------------------------------------------

@@ -427,9 +427,17 @@ int run_set_state(lb_ctx* c, const S* f, const S* g) {
 // collides the context's state in its own buffers and copies the result out;
 // later steps march from post[k-1] to post[k] (both of direction stride N).
 template <class S>
-int run_step_record_binary(lb_ctx* c, int32_t n, S* post) {
+int run_step_record_binary(lb_ctx* c, int32_t n, S* post, typename Compute<S>::T* phi) {
+    using T = typename Compute<S>::T;
     const int64_t N = c->L.nsite;
     const size_t w = (size_t)N * sizeof(S), sp = (size_t)c->L.dstride * sizeof(S);
+    const auto cp = coll_params<S>(c);
+    if (phi) {                                        // phi of the state step 0 collides
+        Timed t(c, LB_K_PHI);
+        const S* g = (const S*)c->gbuf(c->cur);
+        if (c->pending) k_phi<Pol, S, true><<<c->grid(), c->block(), 0, c->stream>>>(g, phi, c->geo(), cp.phi0);
+        else k_phi<Pol, S, false><<<c->grid(), c->block(), 0, c->stream>>>(g, phi, c->geo(), cp.phi0);
+    }
     int rc = run_collide<S>(c);                       // state now direct: the post-collision field
     if (rc) return rc;
     {
@@ -444,14 +452,18 @@ int run_step_record_binary(lb_ctx* c, int32_t n, S* post) {
     constexpr int BZ = March<S>::bz;
     Geo g = c->template march_geo<MP, BZ>();
     g.dstride = N;
-    const auto cp = coll_params<S>(c);
     for (int32_t k = 1; k < n; ++k) {
         const S* src = post + (size_t)(k - 1) * 2 * Q * N;
         S* dst = post + (size_t)k * 2 * Q * N;
         {
             Timed t(c, LB_K_COLLIDE);
-            k_binary_march<MP, BZ, S, March<S>::glds><<<dim3(g.nblocks), dim3(MP::TPB), 0, c->stream>>>(
-                src, src + Q * N, dst, dst + Q * N, g, cp);
+            const dim3 grid(g.nblocks), block(MP::TPB);
+            if (phi)
+                k_binary_march<MP, BZ, S, March<S>::glds, 3, true><<<grid, block, 0, c->stream>>>(
+                    src, src + Q * N, dst, dst + Q * N, g, cp, phi + (size_t)k * N);
+            else
+                k_binary_march<MP, BZ, S, March<S>::glds><<<grid, block, 0, c->stream>>>(
+                    src, src + Q * N, dst, dst + Q * N, g, cp);
         }
         rc = launch_status();
         if (rc) return rc;
@@ -468,8 +480,8 @@ int run_step_record_binary(lb_ctx* c, int32_t n, S* post) {
 }
 
 template <class S>
-int run_step_record(lb_ctx* c, int32_t n, S* post) {
-    if (c->p.model == LB_BINARY) return run_step_record_binary<S>(c, n, post);
+int run_step_record(lb_ctx* c, int32_t n, S* post, typename Compute<S>::T* phi) {
+    if (c->p.model == LB_BINARY) return run_step_record_binary<S>(c, n, post, phi);
     const int64_t N = c->L.nsite;
     const auto cp = coll_params<S>(c);
     const dim3 grid = c->grid(), block = c->block();
@@ -673,14 +685,15 @@ int lb_set_tau(lb_ctx* c, double tau_f) {
     return LB_OK;
 }
 
-int lb_step_record(lb_ctx* c, int32_t nsteps, void* post) {
+int lb_step_record(lb_ctx* c, int32_t nsteps, void* post, void* phi) {
     if (!c || nsteps < 0) return LB_EINVAL;
+    if (phi && c->p.model != LB_BINARY) return LB_EINVAL;
     if (nsteps == 0) return LB_OK;
     if (!post) return LB_EINVAL;
     if (c->p.collision != LB_BGK) return LB_ENOTSUP;
     return by_storage(c, [&](auto tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
-        return run_step_record<S>(c, nsteps, (S*)post);
+        return run_step_record<S>(c, nsteps, (S*)post, (typename Compute<S>::T*)phi);
     });
 }
 
@@ -696,12 +709,13 @@ int lb_set_params(lb_ctx* c, const lb_params* p) {
     return LB_OK;
 }
 
-int lb_adjoint_step_binary(lb_ctx* c, const double* f, const double* g, int pending, const double* lf_next,
-                           const double* lg_next, double* lf_n, double* lg_n, double* grads) {
+int lb_adjoint_step_binary(lb_ctx* c, const double* f, const double* g, const double* phi_n, int pending,
+                           const double* lf_next, const double* lg_next, double* lf_n, double* lg_n,
+                           double* grads) {
     if (!c || !f || !g || !lf_next || !lg_next || !lf_n || !lg_n || !grads) return LB_EINVAL;
     if (c->p.model != LB_BINARY || c->p.storage != LB_F64) return LB_ENOTSUP;
     const double* outs[2] = {lf_n, lg_n};
-    const double* ins[4] = {f, g, lf_next, lg_next};
+    const double* ins[5] = {f, g, lf_next, lg_next, phi_n};
     for (const double* o : outs)
         for (const double* i : ins)
             if (o == i) return LB_EINVAL;
@@ -709,12 +723,14 @@ int lb_adjoint_step_binary(lb_ctx* c, const double* f, const double* g, int pend
     c->launched = true;
     const Geo geo = c->canonical_geo();
     const auto cp = coll_params<double>(c);
-    double* phi = (double*)c->phi();
+    const double* phi = phi_n;
     double* afield = (double*)c->fbuf(1 - c->cur);       // spare state buffer: 19 dstride >= 5 N doubles
-    {
-        Timed t(c, LB_K_PHI);
-        if (pending) k_phi<Pol, double, true><<<c->grid(), c->block(), 0, c->stream>>>(g, phi, geo, 0.0);
-        else k_phi<Pol, double, false><<<c->grid(), c->block(), 0, c->stream>>>(g, phi, geo, 0.0);
+    if (!phi) {
+        Timed t(c, LB_K_ADJOINT);
+        double* p = (double*)c->phi();
+        if (pending) k_phi<Pol, double, true><<<c->grid(), c->block(), 0, c->stream>>>(g, p, geo, 0.0);
+        else k_phi<Pol, double, false><<<c->grid(), c->block(), 0, c->stream>>>(g, p, geo, 0.0);
+        phi = p;
     }
     {
         Timed t(c, LB_K_ADJOINT);
@@ -727,10 +743,9 @@ int lb_adjoint_step_binary(lb_ctx* c, const double* f, const double* g, int pend
     }
     {
         Timed t(c, LB_K_ADJOINT);
-        k_adjoint_binary_stencil<Pol, false><<<c->grid(), c->block(), 0, c->stream>>>(afield, lg_next, lg_n, geo,
-                                                                                     cp.omega_g);
+        k_adjoint_binary_stencil<Pol, false, 3><<<c->grid(), c->block(), 0, c->stream>>>(
+            afield, lg_next, lg_n, geo, cp.omega_g, c->partial(), c->L.nblocks, grads);
     }
-    k_sums_final<Pol, 3><<<1, c->block(), 0, c->stream>>>(c->partial(), c->L.nblocks, grads, 0.0, 0.0, 1);
     return launch_status();
 }
 
@@ -746,9 +761,9 @@ int lb_adjoint_init_binary(lb_ctx* c, const double* rho, const double* u, const 
         Timed t(c, LB_K_ADJOINT);
         k_adjoint_binary_init<Pol><<<c->grid(), c->block(), 0, c->stream>>>(rho, u, phi, lf0, lg0, afield, drho, du,
                                                                            c->partial(), geo, cp);
-        k_adjoint_binary_stencil<Pol, true><<<c->grid(), c->block(), 0, c->stream>>>(afield, nullptr, dphi, geo, 1.0);
+        k_adjoint_binary_stencil<Pol, true, 1><<<c->grid(), c->block(), 0, c->stream>>>(
+            afield, nullptr, dphi, geo, 1.0, c->partial(), c->L.nblocks, dkappa);
     }
-    k_sums_final<Pol, 1><<<1, c->block(), 0, c->stream>>>(c->partial(), c->L.nblocks, dkappa, 0.0, 0.0, 1);
     return launch_status();
 }
 

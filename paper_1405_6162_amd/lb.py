@@ -67,12 +67,12 @@ _SIGNATURES = {
     "lb_conserved_sums": (_int, [_vp, _vp]),
     "lb_field_stats": (_int, [_vp, _vp]),
     "lb_set_params": (_int, [_vp, _vp]),
-    "lb_adjoint_step_binary": (_int, [_vp, _vp, _vp, ctypes.c_int, _vp, _vp, _vp, _vp, _vp]),
+    "lb_adjoint_step_binary": (_int, [_vp, _vp, _vp, _vp, ctypes.c_int, _vp, _vp, _vp, _vp, _vp]),
     "lb_adjoint_init_binary": (_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "lb_get_state": (_int, [_vp, _vp, _vp]),
     "lb_set_state": (_int, [_vp, _vp, _vp]),
     "lb_set_tau": (_int, [_vp, ctypes.c_double]),
-    "lb_step_record": (_int, [_vp, _i32, _vp]),
+    "lb_step_record": (_int, [_vp, _i32, _vp, _vp]),
     "lb_adjoint_step": (_int, [_vp, _vp, _int, _vp, _vp, _vp]),
     "lb_mask_index": (_int, [_vp, _vp, _vp, _vp]),
     "lb_get_sites": (_int, [_vp, _vp, ctypes.c_int64, _vp, _vp]),
@@ -180,8 +180,8 @@ def lb_set_tau(ctx, tau_f):
     _check("lb_set_tau", _lib.lb_set_tau(ctx, float(tau_f)))
 
 
-def lb_step_record(ctx, nsteps, post):
-    _check("lb_step_record", _lib.lb_step_record(ctx, int(nsteps), _ptr(post)))
+def lb_step_record(ctx, nsteps, post, phi=None):
+    _check("lb_step_record", _lib.lb_step_record(ctx, int(nsteps), _ptr(post), _ptr(phi)))
 
 
 def lb_adjoint_step(ctx, f, lam_next, lam_n, domega, f_pending=False):
@@ -193,10 +193,10 @@ def lb_set_params(ctx, params):
     _check("lb_set_params", _lib.lb_set_params(ctx, ctypes.byref(params)))
 
 
-def lb_adjoint_step_binary(ctx, f, g, lf_next, lg_next, lf_n, lg_n, grads, pending=False):
+def lb_adjoint_step_binary(ctx, f, g, lf_next, lg_next, lf_n, lg_n, grads, pending=False, phi=None):
     _check("lb_adjoint_step_binary", _lib.lb_adjoint_step_binary(
-        ctx, _ptr(f), _ptr(g), 1 if pending else 0, _ptr(lf_next), _ptr(lg_next), _ptr(lf_n), _ptr(lg_n),
-        _ptr(grads)))
+        ctx, _ptr(f), _ptr(g), _ptr(phi), 1 if pending else 0, _ptr(lf_next), _ptr(lg_next), _ptr(lf_n),
+        _ptr(lg_n), _ptr(grads)))
 
 
 def lb_adjoint_init_binary(ctx, rho, u, phi, lf0, lg0, dphi, drho, du, dkappa):

@@ -139,13 +139,15 @@ def test_create_checks_workspace_without_device_work(lib):
         assert lib.lb_set_state(ctx, fake, None) == lb.LB_EINVAL
         assert lib.lb_conserved_sums(ctx, None) == lb.LB_EINVAL
         assert lib.lb_adjoint_step(ctx, fake, 0, fake, ctypes.c_void_p((1 << 21)), fake) == lb.LB_ENOTSUP
-        assert lib.lb_step_record(ctx, -1, fake) == lb.LB_EINVAL
-        assert lib.lb_step_record(ctx, 0, None) == lb.LB_OK                      # no-op
+        assert lib.lb_step_record(ctx, -1, fake, None) == lb.LB_EINVAL
+        assert lib.lb_step_record(ctx, 0, None, None) == lb.LB_OK                # no-op
         # binary adjoint: aliasing and missing arguments are refused before any launch
         a, b2, c2, d2 = (ctypes.c_void_p((k + 2) << 20) for k in range(4))
-        assert lib.lb_adjoint_step_binary(ctx, fake, a, 0, b2, c2, b2, d2, fake) == lb.LB_EINVAL
-        assert lib.lb_adjoint_step_binary(ctx, fake, a, 0, b2, c2, d2, d2, fake) == lb.LB_EINVAL
-        assert lib.lb_adjoint_step_binary(ctx, fake, a, 0, b2, c2, d2, None, fake) == lb.LB_EINVAL
+        e2 = ctypes.c_void_p(7 << 20)
+        assert lib.lb_adjoint_step_binary(ctx, fake, a, None, 0, b2, c2, b2, d2, fake) == lb.LB_EINVAL
+        assert lib.lb_adjoint_step_binary(ctx, fake, a, None, 0, b2, c2, d2, d2, fake) == lb.LB_EINVAL
+        assert lib.lb_adjoint_step_binary(ctx, fake, a, None, 0, b2, c2, d2, None, fake) == lb.LB_EINVAL
+        assert lib.lb_adjoint_step_binary(ctx, fake, a, e2, 0, b2, c2, e2, d2, fake) == lb.LB_EINVAL  # phi aliased
         assert lib.lb_adjoint_init_binary(ctx, fake, fake, fake, fake, fake, None, fake, fake, fake) == lb.LB_EINVAL
         # set_params: physics may change, layout and deviation references may not
         q = lb.make_params(6, 5, 4, model=lb.LB_BINARY, kappa=0.05, mobility=0.3)
@@ -173,9 +175,10 @@ def test_single_model_rejects_phi(lib):
         assert lib.lb_moments(ctx, None, None, None) == lb.LB_OK    # nothing requested
         assert lib.lb_get_state(ctx, fake, fake) == lb.LB_EINVAL
         assert lib.lb_adjoint_step(ctx, fake, 1, fake, fake, fake) == lb.LB_EINVAL   # lam_n aliases
-        assert lib.lb_step_record(ctx, 3, None) == lb.LB_EINVAL
+        assert lib.lb_step_record(ctx, 3, None, None) == lb.LB_EINVAL
+        assert lib.lb_step_record(ctx, 0, None, fake) == lb.LB_EINVAL          # phi: binary only
         a = [ctypes.c_void_p((k + 2) << 20) for k in range(7)]
-        assert lib.lb_adjoint_step_binary(ctx, a[0], a[1], 0, a[2], a[3], a[4], a[5], a[6]) == lb.LB_ENOTSUP
+        assert lib.lb_adjoint_step_binary(ctx, a[0], a[1], None, 0, a[2], a[3], a[4], a[5], a[6]) == lb.LB_ENOTSUP
         assert lib.lb_adjoint_init_binary(ctx, *a, fake, fake, fake) == lb.LB_ENOTSUP
     finally:
         assert lib.lb_destroy(ctx) == lb.LB_OK

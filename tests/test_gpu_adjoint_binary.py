@@ -40,9 +40,10 @@ def _params(prm):
     return dict(tau_f=prm.tau_f, A=prm.A, B=prm.B, kappa=prm.kappa, mobility=prm.mobility, gamma=prm.gamma)
 
 
+@pytest.mark.parametrize("given_phi", [False, True])
 @pytest.mark.parametrize("nx,ny,nz", [(4, 4, 4), (5, 6, 7), (67, 9, 5), (16, 16, 16)])
-def test_binary_adjoint_step_kernels(lbgpu, nx, ny, nz):
-    print("case binary adjoint step", nx, ny, nz, flush=True)
+def test_binary_adjoint_step_kernels(lbgpu, nx, ny, nz, given_phi):
+    print("case binary adjoint step", nx, ny, nz, given_phi, flush=True)
     prm = O.Params(tau_f=0.9, kappa=0.05, mobility=0.3)
     f, g = _state(nx, ny, nz, seed=1)
     rng = np.random.default_rng(2)
@@ -52,7 +53,8 @@ def test_binary_adjoint_step_kernels(lbgpu, nx, ny, nz):
     lf, lg = torch.empty_like(dev(lf1)), torch.empty_like(dev(lg1))
     grads = torch.full((3,), 0.5, dtype=torch.float64, device="cuda")     # the call increments it
     lbgpu.lb_set_stream(lat.ctx, lbgpu._stream())
-    lbgpu.lb_adjoint_step_binary(lat.ctx, dev(f), dev(g), dev(lf1), dev(lg1), lf, lg, grads)
+    phi = dev(O.order_parameter(g)) if given_phi else None
+    lbgpu.lb_adjoint_step_binary(lat.ctx, dev(f), dev(g), dev(lf1), dev(lg1), lf, lg, grads, phi=phi)
     assert relerr(lf.cpu().numpy(), want_f) < 1e-12
     assert relerr(lg.cpu().numpy(), want_g) < 1e-12
     got = grads.cpu().numpy() - 0.5
@@ -97,10 +99,12 @@ def test_binary_step_record(lbgpu, pending_start, n):
         lat.step(1)
         f, g = O.step_binary(f, g, prm, 1)
     post = torch.empty((n, 38, nz, ny, nx), dtype=torch.float64, device="cuda")
+    phi = torch.empty((n, nz, ny, nx), dtype=torch.float64, device="cuda")
     lbgpu.lb_set_stream(lat.ctx, lbgpu._stream())
-    lbgpu.lb_step_record(lat.ctx, n, post)
-    p = post.cpu().numpy()
+    lbgpu.lb_step_record(lat.ctx, n, post, phi)
+    p, ph = post.cpu().numpy(), phi.cpu().numpy()
     for k in range(n):
+        assert relerr(ph[k], O.order_parameter(g)) < 1e-13
         pf, pg = O.collide_binary(f, g, prm)
         assert relerr(p[k, :19], pf) < 1e-12
         assert relerr(p[k, 19:], pg) < 1e-12

@@ -26,7 +26,7 @@ class _Lattice:
                                             gamma=prm.gamma)
         self.ctx = self
         self.f = self.g = None
-        self.calls = {"record": 0, "adjoint": 0}
+        self.calls = {"record": 0, "adjoint": 0, "phi_given": 0}
 
     def set_params(self, **kw):
         for k, v in kw.items():
@@ -62,10 +62,12 @@ class _Lattice:
         self.g = g.detach().numpy().copy() if g is not None else None
 
 
-def _record(ctx, n, post):
+def _record(ctx, n, post, phi=None):
     ctx.calls["record"] += 1
     for k in range(n):
         if ctx.model == lb.LB_BINARY:
+            if phi is not None:
+                phi[k] = torch.from_numpy(O.order_parameter(ctx.g))
             pf, pg = O.collide_binary(ctx.f, ctx.g, ctx.prm)
             post[k, :19] = torch.from_numpy(pf)
             post[k, 19:] = torch.from_numpy(pg)
@@ -76,11 +78,14 @@ def _record(ctx, n, post):
             ctx.f = O.propagate(pf)
 
 
-def _adjoint_binary(ctx, f, g, lf, lg, lf_n, lg_n, grads, pending=False):
+def _adjoint_binary(ctx, f, g, lf, lg, lf_n, lg_n, grads, pending=False, phi=None):
     ctx.calls["adjoint"] += 1
     fn, gn = f.numpy(), g.numpy()
     if pending:
         fn, gn = O.propagate(fn), O.propagate(gn)
+    if phi is not None:                    # a recorded phi must be that of this step's state
+        ctx.calls["phi_given"] += 1
+        np.testing.assert_allclose(phi.numpy(), O.order_parameter(gn), rtol=0, atol=1e-15)
     a, b, gr = O.adjoint_step_binary(fn, gn, lf.numpy(), lg.numpy(), ctx.prm)
     lf_n.copy_(torch.from_numpy(a))
     lg_n.copy_(torch.from_numpy(b))
@@ -130,6 +135,8 @@ def test_binary_rollout_checkpoint_logic(fake_lib, T, K):
     loss.backward()
     assert lat.calls["adjoint"] == T                       # one adjoint step per step
     assert lat.calls["record"] == sum(1 for s in range(0, T, K) if min(K, T - s) > 1)
+    # every step but the last of each segment longer than one step reads a recorded phi
+    assert lat.calls["phi_given"] == sum(min(K, T - s) - 1 for s in range(0, T, K) if min(K, T - s) > 1)
     scale = max(np.abs(a).max() for a in (dphi_o, drho_o, du_o))     # dL/drho0 vanishes at T = 0
     np.testing.assert_allclose(p0.grad.numpy(), dphi_o, rtol=0, atol=1e-13 * scale)
     np.testing.assert_allclose(r0.grad.numpy(), drho_o, rtol=0, atol=1e-13 * scale)
