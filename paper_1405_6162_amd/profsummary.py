@@ -2,7 +2,7 @@
 
     python -m paper_1405_6162_amd.profsummary stats  <kernel_stats.csv> [--title T] [--command C]
     python -m paper_1405_6162_amd.profsummary pmc    <fetch counter_collection.csv> <write counter_collection.csv>
-                                                     --kernel SUBSTRING [--copy-bytes B] [--title T] [--command C]
+                                                     --kernel SUBSTRING[,SUBSTRING...] [--copy-bytes B] [--title T] [--command C]
 
 `stats` prints the per-kernel call count and average / min / max duration
 from a `rocprofv3 --kernel-trace --stats --output-format csv` run.
@@ -84,17 +84,23 @@ def cmd_pmc(args):
     print("# copy reference: %d B read and written per dispatch; FETCH_SIZE reads %.1f KiB, WRITE_SIZE %.1f KiB"
           % (args.copy_bytes, fref, wref))
     print("# %-90s %8s %14s %14s" % ("kernel", "n", "FETCH_KiB", "WRITE_KiB"))
-    match = None
+    rows = {}
     for name in fv:
         f = sum(fv[name]) / len(fv[name])
         w = sum(wv.get(name, [0.0])) / max(len(wv.get(name, [])), 1)
         print("  %-90s %8d %14.1f %14.1f" % (short(name), len(fv[name]), f, w))
-        if args.kernel in name:
-            match = (name, f, w)
-    if match is None:
-        raise SystemExit("kernel %r not found" % args.kernel)
-    name, f, w = match
-    print("kernel: %s" % name)
+        rows[name] = (len(fv[name]), f, w)
+    # --kernel a,b: a step made of several kernels; for each substring the
+    # most-dispatched matching kernel, their per-dispatch counters summed
+    chosen = []
+    for sub in args.kernel.split(","):
+        cands = [n for n in rows if sub in n]
+        if not cands:
+            raise SystemExit("kernel %r not found" % sub)
+        chosen.append(max(cands, key=lambda n: rows[n][0]))
+    f = sum(rows[n][1] for n in chosen)
+    w = sum(rows[n][2] for n in chosen)
+    print("kernel: %s" % " + ".join(chosen))
     print("fetch_kib_per_dispatch: %.3f" % f)
     print("write_kib_per_dispatch: %.3f" % w)
     print("fetch_scale: %.5f" % fscale)
