@@ -277,6 +277,72 @@ def step_single_trt(f, tau_plus, tau_minus, nsteps=1):
     return f
 
 
+# Multiple-relaxation-time collision in moment space (d'Humieres, Ginzburg,
+# Krafczyk, Lallemand & Luo 2002): f* = f - M^-1 S M (f - f^eq) with an
+# orthogonal moment basis M of the D3Q19 velocities and a diagonal S.
+
+
+def mrt_basis():
+    """(19, 19) integer matrix whose rows are the moment polynomials at the
+    19 velocities, in the order rho, e, eps, j_x, q_x, j_y, q_y, j_z, q_z,
+    3p_xx, 3pi_xx, p_ww, pi_ww, p_xy, p_yz, p_xz, m_x, m_y, m_z:
+        1, 19c^2 - 30, (21c^4 - 53c^2 + 24)/2, c_x, (5c^2 - 9)c_x, c_y,
+        (5c^2 - 9)c_y, c_z, (5c^2 - 9)c_z, 3c_x^2 - c^2,
+        (3c^2 - 5)(3c_x^2 - c^2), c_y^2 - c_z^2, (3c^2 - 5)(c_y^2 - c_z^2),
+        c_x c_y, c_y c_z, c_x c_z, (c_y^2 - c_z^2)c_x, (c_z^2 - c_x^2)c_y,
+        (c_x^2 - c_y^2)c_z.
+    The rows are mutually orthogonal (plain dot product over the velocities)."""
+    M = np.zeros((NQ, NQ))
+    for i in range(NQ):
+        x, y, z = (int(v) for v in C[i])
+        c2 = x * x + y * y + z * z
+        M[:, i] = [1, 19 * c2 - 30, (21 * c2 * c2 - 53 * c2 + 24) // 2,
+                   x, (5 * c2 - 9) * x, y, (5 * c2 - 9) * y, z, (5 * c2 - 9) * z,
+                   3 * x * x - c2, (3 * c2 - 5) * (3 * x * x - c2),
+                   y * y - z * z, (3 * c2 - 5) * (y * y - z * z),
+                   x * y, y * z, x * z,
+                   (y * y - z * z) * x, (z * z - x * x) * y, (x * x - y * y) * z]
+    return M
+
+
+# Rate group of each moment: conserved (rate irrelevant: f^eq carries them
+# exactly), 'bulk' (e), 'ghost_even' (eps, pi_xx, pi_ww), 'flux' (q),
+# 'shear' (the five traceless stresses), 'ghost_odd' (m).
+MRT_GROUP = ("conserved", "bulk", "ghost_even", "conserved", "flux", "conserved", "flux", "conserved", "flux",
+             "shear", "ghost_even", "shear", "ghost_even", "shear", "shear", "shear",
+             "ghost_odd", "ghost_odd", "ghost_odd")
+
+
+def mrt(f, feq, tau_shear, tau_flux, tau_bulk, tau_ghost_even, tau_ghost_odd):
+    """f* = f - M^-1 S M (f - f^eq), S = diag of the inverse relaxation
+    times by group (M^-1 = M^T diag(1/|row|^2) for the orthogonal basis).
+    The even moments relax with tau_shear, tau_bulk or tau_ghost_even and the
+    odd ones with tau_flux or tau_ghost_odd, so tau_bulk = tau_ghost_even =
+    tau_shear and tau_ghost_odd = tau_flux is the TRT collision, and all
+    five equal is BGK."""
+    M = mrt_basis()
+    norm = (M * M).sum(axis=1)
+    tau = {"shear": tau_shear, "flux": tau_flux, "bulk": tau_bulk, "ghost_even": tau_ghost_even,
+           "ghost_odd": tau_ghost_odd}
+    rate = np.array([0.0 if g == "conserved" else 1.0 / tau[g] for g in MRT_GROUP])
+    neq = f - feq
+    m = np.tensordot(M, neq, axes=1)                      # moments of the non-equilibrium part
+    back = np.tensordot(M.T, (rate / norm)[:, None, None, None] * m, axes=1)
+    return f - back
+
+
+def collide_single_mrt(f, taus):
+    """Single-fluid MRT collision; taus = (shear, flux, bulk, ghost_even, ghost_odd)."""
+    u, rho = velocity(f)
+    return mrt(f, equilibrium_f(rho, u), *taus)
+
+
+def step_single_mrt(f, taus, nsteps=1):
+    for _ in range(nsteps):
+        f = propagate(collide_single_mrt(f, taus))
+    return f
+
+
 def binary_fields(g, prm):
     """phi, grad phi, lap phi, mu and P of the current g (whole lattice first,
     because the stencils need phi at the neighbours)."""

@@ -128,6 +128,20 @@ def _mut_phi_seed_factor(f, g, beta=1.0):
     return lf, 0.5 * lg
 
 
+def _mut_mrt_flux_polynomial():
+    # (5c^2 - 8) c_x for the x energy flux
+    M = O.mrt_basis.__wrapped__()
+    M[4] = M[4] + O.C[:, 0]
+    return M
+
+
+def _mut_mrt_bulk_group():
+    # the bulk rate applied to eps, the ghost rate to e
+    g = list(O.MRT_GROUP)
+    g[1], g[2] = g[2], g[1]
+    return tuple(g)
+
+
 def _swap_weights():
     w = O.W.copy()
     c2 = (O.C * O.C).sum(1)
@@ -164,6 +178,14 @@ MUTATIONS = {
                                                    [pins.test_binary_adjoint_step_matches_complex_step]),
     "binary loss seed phi factor": ("binary_loss_seed", _mut_phi_seed_factor,
                                     [pins.test_binary_loss_seed_complex_step]),
+    "MRT energy-flux polynomial": ("mrt_basis", lambda: _mut_mrt_flux_polynomial(),
+                                   [pins.test_mrt_basis_orthogonal_full_rank_and_parity]),
+}
+
+# non-callable attributes replaced by a value
+VALUE_MUTATIONS = {
+    "MRT bulk rate on the wrong moment": ("MRT_GROUP", _mut_mrt_bulk_group,
+                                          [lambda: pins.test_mrt_sound_damping_follows_bulk_viscosity(1.4)]),
 }
 
 
@@ -176,6 +198,13 @@ def test_pins_catch_planted_mistake(monkeypatch, name):
         monkeypatch.setattr(O, attr, mutant)
     else:
         monkeypatch.setattr(O, attr, mutant())
+    assert _fails(*checks), "no pin caught: %s" % name
+
+
+@pytest.mark.parametrize("name", sorted(VALUE_MUTATIONS))
+def test_pins_catch_planted_value(monkeypatch, name):
+    attr, make, checks = VALUE_MUTATIONS[name]
+    monkeypatch.setattr(O, attr, make())
     assert _fails(*checks), "no pin caught: %s" % name
 
 
