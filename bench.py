@@ -34,6 +34,10 @@ WORKLOADS = {
     "binary384_f32": ("binary", "f32", 384, "D3Q19 binary fluid 384^3 periodic, FP32 deviation storage"),
     "single256_f64": ("single", "f64", 256, "D3Q19 single-fluid BGK 256^3 periodic, FP64, tau = 1"),
     "single256_f32": ("single", "f32", 256, "D3Q19 single-fluid BGK 256^3 periodic, FP32 deviation storage"),
+    "single256_trt_f64": ("single", "f64", 256, "D3Q19 single-fluid TRT 256^3 periodic, FP64, tau+ = 1, "
+                          "tau- = 1.25"),
+    "single256_mrt_f64": ("single", "f64", 256, "D3Q19 single-fluid MRT 256^3 periodic, FP64, tau_shear = 1, "
+                          "tau_flux = 1.25, tau_bulk = 1.4, tau_ghost_even = 0.9, tau_ghost_odd = 1.2"),
     "adjoint64_f64": ("adjoint", "f64", 64, "D3Q19 single-fluid BGK 64^3 shear wave, FP64, 200-step rollout "
                                             "+ adjoint with checkpoints every 20 steps"),
     "adjoint128_f64": ("adjoint", "f64", 128, "D3Q19 single-fluid BGK 128^3 shear wave, FP64, 200-step rollout "
@@ -451,7 +455,12 @@ def main():
     scode = {"f64": lb.LB_F64, "f32": lb.LB_F32, "f16": lb.LB_F16}[storage]
     log("bench: %s, %d warmup + %d timed steps" % (desc, args.warmup, args.steps))
 
-    lat = lb.Lattice(n, n, n, model=mcode, storage=scode, vvl=args.vvl)
+    coll = {}
+    if "_trt_" in args.workload:
+        coll = dict(collision=lb.LB_TRT, tau_minus=1.25)
+    elif "_mrt_" in args.workload:
+        coll = dict(collision=lb.LB_MRT, tau_minus=1.25, tau_bulk=1.4, tau_ghost_even=0.9, tau_ghost_odd=1.2)
+    lat = lb.Lattice(n, n, n, model=mcode, storage=scode, vvl=args.vvl, **coll)
     if model == "binary":
         rho, u, phi = inputs.spinodal_quench(n, n, n, seed=0)
         lat.init_equilibrium(rho, u, phi)

@@ -73,9 +73,17 @@ extern "C" {
 
 /* Collision of f (single fluid).  LB_TRT: two-relaxation-time collision (the
  * parts of f - f^eq even and odd under c -> -c relax with 1/tau_f and
- * 1/tau_minus; tau_minus = tau_f is BGK). */
+ * 1/tau_minus; tau_minus = tau_f is BGK).  LB_MRT: multiple-relaxation-time
+ * collision in the orthogonal moment basis of d'Humieres et al. (2002): the
+ * shear stresses relax with 1/tau_f, the energy fluxes with 1/tau_minus, the
+ * energy moment with 1/tau_bulk (bulk viscosity (2/9)(tau_bulk - 1/2)), the
+ * even ghosts (eps, pi_xx, pi_ww) with 1/tau_ghost_even and the odd ghosts
+ * (m_x, m_y, m_z) with 1/tau_ghost_odd; tau_bulk = tau_ghost_even = tau_f and
+ * tau_ghost_odd = tau_minus is LB_TRT.  Neither is part of the paper's
+ * benchmark, which does not say which collision it uses (Section IV). */
 #define LB_BGK      0
 #define LB_TRT      1
+#define LB_MRT      2
 
 /* Storage precision of the distributions.
  * LB_F64: f and g stored as IEEE double, FP64 arithmetic, stored directly.
@@ -93,14 +101,18 @@ typedef struct lb_params {
     int32_t vvl;          /* sites per lane along z of the fused collide and phi
                              kernels (the virtual vector length of the targetDP
                              execution model, Section III-C): 0 or 1 (default), 2, 4 */
-    int32_t collision;    /* LB_BGK (default) or LB_TRT (LB_SINGLE only)      */
+    int32_t collision;    /* LB_BGK (default), LB_TRT or LB_MRT (LB_SINGLE only) */
     int32_t reserved;     /* must be 0                                        */
     double  tau_f;        /* BGK relaxation time of f, > 0.5                  */
     double  A, B, kappa;  /* free energy (binary only); kappa >= 0            */
     double  mobility;     /* Cahn-Hilliard mobility M > 0 (binary only)       */
     double  gamma;        /* mobility parameter Gamma > 0 (binary only)       */
     double  rho0, phi0;   /* deviation references for LB_F32/LB_F16; ignored for LB_F64 */
-    double  tau_minus;    /* LB_TRT: relaxation time of the odd part, > 0.5   */
+    double  tau_minus;    /* LB_TRT: relaxation time of the odd part; LB_MRT: of the
+                             energy fluxes; > 0.5                              */
+    double  tau_bulk;     /* LB_MRT: energy moment (bulk viscosity), > 0.5     */
+    double  tau_ghost_even; /* LB_MRT: eps, pi_xx, pi_ww, > 0.5                */
+    double  tau_ghost_odd;  /* LB_MRT: m_x, m_y, m_z, > 0.5                    */
 } lb_params;
 
 typedef struct lb_ctx lb_ctx;   /* opaque; created by lb_create */
@@ -189,7 +201,7 @@ int lb_adjoint_step(lb_ctx* ctx, const double* f, int f_pending, const double* l
                     double* lam_n, double* domega);
 
 /* Replace the physical parameters (tau_f, A, B, kappa, mobility, gamma,
- * tau_minus) for subsequent calls.  Every other field (sizes, model,
+ * tau_minus, tau_bulk, tau_ghost_even, tau_ghost_odd) for subsequent calls.  Every other field (sizes, model,
  * storage, vvl, collision, rho0, phi0) must equal the context's, else
  * LB_EINVAL; values are validated as by lb_create.  The state is kept. */
 int lb_set_params(lb_ctx* ctx, const lb_params* p);

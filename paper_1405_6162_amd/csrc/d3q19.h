@@ -42,6 +42,36 @@ __host__ __device__ constexpr T weight(int i) {
     return csq(i) == 0 ? T(1) / T(3) : (csq(i) == 1 ? T(1) / T(18) : T(1) / T(36));
 }
 
+// Moments of the orthogonal D3Q19 basis of d'Humieres et al. (2002) that the
+// multiple-relaxation-time collision relaxes at rates of their own (the
+// others relax as in the two-relaxation-time collision): polynomial m at
+// velocity i, for m = 1 (e), 2 (eps), 10 (3 pi_xx), 12 (pi_ww), 16, 17, 18
+// (m_x, m_y, m_z).
+__host__ __device__ constexpr int mrt_poly(int m, int i) {
+    const int x = cx(i), y = cy(i), z = cz(i), c2 = csq(i);
+    switch (m) {
+        case 1: return 19 * c2 - 30;
+        case 2: return (21 * c2 * c2 - 53 * c2 + 24) / 2;
+        case 10: return (3 * c2 - 5) * (3 * x * x - c2);
+        case 12: return (3 * c2 - 5) * (y * y - z * z);
+        case 16: return (y * y - z * z) * x;
+        case 17: return (z * z - x * x) * y;
+        case 18: return (x * x - y * y) * z;
+    }
+    return 0;
+}
+__host__ __device__ constexpr int mrt_extra(int k) {
+    constexpr int t[7] = {1, 2, 10, 12, 16, 17, 18};
+    return t[k];
+}
+__host__ __device__ constexpr int mrt_norm(int m) {
+    int s = 0;
+    for (int i = 0; i < Q; ++i) s += mrt_poly(m, i) * mrt_poly(m, i);
+    return s;
+}
+static_assert(mrt_norm(1) == 2394 && mrt_norm(2) == 252 && mrt_norm(10) == 72 && mrt_norm(12) == 24 &&
+              mrt_norm(16) == 8, "MRT basis norms");
+
 // Compute type for each storage type: FP64 storage computes in FP64, the
 // reduced-precision storages compute in FP32.
 template <class S> struct Compute;

@@ -22,12 +22,18 @@ namespace lbk {
 constexpr int MODEL_SINGLE = 0;
 constexpr int MODEL_BINARY = 1;
 
+// Collision of f: BGK, two-relaxation-time, or multiple-relaxation-time.
+constexpr int COLL_BGK = 0;
+constexpr int COLL_TRT = 1;
+constexpr int COLL_MRT = 2;
+
 template <class T>
 struct CollParams {
     T omega_f, omega_g;        // 1/tau_f, 1/tau_g
     T A, B, kappa, gamma;      // free energy and mobility parameter
     T rho0, phi0;              // deviation references (0 for FP64 storage)
-    T omega_m;                 // 1/tau_minus of the two-relaxation-time collision
+    T omega_m;                 // 1/tau_minus: odd part (TRT), energy flux (MRT)
+    T omega_b, omega_ge, omega_go;   // MRT: energy (bulk), even ghosts, odd ghosts
 };
 
 // ---------------------------------------------------------------------------
@@ -158,9 +164,13 @@ __global__ __launch_bounds__(P::TPB) void k_phi(const S* __restrict__ g, typenam
 // their six neighbours from there.
 // ---------------------------------------------------------------------------
 
-// BGK, or with TRT the two-relaxation-time collision: the parts of f - f^eq
-// even and odd under c -> -c relax with omega_f and omega_m.
-template <class P, bool TRT = false, class S, class T>
+// BGK; TRT: the parts of f - f^eq even and odd under c -> -c relax with
+// omega_f and omega_m; MRT: TRT for the shear stresses (even) and the energy
+// fluxes (odd), and seven more moments of the orthogonal basis with their own
+// rates -- the energy e (omega_b), the even ghosts eps, pi_xx, pi_ww
+// (omega_ge) and the odd ghosts m_x, m_y, m_z (omega_go) -- applied as a
+// correction (omega_k - its TRT rate) times the moment's projection.
+template <class P, int COLL = COLL_BGK, class S, class T>
 __device__ __forceinline__ void relax_single(const T (&f)[Q], S* fdst, uint32_t off, const Geo& geo,
                                              const CollParams<T>& cp, int64_t stride = -1) {
     const int64_t ds = stride < 0 ? geo.dstride : stride;
@@ -169,7 +179,42 @@ __device__ __forceinline__ void relax_single(const T (&f)[Q], S* fdst, uint32_t 
     const T rho = cp.rho0 + drho;
     const T ux = jx / rho, uy = jy / rho, uz = jz / rho;
     const T usq = ux * ux + uy * uy + uz * uz;
-    if constexpr (TRT) {
+    if constexpr (COLL == COLL_MRT) {
+        T neq[Q];
+        static_for<0, Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            const T cu = cdot<i>(ux, uy, uz);
+            neq[i] = f[i] - weight<T>(i) * (drho + rho * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq));
+        });
+        // projections of the non-equilibrium part on the separately relaxed moments
+        T a[7];
+        static_for<0, 7>([&](auto K) {
+            constexpr int k = decltype(K)::value;
+            constexpr int m = mrt_extra(k);
+            T acc = T(0);
+            static_for<0, Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                constexpr int c = mrt_poly(m, i);
+                if constexpr (c != 0) acc = acc + T(c) * neq[i];
+            });
+            // k = 0: e (bulk); 1-3: eps, pi_xx, pi_ww (even ghosts); 4-6: m (odd ghosts)
+            const T dw = k == 0 ? cp.omega_b - cp.omega_f : (k < 4 ? cp.omega_ge - cp.omega_f : cp.omega_go - cp.omega_m);
+            a[k] = dw * acc / T(mrt_norm(m));
+        });
+        static_for<0, Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            constexpr int o = opp(i);
+            T corr = T(0);
+            static_for<0, 7>([&](auto K) {
+                constexpr int k = decltype(K)::value;
+                constexpr int c = mrt_poly(mrt_extra(k), i);
+                if constexpr (c != 0) corr = corr + T(c) * a[k];
+            });
+            const T np = T(0.5) * (neq[i] + neq[o]);
+            const T nm = T(0.5) * (neq[i] - neq[o]);
+            stg<P::nt_store>(fdst + i * ds, off, static_cast<S>(f[i] - cp.omega_f * np - cp.omega_m * nm - corr));
+        });
+    } else if constexpr (COLL == COLL_TRT) {
         T feq[Q];
         static_for<0, Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
@@ -216,7 +261,7 @@ __device__ __forceinline__ void relax_binary(const T (&f)[Q], const T (&g)[Q], S
     });
 }
 
-template <class P, int MODEL, class S, bool GATHER, bool TRT = false>
+template <class P, int MODEL, class S, bool GATHER, int COLL = COLL_BGK>
 __global__ __launch_bounds__(P::TPB) void k_collide(const S* fsrc, const S* gsrc, S* fdst, S* gdst,
                                                     const typename Compute<S>::T* __restrict__ phi, Geo geo,
                                                     CollParams<typename Compute<S>::T> cp) {
@@ -263,14 +308,14 @@ __global__ __launch_bounds__(P::TPB) void k_collide(const S* fsrc, const S* gsrc
             if (!st.active) continue;
             T f[Q];
             load_site<P, GATHER>(fsrc, st, geo, f);
-            relax_single<P, TRT>(f, fdst, offset_at<0, 0, 0>(st, geo), geo, cp);
+            relax_single<P, COLL>(f, fdst, offset_at<0, 0, 0>(st, geo), geo, cp);
         }
     }
 }
 
 // Single-fluid collision from and into arrays of any direction stride (used
 // to record each step's post-collision field into caller memory).
-template <class P, class S, bool GATHER, bool TRT = false>
+template <class P, class S, bool GATHER, int COLL = COLL_BGK>
 __global__ __launch_bounds__(P::TPB) void k_collide_single_strided(const S* fsrc, int64_t src_stride, S* fdst,
                                                                    int64_t dst_stride, Geo geo,
                                                                    CollParams<typename Compute<S>::T> cp) {
@@ -282,7 +327,7 @@ __global__ __launch_bounds__(P::TPB) void k_collide_single_strided(const S* fsrc
         if (!st.active) continue;
         T f[Q];
         load_site<P, GATHER>(fsrc, st, geo, f, src_stride);
-        relax_single<P, TRT>(f, fdst, offset_at<0, 0, 0>(st, geo), geo, cp, dst_stride);
+        relax_single<P, COLL>(f, fdst, offset_at<0, 0, 0>(st, geo), geo, cp, dst_stride);
     }
 }
 

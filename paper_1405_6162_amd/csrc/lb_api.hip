@@ -81,11 +81,15 @@ int check_params(const lb_params* p) {
     if (p->storage != LB_F64 && p->storage != LB_F32 && p->storage != LB_F16) return LB_EINVAL;
     if (p->vvl != 0 && p->vvl != 1 && p->vvl != 2 && p->vvl != 4) return LB_EINVAL;
     if (p->reserved != 0) return LB_EINVAL;
-    if (p->collision != LB_BGK && p->collision != LB_TRT) return LB_EINVAL;
-    if (p->collision == LB_TRT) {
-        if (!std::isfinite(p->tau_minus) || !(p->tau_minus > 0.5)) return LB_EINVAL;
+    if (p->collision != LB_BGK && p->collision != LB_TRT && p->collision != LB_MRT) return LB_EINVAL;
+    auto valid_tau = [](double t) { return std::isfinite(t) && t > 0.5; };
+    if (p->collision != LB_BGK) {
+        if (!valid_tau(p->tau_minus)) return LB_EINVAL;
         if (p->model != LB_SINGLE) return LB_ENOTSUP;
     }
+    if (p->collision == LB_MRT &&
+        (!valid_tau(p->tau_bulk) || !valid_tau(p->tau_ghost_even) || !valid_tau(p->tau_ghost_odd)))
+        return LB_EINVAL;
     if (!std::isfinite(p->tau_f) || !(p->tau_f > 0.5)) return LB_EINVAL;
     if (p->model == LB_BINARY) {
         if (!std::isfinite(p->A) || !std::isfinite(p->B) || !std::isfinite(p->kappa)) return LB_EINVAL;
@@ -221,7 +225,11 @@ CollParams<typename Compute<S>::T> coll_params(const lb_ctx* c) {
     const bool dev = c->p.storage != LB_F64;
     cp.rho0 = dev ? (T)c->p.rho0 : T(0);
     cp.phi0 = dev ? (T)c->p.phi0 : T(0);
-    cp.omega_m = c->p.collision == LB_TRT ? (T)(1.0 / c->p.tau_minus) : cp.omega_f;
+    cp.omega_m = c->p.collision != LB_BGK ? (T)(1.0 / c->p.tau_minus) : cp.omega_f;
+    const bool mrt = c->p.collision == LB_MRT;
+    cp.omega_b = mrt ? (T)(1.0 / c->p.tau_bulk) : cp.omega_f;
+    cp.omega_ge = mrt ? (T)(1.0 / c->p.tau_ghost_even) : cp.omega_f;
+    cp.omega_go = mrt ? (T)(1.0 / c->p.tau_ghost_odd) : cp.omega_m;
     return cp;
 }
 
@@ -296,8 +304,11 @@ int run_collide(lb_ctx* c) {
                 if (c->pending) k_collide<P, MODEL_BINARY, S, true><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd, phi, geo, cp);
                 else k_collide<P, MODEL_BINARY, S, false><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd, phi, geo, cp);
             } else if (c->p.collision == LB_TRT) {
-                if (c->pending) k_collide<P, MODEL_SINGLE, S, true, true><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd, phi, geo, cp);
-                else k_collide<P, MODEL_SINGLE, S, false, true><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd, phi, geo, cp);
+                if (c->pending) k_collide<P, MODEL_SINGLE, S, true, COLL_TRT><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd, phi, geo, cp);
+                else k_collide<P, MODEL_SINGLE, S, false, COLL_TRT><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd, phi, geo, cp);
+            } else if (c->p.collision == LB_MRT) {
+                if (c->pending) k_collide<P, MODEL_SINGLE, S, true, COLL_MRT><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd, phi, geo, cp);
+                else k_collide<P, MODEL_SINGLE, S, false, COLL_MRT><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd, phi, geo, cp);
             } else {
                 if (c->pending) k_collide<P, MODEL_SINGLE, S, true><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd, phi, geo, cp);
                 else k_collide<P, MODEL_SINGLE, S, false><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd, phi, geo, cp);

@@ -16,7 +16,7 @@ import torch
 LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_ENOTSUP = 0, -1, -2, -3, -4
 LB_SINGLE, LB_BINARY = 0, 1
 LB_F64, LB_F32, LB_F16 = 0, 1, 2
-LB_BGK, LB_TRT = 0, 1
+LB_BGK, LB_TRT, LB_MRT = 0, 1, 2
 LB_K_COLLIDE, LB_K_PHI, LB_K_STREAM, LB_K_ADJOINT, LB_K_OTHER = 0, 1, 2, 3, 4
 Q = 19
 
@@ -42,15 +42,22 @@ class lb_params(ctypes.Structure):
         ("mobility", ctypes.c_double), ("gamma", ctypes.c_double),
         ("rho0", ctypes.c_double), ("phi0", ctypes.c_double),
         ("tau_minus", ctypes.c_double),
+        ("tau_bulk", ctypes.c_double), ("tau_ghost_even", ctypes.c_double), ("tau_ghost_odd", ctypes.c_double),
     ]
 
 
 def make_params(nx, ny, nz, model=LB_SINGLE, storage=LB_F64, tau_f=1.0, A=-0.0625, B=0.0625,
                 kappa=0.04, mobility=0.45, gamma=1.0, rho0=1.0, phi0=0.0, vvl=1, collision=LB_BGK,
-                tau_minus=None):
+                tau_minus=None, tau_bulk=None, tau_ghost_even=None, tau_ghost_odd=None):
+    """lb_params with defaults; the relaxation times not given default to the
+    ones that make each collision reduce to the simpler one (TRT to BGK, MRT
+    to TRT)."""
     tm = tau_f if tau_minus is None else tau_minus
+    tb = tau_f if tau_bulk is None else tau_bulk
+    tge = tau_f if tau_ghost_even is None else tau_ghost_even
+    tgo = tm if tau_ghost_odd is None else tau_ghost_odd
     return lb_params(nx, ny, nz, model, storage, vvl, collision, 0, tau_f, A, B, kappa, mobility, gamma,
-                     rho0, phi0, tm)
+                     rho0, phi0, tm, tb, tge, tgo)
 
 
 _lib = None
@@ -388,7 +395,8 @@ class Lattice:
     def set_params(self, **phys):
         """Change physical parameters (tau_f, A, B, kappa, mobility, gamma,
         tau_minus) for subsequent calls; the state is kept."""
-        allowed = {"tau_f", "A", "B", "kappa", "mobility", "gamma", "tau_minus"}
+        allowed = {"tau_f", "A", "B", "kappa", "mobility", "gamma", "tau_minus", "tau_bulk", "tau_ghost_even",
+                   "tau_ghost_odd"}
         bad = set(phys) - allowed
         if bad:
             raise ValueError("cannot change %s after creation" % ", ".join(sorted(bad)))

@@ -40,7 +40,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 def test_constants_match_header():
     text = open(HEADER).read()
-    for name in ("LB_OK", "LB_EINVAL", "LB_ENOMEM", "LB_EDEVICE", "LB_ENOTSUP", "LB_SINGLE", "LB_BGK", "LB_TRT",
+    for name in ("LB_OK", "LB_EINVAL", "LB_ENOMEM", "LB_EDEVICE", "LB_ENOTSUP", "LB_SINGLE", "LB_BGK", "LB_TRT", "LB_MRT",
                  "LB_BINARY", "LB_F64", "LB_F32", "LB_F16", "LB_K_COLLIDE", "LB_K_PHI",
                  "LB_K_STREAM", "LB_K_ADJOINT", "LB_K_OTHER"):
         m = re.search(r"#define\s+%s\s+\(?(-?\d+)\)?" % name, text)
@@ -105,7 +105,12 @@ def test_bad_parameters_rejected(lib, change):
 def test_collision_values(lib):
     assert _ws(lb.make_params(4, 4, 4, collision=lb.LB_TRT, tau_minus=1.2))[0] == lb.LB_OK
     assert _ws(lb.make_params(4, 4, 4, collision=lb.LB_TRT, tau_minus=0.5))[0] == lb.LB_EINVAL
-    assert _ws(lb.make_params(4, 4, 4, collision=2))[0] == lb.LB_EINVAL
+    assert _ws(lb.make_params(4, 4, 4, collision=3))[0] == lb.LB_EINVAL
+    mrt = dict(collision=lb.LB_MRT, tau_minus=1.1, tau_bulk=1.4, tau_ghost_even=0.9, tau_ghost_odd=1.2)
+    assert _ws(lb.make_params(4, 4, 4, **mrt))[0] == lb.LB_OK
+    for bad in ("tau_bulk", "tau_ghost_even", "tau_ghost_odd", "tau_minus"):
+        assert _ws(lb.make_params(4, 4, 4, **dict(mrt, **{bad: 0.5})))[0] == lb.LB_EINVAL, bad
+    assert _ws(lb.make_params(4, 4, 4, model=lb.LB_BINARY, **mrt))[0] == lb.LB_ENOTSUP
     assert _ws(lb.make_params(4, 4, 4, model=lb.LB_BINARY, collision=lb.LB_TRT, tau_minus=1.2))[0] \
         == lb.LB_ENOTSUP
     p = lb.make_params(4, 4, 4)

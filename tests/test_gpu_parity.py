@@ -285,3 +285,60 @@ def test_trt_single_fluid(lbgpu, nx, ny, nz, vvl):
     lat.step(4)
     ref = O.step_single_trt(O.propagate(ref), tp, tm, 4)
     assert relerr(cpu(lat.get_state()[0]), ref) < TOL64
+
+
+MRT_TAUS = (0.8, 1.1, 1.4, 0.9, 1.2)          # shear, flux (tau_minus), bulk, ghost_even, ghost_odd
+
+
+def _mrt_lattice(lbgpu, nx, ny, nz, taus, **kw):
+    ts, tq, tb, tge, tgo = taus
+    return lbgpu.Lattice(nx, ny, nz, tau_f=ts, collision=lbgpu.LB_MRT, tau_minus=tq, tau_bulk=tb,
+                         tau_ghost_even=tge, tau_ghost_odd=tgo, **kw)
+
+
+@pytest.mark.parametrize("nx,ny,nz,vvl", [(16, 16, 16, 1), (5, 6, 37, 1), (70, 5, 17, 2), (12, 10, 9, 4)])
+def test_mrt_single_fluid(lbgpu, nx, ny, nz, vvl):
+    """Multiple-relaxation-time collision against the oracle: collide-only and
+    fused steps."""
+    print("case mrt", nx, ny, nz, vvl, flush=True)
+    rho, u = single_case(nx, ny, nz, seed=17)
+    lat = _mrt_lattice(lbgpu, nx, ny, nz, MRT_TAUS, vvl=vvl)
+    rng = np.random.default_rng(20)                  # off equilibrium, so every moment has something to relax
+    ref = O.init_single(rho, u) * (1 + 1e-3 * rng.standard_normal((19, nz, ny, nx)))
+    lat.set_state(ref)
+    lat.collide()
+    ref = O.collide_single_mrt(ref, MRT_TAUS)
+    assert relerr(cpu(lat.get_state()[0]), ref) < TOL64
+    lat.propagate()
+    lat.step(4)
+    ref = O.step_single_mrt(O.propagate(ref), MRT_TAUS, 4)
+    assert relerr(cpu(lat.get_state()[0]), ref) < TOL64
+
+
+def test_mrt_reduces_to_trt_on_gpu(lbgpu):
+    """With tau_bulk = tau_ghost_even = tau_f and tau_ghost_odd = tau_minus the
+    MRT kernel gives the TRT kernel's result (to rounding)."""
+    n = 17
+    rho, u = single_case(n, n, n, seed=18)
+    a = _mrt_lattice(lbgpu, n, n, n, (0.8, 1.3, 0.8, 0.8, 1.3))
+    b = lbgpu.Lattice(n, n, n, tau_f=0.8, collision=lbgpu.LB_TRT, tau_minus=1.3)
+    for lat in (a, b):
+        lat.init_equilibrium(rho, u)
+        lat.step(5)
+    fa, fb = cpu(a.get_state()[0]), cpu(b.get_state()[0])
+    assert relerr(fa, fb) < 1e-14
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-5), ("f16", 5e-2)])
+def test_mrt_reduced_precision(lbgpu, storage, tol):
+    """MRT in deviation storage: velocity within the storage's tolerance of the
+    FP64 oracle after 10 steps."""
+    n = 16
+    code = {"f32": lbgpu.LB_F32, "f16": lbgpu.LB_F16}[storage]
+    rho, u = single_case(n, n, n, seed=19)
+    lat = _mrt_lattice(lbgpu, n, n, n, MRT_TAUS, storage=code)
+    lat.init_equilibrium(rho, u)
+    lat.step(10)
+    _r, ug, _p = (cpu(t) for t in lat.moments())
+    uref, _rr = O.velocity(O.step_single_mrt(O.init_single(rho, u), MRT_TAUS, 10))
+    assert relerr(ug, uref) < tol
