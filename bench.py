@@ -28,6 +28,11 @@ HBM_PEAK_GBS = 8000.0          # MI355X published HBM3E bandwidth
 WORKLOADS = {
     # name: (model, storage, n, description)
     "binary128_f64": ("binary", "f64", 128, "D3Q19 binary fluid 128^3 periodic, FP64, spinodal quench"),
+    "binary128_trt_f64": ("binary", "f64", 128, "D3Q19 binary fluid 128^3 periodic, FP64, spinodal quench, "
+                          "f by TRT (tau+ = 1, tau- = 1.25)"),
+    "binary128_mrt_f64": ("binary", "f64", 128, "D3Q19 binary fluid 128^3 periodic, FP64, spinodal quench, "
+                          "f by MRT (tau_shear = 1, tau_flux = 1.25, tau_bulk = 1.4, tau_ghost_even = 0.9, "
+                          "tau_ghost_odd = 1.2)"),
     "binary256_f64": ("binary", "f64", 256, "D3Q19 binary fluid 256^3 periodic, FP64, spinodal quench"),
     "binary256_f32": ("binary", "f32", 256, "D3Q19 binary fluid 256^3 periodic, FP32 deviation storage"),
     "binary384_f16": ("binary", "f16", 384, "D3Q19 binary fluid 384^3 periodic, FP16 deviation storage"),

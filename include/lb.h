@@ -71,7 +71,8 @@ extern "C" {
 #define LB_SINGLE   0      /* one fluid, distribution f */
 #define LB_BINARY   1      /* binary mixture, distributions f and g (g carries phi) */
 
-/* Collision of f (single fluid).  LB_TRT: two-relaxation-time collision (the
+/* Collision of f (either model; g always relaxes with 1/tau_g).  LB_TRT:
+ * two-relaxation-time collision (the
  * parts of f - f^eq even and odd under c -> -c relax with 1/tau_f and
  * 1/tau_minus; tau_minus = tau_f is BGK).  LB_MRT: multiple-relaxation-time
  * collision in the orthogonal moment basis of d'Humieres et al. (2002): the
@@ -101,7 +102,7 @@ typedef struct lb_params {
     int32_t vvl;          /* sites per lane along z of the fused collide and phi
                              kernels (the virtual vector length of the targetDP
                              execution model, Section III-C): 0 or 1 (default), 2, 4 */
-    int32_t collision;    /* LB_BGK (default), LB_TRT or LB_MRT (LB_SINGLE only) */
+    int32_t collision;    /* LB_BGK (default), LB_TRT or LB_MRT               */
     int32_t reserved;     /* must be 0                                        */
     double  tau_f;        /* BGK relaxation time of f, > 0.5                  */
     double  A, B, kappa;  /* free energy (binary only); kappa >= 0            */
@@ -219,7 +220,8 @@ int lb_set_params(lb_ctx* ctx, const lb_params* p);
  * lf_next, lg_next = dL/df^{n+1}, dL/dg^{n+1}; lf_n, lg_n receive dL/df^n and
  * dL/dg^n (must not alias the inputs or each other).  grads (3 device
  * doubles) is INCREMENTED by dL/d(1/tau_f), dL/d(1/tau_g) and dL/dkappa of
- * this step (tau_g = mobility/gamma + 1/2).  Uses the context's parameters;
+ * this step (tau_g = mobility/gamma + 1/2).  LB_BGK collision only, else
+ * LB_ENOTSUP.  Uses the context's parameters;
  * uses the context's spare state buffer and phi buffer as scratch, so calls
  * on one context must not overlap; the lattice state itself is unchanged. */
 int lb_adjoint_step_binary(lb_ctx* ctx, const double* f, const double* g, const double* phi_n,

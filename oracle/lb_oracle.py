@@ -364,6 +364,25 @@ def collide_binary(f, g, prm):
     return f_new, g_new
 
 
+def collide_binary_mrt(f, g, prm, taus):
+    """Binary-fluid collision with f relaxing by the multiple-relaxation-time
+    collision (mrt, taus = (shear, flux, bulk, ghost_even, ghost_odd)) around
+    the same equilibrium f^eq(rho, u, P) as collide_binary; g relaxes as in
+    collide_binary."""
+    phi, _grad, _lap, mu, P = binary_fields(g, prm)
+    u, rho = velocity(f)
+    f_new = mrt(f, equilibrium_f(rho, u, P), *taus)
+    g_new = bgk(g, equilibrium_g(phi, u, mu, prm), prm.tau_g)
+    return f_new, g_new
+
+
+def step_binary_mrt(f, g, prm, taus, nsteps=1):
+    for _ in range(nsteps):
+        f, g = collide_binary_mrt(f, g, prm, taus)
+        f, g = propagate(f), propagate(g)
+    return f, g
+
+
 def propagate(f):
     """Periodic streaming f_i(s + c_i) <- f_i(s): a pure permutation."""
     out = np.empty_like(f)

@@ -164,30 +164,17 @@ __global__ __launch_bounds__(P::TPB) void k_phi(const S* __restrict__ g, typenam
 // their six neighbours from there.
 // ---------------------------------------------------------------------------
 
-// BGK; TRT: the parts of f - f^eq even and odd under c -> -c relax with
-// omega_f and omega_m; MRT: TRT for the shear stresses (even) and the energy
-// fluxes (odd), and seven more moments of the orthogonal basis with their own
-// rates -- the energy e (omega_b), the even ghosts eps, pi_xx, pi_ww
-// (omega_ge) and the odd ghosts m_x, m_y, m_z (omega_go) -- applied as a
-// correction (omega_k - its TRT rate) times the moment's projection.
-template <class P, int COLL = COLL_BGK, class S, class T>
-__device__ __forceinline__ void relax_single(const T (&f)[Q], S* fdst, uint32_t off, const Geo& geo,
-                                             const CollParams<T>& cp, int64_t stride = -1) {
-    const int64_t ds = stride < 0 ? geo.dstride : stride;
-    T drho, jx, jy, jz;
-    moments_in<typename Accum<S>::T>(f, drho, jx, jy, jz);
-    const T rho = cp.rho0 + drho;
-    const T ux = jx / rho, uy = jy / rho, uz = jz / rho;
-    const T usq = ux * ux + uy * uy + uz * uz;
+// TRT: the parts of f - f^eq even and odd under c -> -c relax with omega_f
+// and omega_m.  MRT: TRT for the shear stresses (even) and the energy fluxes
+// (odd), and seven more moments of the orthogonal basis with their own rates
+// -- the energy e (omega_b), the even ghosts eps, pi_xx, pi_ww (omega_ge) and
+// the odd ghosts m_x, m_y, m_z (omega_go) -- applied as a correction
+// (omega_k - its TRT rate) times the moment's projection.  neq = f - f^eq.
+template <class P, int COLL, class S, class T>
+__device__ __forceinline__ void relax_moments_store(const T (&f)[Q], const T (&neq)[Q], S* fdst, uint32_t off,
+                                                    int64_t ds, const CollParams<T>& cp) {
+    T a[7] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
     if constexpr (COLL == COLL_MRT) {
-        T neq[Q];
-        static_for<0, Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            const T cu = cdot<i>(ux, uy, uz);
-            neq[i] = f[i] - weight<T>(i) * (drho + rho * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq));
-        });
-        // projections of the non-equilibrium part on the separately relaxed moments
-        T a[7];
         static_for<0, 7>([&](auto K) {
             constexpr int k = decltype(K)::value;
             constexpr int m = mrt_extra(k);
@@ -201,33 +188,41 @@ __device__ __forceinline__ void relax_single(const T (&f)[Q], S* fdst, uint32_t 
             const T dw = k == 0 ? cp.omega_b - cp.omega_f : (k < 4 ? cp.omega_ge - cp.omega_f : cp.omega_go - cp.omega_m);
             a[k] = dw * acc / T(mrt_norm(m));
         });
-        static_for<0, Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            constexpr int o = opp(i);
-            T corr = T(0);
+    }
+    static_for<0, Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr int o = opp(i);
+        T corr = T(0);
+        if constexpr (COLL == COLL_MRT) {
             static_for<0, 7>([&](auto K) {
                 constexpr int k = decltype(K)::value;
                 constexpr int c = mrt_poly(mrt_extra(k), i);
                 if constexpr (c != 0) corr = corr + T(c) * a[k];
             });
-            const T np = T(0.5) * (neq[i] + neq[o]);
-            const T nm = T(0.5) * (neq[i] - neq[o]);
-            stg<P::nt_store>(fdst + i * ds, off, static_cast<S>(f[i] - cp.omega_f * np - cp.omega_m * nm - corr));
-        });
-    } else if constexpr (COLL == COLL_TRT) {
-        T feq[Q];
+        }
+        const T np = T(0.5) * (neq[i] + neq[o]);
+        const T nm = T(0.5) * (neq[i] - neq[o]);
+        stg<P::nt_store>(fdst + i * ds, off, static_cast<S>(f[i] - cp.omega_f * np - cp.omega_m * nm - corr));
+    });
+}
+
+template <class P, int COLL = COLL_BGK, class S, class T>
+__device__ __forceinline__ void relax_single(const T (&f)[Q], S* fdst, uint32_t off, const Geo& geo,
+                                             const CollParams<T>& cp, int64_t stride = -1) {
+    const int64_t ds = stride < 0 ? geo.dstride : stride;
+    T drho, jx, jy, jz;
+    moments_in<typename Accum<S>::T>(f, drho, jx, jy, jz);
+    const T rho = cp.rho0 + drho;
+    const T ux = jx / rho, uy = jy / rho, uz = jz / rho;
+    const T usq = ux * ux + uy * uy + uz * uz;
+    if constexpr (COLL != COLL_BGK) {
+        T neq[Q];
         static_for<0, Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
             const T cu = cdot<i>(ux, uy, uz);
-            feq[i] = weight<T>(i) * (drho + rho * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq));
+            neq[i] = f[i] - weight<T>(i) * (drho + rho * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq));
         });
-        static_for<0, Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            constexpr int o = opp(i);
-            const T np = T(0.5) * ((f[i] + f[o]) - (feq[i] + feq[o]));
-            const T nm = T(0.5) * ((f[i] - f[o]) - (feq[i] - feq[o]));
-            stg<P::nt_store>(fdst + i * ds, off, static_cast<S>(f[i] - cp.omega_f * np - cp.omega_m * nm));
-        });
+        relax_moments_store<P, COLL>(f, neq, fdst, off, ds, cp);
     } else {
         // every post-collision value before the first store (measured 1.3%
         // faster than storing each as it is computed)
@@ -246,7 +241,9 @@ __device__ __forceinline__ void relax_single(const T (&f)[Q], S* fdst, uint32_t 
     }
 }
 
-template <class P, class S, class T>
+// Binary collision of one site: g relaxes with omega_g (BGK); f with BGK, or
+// with TRT / MRT around the same f^eq (relax_moments_store).
+template <class P, int COLL = COLL_BGK, class S, class T>
 __device__ __forceinline__ void relax_binary(const T (&f)[Q], const T (&g)[Q], S* fdst, S* gdst, uint32_t off,
                                              const Geo& geo, const CollParams<T>& cp, T phic, T gx, T gy, T gz,
                                              T lap) {
@@ -257,6 +254,19 @@ __device__ __forceinline__ void relax_binary(const T (&f)[Q], const T (&g)[Q], S
     const T usq = ux * ux + uy * uy + uz * uz;
     const FreeEnergy<T> fe(phic, gx, gy, gz, lap, cp);
     const T dphi = phic - cp.phi0;
+    if constexpr (COLL != COLL_BGK) {
+        T neq[Q];
+        static_for<0, Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            const T cu = cdot<i>(ux, uy, uz);
+            const T base = T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq;
+            neq[i] = f[i] - weight<T>(i) * (drho + rho * base + fe.template stress_term<i>(cp));
+            const T geq = weight<T>(i) * (dphi + phic * base + fe.template mobility_term<i>(cp));
+            stg<P::nt_store>(gdst + i * geo.dstride, off, static_cast<S>(g[i] - cp.omega_g * (g[i] - geq)));
+        });
+        relax_moments_store<P, COLL>(f, neq, fdst, off, geo.dstride, cp);
+        return;
+    }
     static_for<0, Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         const T cu = cdot<i>(ux, uy, uz);
@@ -306,7 +316,7 @@ __global__ __launch_bounds__(P::TPB) void k_collide(const S* fsrc, const S* gsrc
             T f[Q], g[Q];
             load_site<P, GATHER>(fsrc, st, geo, f);
             load_site<P, GATHER>(gsrc, st, geo, g);
-            relax_binary<P>(f, g, fdst, gdst, offset_at<0, 0, 0>(st, geo), geo, cp, phic, gx, gy, gz, lap);
+            relax_binary<P, COLL>(f, g, fdst, gdst, offset_at<0, 0, 0>(st, geo), geo, cp, phic, gx, gy, gz, lap);
         }
     } else {
 #pragma unroll
@@ -390,7 +400,7 @@ __device__ __forceinline__ T phi_of_gathered(const S* g, const Site& st, const G
 // next is never one still being read, so one barrier per plane suffices.
 // With PHI_OUT the kernel also stores the phi it computes for its own sites
 // (phi_out[s], canonical), i.e. phi of the state this step collides.
-template <class P, int BZ, class S, bool GLDS, int RING = 3, bool PHI_OUT = false>
+template <class P, int BZ, class S, bool GLDS, int RING = 3, bool PHI_OUT = false, int COLL = COLL_BGK>
 __global__ __launch_bounds__(P::TPB) void k_binary_march(const S* __restrict__ fsrc, const S* __restrict__ gsrc,
                                                          S* __restrict__ fdst, S* __restrict__ gdst, Geo geo,
                                                          CollParams<typename Compute<S>::T> cp,
@@ -484,7 +494,7 @@ __global__ __launch_bounds__(P::TPB) void k_binary_march(const S* __restrict__ f
             const T gy = T(0.5) * (pyp - pym);
             const T gz = T(0.5) * (pzp - pzm);
             const T lap = (pxp + pxm) + (pyp + pym) + (pzp + pzm) - T(6) * phic;
-            relax_binary<P>(fc, gc, fdst, gdst, offset_at<0, 0, 0>(sc, geo), geo, cp, phic, gx, gy, gz, lap);
+            relax_binary<P, COLL>(fc, gc, fdst, gdst, offset_at<0, 0, 0>(sc, geo), geo, cp, phic, gx, gy, gz, lap);
         }
         if constexpr (!GLDS) {
 #pragma unroll

@@ -83,10 +83,7 @@ int check_params(const lb_params* p) {
     if (p->reserved != 0) return LB_EINVAL;
     if (p->collision != LB_BGK && p->collision != LB_TRT && p->collision != LB_MRT) return LB_EINVAL;
     auto valid_tau = [](double t) { return std::isfinite(t) && t > 0.5; };
-    if (p->collision != LB_BGK) {
-        if (!valid_tau(p->tau_minus)) return LB_EINVAL;
-        if (p->model != LB_SINGLE) return LB_ENOTSUP;
-    }
+    if (p->collision != LB_BGK && !valid_tau(p->tau_minus)) return LB_EINVAL;
     if (p->collision == LB_MRT &&
         (!valid_tau(p->tau_bulk) || !valid_tau(p->tau_ghost_even) || !valid_tau(p->tau_ghost_odd)))
         return LB_EINVAL;
@@ -273,8 +270,17 @@ int run_binary_march(lb_ctx* c) {
     const Geo g = c->template march_geo<MP, BZ>();
     {
         Timed t(c, LB_K_COLLIDE);
-        k_binary_march<MP, BZ, S, March<S>::glds><<<dim3(g.nblocks), dim3(MP::TPB), 0, c->stream>>>(
-            (const S*)c->fbuf(src), (const S*)c->gbuf(src), (S*)c->fbuf(dst), (S*)c->gbuf(dst), g, cp);
+        const dim3 grid(g.nblocks), block(MP::TPB);
+        const S* fs = (const S*)c->fbuf(src);
+        const S* gs = (const S*)c->gbuf(src);
+        S* fd = (S*)c->fbuf(dst);
+        S* gd = (S*)c->gbuf(dst);
+        if (c->p.collision == LB_TRT)
+            k_binary_march<MP, BZ, S, March<S>::glds, 3, false, COLL_TRT><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd, g, cp);
+        else if (c->p.collision == LB_MRT)
+            k_binary_march<MP, BZ, S, March<S>::glds, 3, false, COLL_MRT><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd, g, cp);
+        else
+            k_binary_march<MP, BZ, S, March<S>::glds><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd, g, cp);
     }
     int rc = launch_status();
     if (rc) return rc;
@@ -300,7 +306,13 @@ int run_collide(lb_ctx* c) {
             using P = decltype(pol);
             const Geo geo = c->template geo_for<P>();
             const dim3 grid(geo.nblocks), block(P::TPB);
-            if (bin) {
+            if (bin && c->p.collision == LB_TRT) {
+                if (c->pending) k_collide<P, MODEL_BINARY, S, true, COLL_TRT><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd, phi, geo, cp);
+                else k_collide<P, MODEL_BINARY, S, false, COLL_TRT><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd, phi, geo, cp);
+            } else if (bin && c->p.collision == LB_MRT) {
+                if (c->pending) k_collide<P, MODEL_BINARY, S, true, COLL_MRT><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd, phi, geo, cp);
+                else k_collide<P, MODEL_BINARY, S, false, COLL_MRT><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd, phi, geo, cp);
+            } else if (bin) {
                 if (c->pending) k_collide<P, MODEL_BINARY, S, true><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd, phi, geo, cp);
                 else k_collide<P, MODEL_BINARY, S, false><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd, phi, geo, cp);
             } else if (c->p.collision == LB_TRT) {
@@ -724,7 +736,7 @@ int lb_adjoint_step_binary(lb_ctx* c, const double* f, const double* g, const do
                            const double* lf_next, const double* lg_next, double* lf_n, double* lg_n,
                            double* grads) {
     if (!c || !f || !g || !lf_next || !lg_next || !lf_n || !lg_n || !grads) return LB_EINVAL;
-    if (c->p.model != LB_BINARY || c->p.storage != LB_F64) return LB_ENOTSUP;
+    if (c->p.model != LB_BINARY || c->p.storage != LB_F64 || c->p.collision != LB_BGK) return LB_ENOTSUP;
     const double* outs[2] = {lf_n, lg_n};
     const double* ins[5] = {f, g, lf_next, lg_next, phi_n};
     for (const double* o : outs)
@@ -763,7 +775,7 @@ int lb_adjoint_step_binary(lb_ctx* c, const double* f, const double* g, const do
 int lb_adjoint_init_binary(lb_ctx* c, const double* rho, const double* u, const double* phi, const double* lf0,
                            const double* lg0, double* dphi, double* drho, double* du, double* dkappa) {
     if (!c || !rho || !u || !phi || !lf0 || !lg0 || !dphi || !drho || !du || !dkappa) return LB_EINVAL;
-    if (c->p.model != LB_BINARY || c->p.storage != LB_F64) return LB_ENOTSUP;
+    if (c->p.model != LB_BINARY || c->p.storage != LB_F64 || c->p.collision != LB_BGK) return LB_ENOTSUP;
     c->launched = true;
     const Geo geo = c->canonical_geo();
     const auto cp = coll_params<double>(c);

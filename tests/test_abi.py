@@ -110,9 +110,8 @@ def test_collision_values(lib):
     assert _ws(lb.make_params(4, 4, 4, **mrt))[0] == lb.LB_OK
     for bad in ("tau_bulk", "tau_ghost_even", "tau_ghost_odd", "tau_minus"):
         assert _ws(lb.make_params(4, 4, 4, **dict(mrt, **{bad: 0.5})))[0] == lb.LB_EINVAL, bad
-    assert _ws(lb.make_params(4, 4, 4, model=lb.LB_BINARY, **mrt))[0] == lb.LB_ENOTSUP
-    assert _ws(lb.make_params(4, 4, 4, model=lb.LB_BINARY, collision=lb.LB_TRT, tau_minus=1.2))[0] \
-        == lb.LB_ENOTSUP
+    assert _ws(lb.make_params(4, 4, 4, model=lb.LB_BINARY, **mrt))[0] == lb.LB_OK
+    assert _ws(lb.make_params(4, 4, 4, model=lb.LB_BINARY, collision=lb.LB_TRT, tau_minus=1.2))[0] == lb.LB_OK
     p = lb.make_params(4, 4, 4)
     p.reserved = 3
     assert _ws(p)[0] == lb.LB_EINVAL

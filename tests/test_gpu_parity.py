@@ -342,3 +342,46 @@ def test_mrt_reduced_precision(lbgpu, storage, tol):
     _r, ug, _p = (cpu(t) for t in lat.moments())
     uref, _rr = O.velocity(O.step_single_mrt(O.init_single(rho, u), MRT_TAUS, 10))
     assert relerr(ug, uref) < tol
+
+
+@pytest.mark.parametrize("coll", ["trt", "mrt"])
+@pytest.mark.parametrize("nx,ny,nz", [(16, 16, 16), (5, 6, 37), (70, 5, 17)])
+def test_binary_trt_mrt(lbgpu, coll, nx, ny, nz):
+    """Binary fluid with f relaxing by TRT or MRT: the two-pass collide of a
+    direct state and the single-pass march, against the oracle."""
+    print("case binary", coll, nx, ny, nz, flush=True)
+    prm = O.Params(tau_f=0.8)
+    taus = (0.8, 1.25, 1.4, 0.9, 1.2) if coll == "mrt" else (0.8, 1.25, 0.8, 0.8, 1.25)
+    kw = dict(collision=lbgpu.LB_MRT if coll == "mrt" else lbgpu.LB_TRT, tau_minus=taus[1])
+    if coll == "mrt":
+        kw.update(tau_bulk=taus[2], tau_ghost_even=taus[3], tau_ghost_odd=taus[4])
+    rho, u, phi = binary_case(nx, ny, nz, seed=21, phi_max=0.3, u_max=0.01)
+    lat = lbgpu.Lattice(nx, ny, nz, model=lbgpu.LB_BINARY, **params_of(prm), **kw)
+    f, g = O.step_binary(*O.init_binary(rho, u, phi, prm), prm, 1)      # off equilibrium
+    lat.set_state(f, g)
+    lat.collide()
+    rf, rg = O.collide_binary_mrt(f, g, prm, taus)
+    sf, sg = (cpu(a) for a in lat.get_state())
+    assert relerr(sf, rf) < TOL64 and relerr(sg, rg) < TOL64
+    lat.propagate()
+    lat.step(4)
+    rf, rg = O.step_binary_mrt(O.propagate(rf), O.propagate(rg), prm, taus, 4)
+    sf, sg = (cpu(a) for a in lat.get_state())
+    assert relerr(sf, rf) < TOL64 and relerr(sg, rg) < TOL64
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 2e-4), ("f16", 0.3)])
+def test_binary_mrt_reduced_precision(lbgpu, storage, tol):
+    n = 16
+    prm = O.Params()
+    taus = (1.0, 1.25, 1.4, 0.9, 1.2)
+    code = {"f32": lbgpu.LB_F32, "f16": lbgpu.LB_F16}[storage]
+    rho, u, phi = binary_case(n, n, n, seed=22, phi_max=0.3, u_max=0.01)
+    lat = lbgpu.Lattice(n, n, n, model=lbgpu.LB_BINARY, storage=code, phi0=float(phi.mean()),
+                        collision=lbgpu.LB_MRT, tau_minus=1.25, tau_bulk=1.4, tau_ghost_even=0.9, tau_ghost_odd=1.2)
+    lat.init_equilibrium(rho, u, phi)
+    lat.step(10)
+    _r, ug, pg = (cpu(t) for t in lat.moments())
+    rf, rg = O.step_binary_mrt(*O.init_binary(rho, u, phi, prm), prm, taus, 10)
+    uref, _rr = O.velocity(rf)
+    assert relerr(ug, uref) < tol and relerr(pg, O.order_parameter(rg)) < tol

@@ -690,3 +690,20 @@ def test_mrt_sound_damping_follows_bulk_viscosity(tau_bulk):
     gamma = -np.log(energy(f) / e0) / (2 * T)
     nu, zeta = (tau - 0.5) / 3.0, 2.0 / 9.0 * (tau_bulk - 0.5)
     assert abs(gamma / (k * k * (2 * nu / 3 + zeta / 2)) - 1.0) < 0.01
+
+
+def test_binary_mrt_reduces_and_conserves():
+    """Binary MRT: equal times give collide_binary; rho, j and phi are
+    conserved whatever the times; g is untouched by the f times."""
+    prm = O.Params(tau_f=0.9)
+    rho, u, phi = inputs.spinodal_quench(5, 4, 3, seed=34, phi_max=0.3)
+    f, g = O.step_binary(*O.init_binary(rho, u, phi, prm), prm, 1)
+    a = O.collide_binary_mrt(f, g, prm, (0.9,) * 5)
+    b = O.collide_binary(f, g, prm)
+    np.testing.assert_allclose(a[0], b[0], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(a[1], b[1], rtol=0, atol=0)
+    fs, gs = O.collide_binary_mrt(f, g, prm, MRT_TAUS)
+    np.testing.assert_allclose(O.density(fs), O.density(f), rtol=1e-15)
+    np.testing.assert_allclose(O.momentum(fs), O.momentum(f), rtol=0, atol=1e-16)
+    np.testing.assert_allclose(O.order_parameter(gs), O.order_parameter(g), rtol=0, atol=1e-15)
+    np.testing.assert_array_equal(gs, b[1])
