@@ -1,4 +1,5 @@
-"""Compile the gfx950 HIP library (liblb.so) in-tree with hipcc.
+"""Compile the gfx950 HIP library (liblb.so) in-tree with hipcc, and the
+plain-C example program (lb_example) next to it.
 
     python -m paper_1405_6162_amd.build
 
@@ -17,6 +18,9 @@ SRC = os.path.join(PKG, "csrc", "lb_api.hip")
 DEPS = [os.path.join(PKG, "csrc", n) for n in ("d3q19.h", "kernels.h")] + [os.path.join(ROOT, "include", "lb.h")]
 LIB_DIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIB_DIR, "liblb.so")
+EXAMPLE_SRC = os.path.join(PKG, "csrc", "lb_example.c")
+EXAMPLE = os.path.join(LIB_DIR, "lb_example")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -44,7 +48,28 @@ def build(verbose=False):
         sys.stderr.write(res.stdout + res.stderr)
         raise RuntimeError("hipcc failed building %s" % LIB)
     os.replace(tmp, LIB)
+    build_example(verbose)
     return LIB
+
+
+def build_example(verbose=False):
+    """The plain-C example (lb_example.c) linked against liblb.so and the HIP
+    runtime, next to the library."""
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if not cc:
+        raise RuntimeError("a C compiler is required to build %s" % EXAMPLE)
+    tmp = EXAMPLE + ".tmp%d" % os.getpid()
+    cmd = [cc, "-O2", "-std=c11", "-Wall", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROCM, "include"),
+           "-I", os.path.join(ROOT, "include"), EXAMPLE_SRC, "-L", os.path.join(ROCM, "lib"), "-lamdhip64",
+           "-L", LIB_DIR, "-llb", "-Wl,-rpath,$ORIGIN", "-Wl,-rpath," + os.path.join(ROCM, "lib"), "-lm", "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("C compiler failed building %s" % EXAMPLE)
+    os.replace(tmp, EXAMPLE)
+    return EXAMPLE
 
 
 if __name__ == "__main__":
