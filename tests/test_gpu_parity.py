@@ -51,7 +51,8 @@ def cpu(t):
 # and z extents below, at and above the single-pass kernel's chunks of 8
 # (FP64) and 16 planes (37 = 16 + 16 + 5 = 4 x 8 + 5, 17 = 16 + 1 = 2 x 8 + 1).
 SIZES = [(4, 4, 4), (16, 16, 16), (5, 6, 7), (67, 9, 5), (4, 8, 12), (1, 1, 3), (130, 3, 2),
-         (5, 6, 37), (70, 5, 17)]
+         (5, 6, 37), (70, 5, 17),
+         (1, 1, 1), (3, 1, 1), (1, 7, 1), (2, 2, 2), (64, 4, 16)]      # one site; single-extent axes; whole tiles
 
 
 @pytest.mark.parametrize("nx,ny,nz", SIZES)
