@@ -3,7 +3,9 @@
 TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import this
 module: only the tests, the smoke check and the CPU baseline leg of the
 benchmark use it.  It shares no code, tables or constants with the HIP
-library; the two meet only on the seeded inputs they are both given.
+library; the two meet only on the seeded inputs they are both given.  A
+second, independent reference of the core step in plain C behind the
+library's C ABI (lb_oracle.c) is checked against this one by the tests.
 
 What the paper fixes and what is a reading
 ------------------------------------------
