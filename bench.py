@@ -302,6 +302,15 @@ def _rounded(*a):
     return tuple(x.astype("float32").astype("float64") for x in a)
 
 
+def interface_density(phi):
+    """Fraction of nearest-neighbour bonds (all three axes, periodic) across
+    which phi changes sign: interface area per unit volume in lattice units."""
+    import torch
+    p = phi.to(torch.float64)
+    cut = [(p * torch.roll(p, 1, dims=d) < 0).to(torch.float64).mean() for d in range(3)]
+    return float(sum(cut) / 3)
+
+
 def coarsening_length(phi):
     """L = 2 pi sum S(k) / sum |k| S(k) over k != 0, S = |FFT(phi)|^2."""
     import torch
@@ -349,7 +358,8 @@ def bench_precision(args, storage, n, desc):
            "reference": {"storage": ref_storage, "MLUPS": round(ref_mlups, 2),
                          "speedup": round(mlups / ref_mlups, 3)},
            "errors_vs_reference": err, "drift": drift, "reference_drift": ref_drift,
-           "coarsening_length": {storage: coarsening_length(p_low), ref_storage: coarsening_length(p_ref)}}
+           "coarsening_length": {storage: coarsening_length(p_low), ref_storage: coarsening_length(p_ref)},
+           "interface_density": {storage: interface_density(p_low), ref_storage: interface_density(p_ref)}}
     ref.close()
     low.close()
     if storage == "f32":
@@ -369,9 +379,11 @@ def bench_precision(args, storage, n, desc):
         for sto in ("f32", "f16"):
             lat, _, d = run(sto, 96, steps)
             e, p64, pl = _moment_errors(lb, r64, lat)
-            sub[sto] = {"errors_vs_f64": e, "drift": d, "coarsening_length": coarsening_length(pl)}
+            sub[sto] = {"errors_vs_f64": e, "drift": d, "coarsening_length": coarsening_length(pl),
+                        "interface_density": interface_density(pl)}
             lat.close()
-        sub["f64"] = {"drift": d64, "coarsening_length": coarsening_length(p64)}
+        sub["f64"] = {"drift": d64, "coarsening_length": coarsening_length(p64),
+                      "interface_density": interface_density(p64)}
         r64.close()
         out["sub_run_96"] = sub
     print(json.dumps(out), flush=True)

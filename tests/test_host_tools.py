@@ -114,3 +114,6 @@ def test_bench_host_helpers():
     x = torch.arange(n, dtype=torch.float64)
     phi = torch.cos(2 * np.pi * 4 * x / n).view(1, 1, n).expand(n, n, n).contiguous()
     assert bench.coarsening_length(phi) == pytest.approx(n / 4, rel=1e-12)
+    # cos(2 pi 4 x / n) changes sign 8 times along x and never along y, z
+    phi = phi + 0.123                     # avoid exact zeros at the nodes
+    assert bench.interface_density(phi) == pytest.approx(8 / n / 3, rel=1e-12)
