@@ -46,7 +46,7 @@ template <> struct March<float> {
 template <> struct March<_Float16> {
     using P = Tiling<64, 4, 1, false, true, true>;
     static constexpr int bz = 16;
-    static constexpr bool glds = false;
+    static constexpr bool glds = true;      // measured +2% over registers at 384^3
 };
 
 constexpr size_t kAlign = 4096;
