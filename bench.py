@@ -256,7 +256,7 @@ def bench_adjoint_binary(args, n, desc, T=200, K=20):
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(args.workload),
                      "traffic_unit": "bytes per adjoint step (local + stencil kernel)",
-                     "bytes_per_site": alg["adjoint"], "bytes_per_site_moved": 1160,
+                     "bytes_per_site": alg["adjoint"], "bytes_per_site_moved": 1016,
                      "avg_step_ms": round(per_step_ms, 5), "launches": adj_n},
         "gradients": {"kappa": float(gpar[0]), "mobility": float(gpar[1]), "tau_f": float(gpar[2]),
                       "max_abs_dphi0": float(gphi.abs().max())},

@@ -1,8 +1,9 @@
 """Differentiable rollouts: the single fluid, f_T = step^T(f_0; tau), and the
 binary fluid, (f_T, g_T) from the equilibrium on (rho0, u0, phi0) with
 kappa, mobility and tau_f, as torch.autograd.Functions whose backward runs
-the hand-written adjoint kernels (lb_adjoint_step, lb_adjoint_step_binary,
-lb_adjoint_init_binary) of the fused collide-stream step.
+the hand-written adjoint kernels of the fused collide-stream step, one
+library call per checkpoint segment (lb_adjoint_segment,
+lb_adjoint_segment_binary; for the binary fluid then lb_adjoint_init_binary).
 
 Memory: the forward keeps only the states at steps 0, K, 2K, ...; the
 backward recomputes each segment of at most K steps on the GPU, recording
@@ -55,7 +56,8 @@ class LBRollout(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_fT):
         lat, T, K, tau = ctx.lattice, ctx.nsteps, ctx.every, ctx.tau
-        lam = grad_fT.detach().to(torch.float64).contiguous()
+        lam = grad_fT.detach().to(torch.float64).contiguous().clone()     # updated in place below
+        work = torch.empty_like(lam)
         domega = torch.zeros(1, dtype=torch.float64, device=lam.device)
         lat.set_tau(tau)
         nseg = len(ctx.ckpts)
@@ -65,22 +67,16 @@ class LBRollout(torch.autograd.Function):
             if length <= 0:
                 continue
             # recompute the segment: the checkpoint is f^start; the recorded
-            # post-collision fields post[k] give f^{start+k+1} in pull form
+            # post-collision fields post[k] give f^{start+k+1} in pull form;
+            # then one library call walks the segment backwards
             ckpt = ctx.ckpts[seg]
             lat.set_state(ckpt)
             post = None
+            lb.lb_set_stream(lat.ctx, lb._stream())
             if length > 1:
                 post = torch.empty((length - 1,) + tuple(ckpt.shape), dtype=torch.float64, device=ckpt.device)
-                lb.lb_set_stream(lat.ctx, lb._stream())
                 lb.lb_step_record(lat.ctx, length - 1, post)
-            for n in range(length - 1, -1, -1):
-                lam_prev = torch.empty_like(lam)
-                lb.lb_set_stream(lat.ctx, lb._stream())
-                if n == 0:
-                    lb.lb_adjoint_step(lat.ctx, ckpt, lam, lam_prev, domega)
-                else:
-                    lb.lb_adjoint_step(lat.ctx, post[n - 1], lam, lam_prev, domega, f_pending=True)
-                lam = lam_prev
+            lb.lb_adjoint_segment(lat.ctx, ckpt, post, length, lam, work, domega)
             del post
         grad_tau = (-domega[0] / (tau * tau)).reshape(())
         ctx.ckpts = None
@@ -98,9 +94,9 @@ class LBBinaryRollout(torch.autograd.Function):
     state and parameters this call overwrites.  Gradients flow to rho0, u0,
     phi0, kappa, mobility and tau_f.  The backward recomputes each segment of
     at most `every` steps from its checkpoint, recording every step's
-    post-collision f and g, and runs the two adjoint kernels per step
-    (lb_adjoint_step_binary), then the reverse of the initialisation
-    (lb_adjoint_init_binary).
+    post-collision f and g, and reverses it in one call
+    (lb_adjoint_segment_binary: the local and the stencil adjoint kernel per
+    step), then the reverse of the initialisation (lb_adjoint_init_binary).
     """
 
     @staticmethod
@@ -134,8 +130,10 @@ class LBBinaryRollout(torch.autograd.Function):
         shape = ctx.ckpts[0][0].shape
         dev = ctx.ckpts[0][0].device
         zero = lambda: torch.zeros(shape, dtype=torch.float64, device=dev)
-        lf = grad_f.detach().to(torch.float64).contiguous() if grad_f is not None else zero()
-        lg = grad_g.detach().to(torch.float64).contiguous() if grad_g is not None else zero()
+        # lf, lg are updated in place below: never the caller's gradient tensors
+        lf = grad_f.detach().to(torch.float64).contiguous().clone() if grad_f is not None else zero()
+        lg = grad_g.detach().to(torch.float64).contiguous().clone() if grad_g is not None else zero()
+        work = torch.empty((2 * lb.Q,) + tuple(shape[1:]), dtype=torch.float64, device=dev)
         grads = torch.zeros(3, dtype=torch.float64, device=dev)
         for seg in range(len(ctx.ckpts) - 1, -1, -1):
             start = seg * K
@@ -145,23 +143,14 @@ class LBBinaryRollout(torch.autograd.Function):
             f_ck, g_ck = ctx.ckpts[seg]
             lat.set_state(f_ck, g_ck)
             post = phi = None
+            lb.lb_set_stream(lat.ctx, lb._stream())
             if length > 1:
                 # post[k] and phi[k] (phi of the state step k collides) for k < length - 1;
-                # the last step's phi is computed by the adjoint call itself
+                # the last step's phi is computed by the sweep itself
                 post = torch.empty((length - 1, 2 * lb.Q) + tuple(shape[1:]), dtype=torch.float64, device=dev)
                 phi = torch.empty((length - 1,) + tuple(shape[1:]), dtype=torch.float64, device=dev)
-                lb.lb_set_stream(lat.ctx, lb._stream())
                 lb.lb_step_record(lat.ctx, length - 1, post, phi)
-            for n in range(length - 1, -1, -1):
-                lf_n, lg_n = torch.empty_like(lf), torch.empty_like(lg)
-                phi_n = phi[n] if phi is not None and n < length - 1 else None
-                lb.lb_set_stream(lat.ctx, lb._stream())
-                if n == 0:
-                    lb.lb_adjoint_step_binary(lat.ctx, f_ck, g_ck, lf, lg, lf_n, lg_n, grads, phi=phi_n)
-                else:
-                    lb.lb_adjoint_step_binary(lat.ctx, post[n - 1, :lb.Q], post[n - 1, lb.Q:], lf, lg, lf_n, lg_n,
-                                              grads, pending=True, phi=phi_n)
-                lf, lg = lf_n, lg_n
+            lb.lb_adjoint_segment_binary(lat.ctx, f_ck, g_ck, post, phi, length, lf, lg, work, grads)
             del post, phi
         rho0, u0, phi0 = ctx.fields
         dphi, drho, du = torch.empty_like(phi0), torch.empty_like(rho0), torch.empty_like(u0)

@@ -951,21 +951,39 @@ __device__ __forceinline__ void phi_stencil(const double* __restrict__ phi, cons
     lap = (pxp + pxm) + (pyp + pym) + (pzp + pzm) - 6.0 * p;
 }
 
+// How the local kernel obtains the post-collision g adjoints of its site,
+// lambda*_j(s) = lambda_g^{n+1}_j(s + c_j), and whether it keeps them:
+//   LG_GATHER       gathered from lambda_g^{n+1} (canonical);
+//   LG_GATHER_KEEP  the same, and stored unshifted, P^n_j(s) = lambda*_j(s);
+//   LG_PULLED_KEEP  lambda_g^{n+1} is held as the pair (P^{n+1}, b^{n+1}),
+//                   lambda_g^{n+1}_j(x) = (1 - omega_g) P^{n+1}_j(x) + b^{n+1}(x),
+//                   with b the stencil kernel's dL/dphi; gathered from that
+//                   pair and stored as P^n.
+// The pair form lets a reverse sweep over several steps skip writing and
+// re-reading lambda_g itself: per step the stencil kernel then only turns
+// the sensitivity fields into b (8 bytes a site) instead of gathering and
+// writing lambda_g (304), at the price of the local kernel storing P (152).
+enum { LG_GATHER = 0, LG_GATHER_KEEP = 1, LG_PULLED_KEEP = 2 };
+
 // Local part of the binary adjoint step.  fn, gn: f^n and g^n (canonical,
 // or the recorded post-collision fields of the previous step when
-// F_PENDING, pulled); phi: phi^n (canonical); lf_next, lg_next: lambda^{n+1}.
-// Writes lambda_f^n and the five sensitivity fields afield[k*N + s]
-// (a_phi, a_Gx, a_Gy, a_Gz, a_lap); block partials of dL/domega_f,
-// dL/domega_g and dL/dkappa go to partial[8 b + 0..2].  Only lambda_f stays
-// in registers: f is reduced to its moments (and sum lambda_f f) as it
-// loads, and g with lambda_g are consumed in one pass once u is known.
-template <class P, bool F_PENDING>
+// F_PENDING, pulled); phi: phi^n (canonical); lf_next: lambda_f^{n+1};
+// lg_next: lambda_g^{n+1}, or P^{n+1} with b_next = b^{n+1} (LG above).
+// Writes lambda_f^n, P^n to p_out (LG != LG_GATHER) and the five
+// sensitivity fields afield[k*N + s] (a_phi, a_Gx, a_Gy, a_Gz, a_lap); block
+// partials of dL/domega_f, dL/domega_g and dL/dkappa go to
+// partial[8 b + 0..2].  Only lambda_f stays in registers: f is reduced to
+// its moments (and sum lambda_f f) as it loads, and g with lambda_g are
+// consumed in one pass once u is known.
+template <class P, bool F_PENDING, int LG>
 __global__ __launch_bounds__(P::TPB) void k_adjoint_binary(const double* __restrict__ fn,
                                                            const double* __restrict__ gn,
                                                            const double* __restrict__ phi,
                                                            const double* __restrict__ lf_next,
                                                            const double* __restrict__ lg_next,
-                                                           double* __restrict__ lf_n, double* __restrict__ afield,
+                                                           const double* __restrict__ b_next,
+                                                           double* __restrict__ lf_n, double* __restrict__ p_out,
+                                                           double* __restrict__ afield,
                                                            double* __restrict__ partial, Geo geo,
                                                            CollParams<double> cp) {
     __shared__ double sh[3][P::TPB];
@@ -1004,7 +1022,10 @@ __global__ __launch_bounds__(P::TPB) void k_adjoint_binary(const double* __restr
         static_for<0, Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
             const double gi = *at(gn + i * geo.dstride, src_offset<i, F_PENDING>(st, geo));
-            const double l = *at(lg_next + i * geo.dstride, offset_at<cx(i), cy(i), cz(i)>(st, geo));
+            const uint32_t up = offset_at<cx(i), cy(i), cz(i)>(st, geo);
+            double l = *at(lg_next + i * geo.dstride, up);
+            if constexpr (LG == LG_PULLED_KEEP) l = (1.0 - cp.omega_g) * l + *at(b_next, up);
+            if constexpr (LG != LG_GATHER) *at(p_out + i * geo.dstride, off) = l;
             const double cu = cdot<i>(ux, uy, uz);
             const double E = 1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq;
             gs.template add<i>(l, cu, E, 0.0);
@@ -1091,11 +1112,12 @@ __global__ __launch_bounds__(P::TPB) void k_adjoint_binary_init(const double* __
 
 // Stencil part: b(s) = a_phi(s) - 6 a_lap(s) + sum_a [a_G_a(s - e_a) - a_G_a(s + e_a)] / 2
 //                      + sum_a [a_lap(s + e_a) + a_lap(s - e_a)]   (= dL/dphi(s)).
-// INIT: out[s] = b.  Otherwise out is lambda_g^n: out_j(s) = (1 - omega_g)
-// lambda_g^{n+1}_j(s + c_j) + b(s).  Block 0 also adds the K block partials
+// B_ONLY (the reverse of the initialisation, and each step of a sweep in
+// the pair form): out[s] = b.  Otherwise out is lambda_g^n:
+// out_j(s) = (1 - omega_g) lambda_g^{n+1}_j(s + c_j) + b(s).  Block 0 also adds the K block partials
 // the local kernel left (partial[8 b + k], b < nblocks) into sums[0..K), in
 // block order, which saves the step a separate reduction launch.
-template <class P, bool INIT, int K>
+template <class P, bool B_ONLY, int K>
 __global__ __launch_bounds__(P::TPB) void k_adjoint_binary_stencil(const double* __restrict__ afield,
                                                                    const double* __restrict__ lg_next,
                                                                    double* __restrict__ out, Geo geo,
@@ -1120,7 +1142,7 @@ __global__ __launch_bounds__(P::TPB) void k_adjoint_binary_stencil(const double*
         b = b + (al[offset_at<1, 0, 0>(st, geo)] + al[offset_at<-1, 0, 0>(st, geo)]);
         b = b + (al[offset_at<0, 1, 0>(st, geo)] + al[offset_at<0, -1, 0>(st, geo)]);
         b = b + (al[offset_at<0, 0, 1>(st, geo)] + al[offset_at<0, 0, -1>(st, geo)]);
-        if constexpr (INIT) {
+        if constexpr (B_ONLY) {
             out[off] = b;
         } else {
             static_for<0, Q>([&](auto I) {
@@ -1131,6 +1153,26 @@ __global__ __launch_bounds__(P::TPB) void k_adjoint_binary_stencil(const double*
         }
     }
     if (blockIdx.x == 0) final_sums<P::TPB, K>(partial, nblocks, sums, 0.0, 0.0, 1);
+}
+
+// lambda_g^n_j(s) = (1 - omega_g) P^n_j(s) + b^n(s): the pair form of the
+// local kernel (LG_PULLED_KEEP) back to canonical lambda_g.  Pointwise, so
+// pn and out may be the same array (hence no __restrict__ on them).
+template <class P>
+__global__ __launch_bounds__(P::TPB) void k_adjoint_binary_combine(const double* pn,
+                                                                   const double* __restrict__ b, double* out,
+                                                                   Geo geo, double omega_g) {
+    const Column col = column_of_thread<P>(geo);
+    for (int v = 0; v < P::TZ; ++v) {
+        const Site st = site_at(col, v, geo);
+        if (!st.active) continue;
+        const uint32_t off = offset_at<0, 0, 0>(st, geo);
+        const double bs = b[off];
+        static_for<0, Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            *at(out + i * geo.dstride, off) = (1.0 - omega_g) * *at(pn + i * geo.dstride, off) + bs;
+        });
+    }
 }
 
 // ---------------------------------------------------------------------------

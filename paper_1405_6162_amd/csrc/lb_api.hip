@@ -570,6 +570,28 @@ int by_storage(lb_ctx* c, F&& fn) {
 
 }  // namespace
 
+namespace {
+
+// True when two device ranges [a, a + na) and [b, b + nb) (in doubles) overlap.
+bool overlaps(const double* a, size_t na, const double* b, size_t nb) {
+    if (!a || !b) return false;
+    return a < b + nb && b < a + na;
+}
+
+template <int LG>
+void launch_adjoint_binary_local(lb_ctx* c, bool pending, const double* f, const double* g, const double* phi,
+                                 const double* lf_next, const double* lg_next, const double* b_next, double* lf_n,
+                                 double* p_out, double* afield, const Geo& geo, const CollParams<double>& cp) {
+    if (pending)
+        k_adjoint_binary<Pol, true, LG><<<c->grid(), c->block(), 0, c->stream>>>(
+            f, g, phi, lf_next, lg_next, b_next, lf_n, p_out, afield, c->partial(), geo, cp);
+    else
+        k_adjoint_binary<Pol, false, LG><<<c->grid(), c->block(), 0, c->stream>>>(
+            f, g, phi, lf_next, lg_next, b_next, lf_n, p_out, afield, c->partial(), geo, cp);
+}
+
+}  // namespace
+
 extern "C" {
 
 int lb_workspace_bytes(const lb_params* p, size_t* bytes) {
@@ -758,11 +780,11 @@ int lb_adjoint_step_binary(lb_ctx* c, const double* f, const double* g, const do
     {
         Timed t(c, LB_K_ADJOINT);
         if (pending)
-            k_adjoint_binary<Pol, true><<<c->grid(), c->block(), 0, c->stream>>>(f, g, phi, lf_next, lg_next, lf_n,
-                                                                               afield, c->partial(), geo, cp);
+            k_adjoint_binary<Pol, true, LG_GATHER><<<c->grid(), c->block(), 0, c->stream>>>(
+                f, g, phi, lf_next, lg_next, nullptr, lf_n, nullptr, afield, c->partial(), geo, cp);
         else
-            k_adjoint_binary<Pol, false><<<c->grid(), c->block(), 0, c->stream>>>(f, g, phi, lf_next, lg_next, lf_n,
-                                                                                afield, c->partial(), geo, cp);
+            k_adjoint_binary<Pol, false, LG_GATHER><<<c->grid(), c->block(), 0, c->stream>>>(
+                f, g, phi, lf_next, lg_next, nullptr, lf_n, nullptr, afield, c->partial(), geo, cp);
     }
     {
         Timed t(c, LB_K_ADJOINT);
@@ -806,6 +828,104 @@ int lb_adjoint_step(lb_ctx* c, const double* f, int f_pending, const double* lam
                                                                          c->canonical_geo(), 1.0 / c->p.tau_f);
     }
     k_sums_final<Pol, 1><<<1, c->block(), 0, c->stream>>>(c->partial(), c->L.nblocks, domega, 0.0, 0.0, 1);
+    return launch_status();
+}
+
+int lb_adjoint_segment(lb_ctx* c, const double* f0, const double* post, int32_t length, double* lam, double* work,
+                       double* domega) {
+    if (!c || !f0 || !lam || !work || !domega || length < 1) return LB_EINVAL;
+    if (length > 1 && !post) return LB_EINVAL;
+    if (c->p.model != LB_SINGLE || c->p.storage != LB_F64 || c->p.collision != LB_BGK) return LB_ENOTSUP;
+    const size_t n19 = (size_t)Q * c->L.nsite;
+    const size_t npost = length > 1 ? (size_t)(length - 1) * n19 : 0;
+    if (overlaps(lam, n19, work, n19) || overlaps(lam, n19, f0, n19) || overlaps(work, n19, f0, n19) ||
+        overlaps(lam, n19, post, npost) || overlaps(work, n19, post, npost) || overlaps(domega, 1, lam, n19) ||
+        overlaps(domega, 1, work, n19) || overlaps(domega, 1, f0, n19) || overlaps(domega, 1, post, npost))
+        return LB_EINVAL;
+    c->launched = true;
+    const Geo geo = c->canonical_geo();
+    const double omega = 1.0 / c->p.tau_f;
+    double* cur = lam;            // lambda^{n+1}
+    double* nxt = work;
+    for (int32_t n = length - 1; n >= 0; --n) {
+        {
+            Timed t(c, LB_K_ADJOINT);
+            if (n > 0)
+                k_adjoint<Pol, true><<<c->grid(), c->block(), 0, c->stream>>>(post + (size_t)(n - 1) * n19, cur, nxt,
+                                                                            c->partial(), geo, omega);
+            else
+                k_adjoint<Pol, false><<<c->grid(), c->block(), 0, c->stream>>>(f0, cur, nxt, c->partial(), geo, omega);
+        }
+        k_sums_final<Pol, 1><<<1, c->block(), 0, c->stream>>>(c->partial(), c->L.nblocks, domega, 0.0, 0.0, 1);
+        std::swap(cur, nxt);
+    }
+    if (cur != lam) {
+        Timed t(c, LB_K_OTHER);
+        if (hipMemcpyAsync(lam, cur, n19 * sizeof(double), hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+            return LB_EDEVICE;
+    }
+    return launch_status();
+}
+
+int lb_adjoint_segment_binary(lb_ctx* c, const double* f0, const double* g0, const double* post, const double* phi,
+                              int32_t length, double* lf, double* lg, double* work, double* grads) {
+    if (!c || !f0 || !g0 || !lf || !lg || !work || !grads || length < 1) return LB_EINVAL;
+    if (length > 1 && !post) return LB_EINVAL;
+    if (c->p.model != LB_BINARY || c->p.storage != LB_F64 || c->p.collision != LB_BGK) return LB_ENOTSUP;
+    const size_t N = c->L.nsite, n19 = (size_t)Q * N;
+    const size_t npost = length > 1 ? (size_t)(length - 1) * 2 * n19 : 0;
+    const size_t nphi = phi && length > 1 ? (size_t)(length - 1) * N : 0;
+    struct R { const double* p; size_t n; };
+    const R outs[3] = {{lf, n19}, {lg, n19}, {work, 2 * n19}};
+    const R all[8] = {{lf, n19}, {lg, n19}, {work, 2 * n19}, {f0, n19}, {g0, n19}, {post, npost}, {phi, nphi},
+                      {grads, 3}};
+    for (int o = 0; o < 3; ++o)                      // all[o] is outs[o]
+        for (int a = 0; a < 8; ++a)
+            if (a != o && overlaps(outs[o].p, outs[o].n, all[a].p, all[a].n)) return LB_EINVAL;
+    if (overlaps(grads, 3, f0, n19) || overlaps(grads, 3, g0, n19) || overlaps(grads, 3, post, npost))
+        return LB_EINVAL;
+    c->launched = true;
+    const Geo geo = c->canonical_geo();
+    const auto cp = coll_params<double>(c);
+    double* afield = (double*)c->fbuf(1 - c->cur);   // spare state buffer: 19 dstride >= 6 N doubles
+    double* bfield = afield + 5 * N;
+    double* lf_cur = lf;                              // lambda_f^{n+1}
+    double* lf_nxt = work;
+    double* p_cur = lg;                               // lambda_g^{n+1} (first step) or P^{n+1}
+    double* p_nxt = work + n19;
+    for (int32_t n = length - 1; n >= 0; --n) {
+        Timed t(c, LB_K_ADJOINT);
+        const bool pending = n > 0;
+        const double* fn = pending ? post + (size_t)(n - 1) * 2 * n19 : f0;
+        const double* gn = pending ? fn + n19 : g0;
+        const double* ph = (phi && n < length - 1) ? phi + (size_t)n * N : nullptr;
+        if (!ph) {
+            double* p = (double*)c->phi();
+            if (pending) k_phi<Pol, double, true><<<c->grid(), c->block(), 0, c->stream>>>(gn, p, geo, 0.0);
+            else k_phi<Pol, double, false><<<c->grid(), c->block(), 0, c->stream>>>(gn, p, geo, 0.0);
+            ph = p;
+        }
+        if (n == length - 1)
+            launch_adjoint_binary_local<LG_GATHER_KEEP>(c, pending, fn, gn, ph, lf_cur, p_cur, nullptr, lf_nxt,
+                                                        p_nxt, afield, geo, cp);
+        else
+            launch_adjoint_binary_local<LG_PULLED_KEEP>(c, pending, fn, gn, ph, lf_cur, p_cur, bfield, lf_nxt,
+                                                        p_nxt, afield, geo, cp);
+        k_adjoint_binary_stencil<Pol, true, 3><<<c->grid(), c->block(), 0, c->stream>>>(
+            afield, nullptr, bfield, geo, 1.0, c->partial(), c->L.nblocks, grads);
+        std::swap(lf_cur, lf_nxt);
+        std::swap(p_cur, p_nxt);
+    }
+    {
+        // lambda_g^{s0} = (1 - omega_g) P^{s0} + b^{s0}, into lg (in place when P^{s0} is there)
+        Timed t(c, LB_K_ADJOINT);
+        k_adjoint_binary_combine<Pol><<<c->grid(), c->block(), 0, c->stream>>>(p_cur, bfield, lg, geo, cp.omega_g);
+    }
+    if (lf_cur != lf) {
+        Timed t(c, LB_K_OTHER);
+        if (hipMemcpyAsync(lf, lf_cur, n19 * sizeof(double), hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+            return LB_EDEVICE;
+    }
     return launch_status();
 }
 

@@ -81,6 +81,8 @@ _SIGNATURES = {
     "lb_set_tau": (_int, [_vp, ctypes.c_double]),
     "lb_step_record": (_int, [_vp, _i32, _vp, _vp]),
     "lb_adjoint_step": (_int, [_vp, _vp, _int, _vp, _vp, _vp]),
+    "lb_adjoint_segment": (_int, [_vp, _vp, _vp, _i32, _vp, _vp, _vp]),
+    "lb_adjoint_segment_binary": (_int, [_vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp]),
     "lb_mask_index": (_int, [_vp, _vp, _vp, _vp]),
     "lb_get_sites": (_int, [_vp, _vp, ctypes.c_int64, _vp, _vp]),
     "lb_set_sites": (_int, [_vp, _vp, ctypes.c_int64, _vp, _vp]),
@@ -210,6 +212,16 @@ def lb_adjoint_init_binary(ctx, rho, u, phi, lf0, lg0, dphi, drho, du, dkappa):
     _check("lb_adjoint_init_binary", _lib.lb_adjoint_init_binary(
         ctx, _ptr(rho), _ptr(u), _ptr(phi), _ptr(lf0), _ptr(lg0), _ptr(dphi), _ptr(drho), _ptr(du),
         _ptr(dkappa)))
+
+
+def lb_adjoint_segment(ctx, f0, post, length, lam, work, domega):
+    _check("lb_adjoint_segment", _lib.lb_adjoint_segment(ctx, _ptr(f0), _ptr(post), int(length), _ptr(lam),
+                                                         _ptr(work), _ptr(domega)))
+
+
+def lb_adjoint_segment_binary(ctx, f0, g0, post, phi, length, lf, lg, work, grads):
+    _check("lb_adjoint_segment_binary", _lib.lb_adjoint_segment_binary(
+        ctx, _ptr(f0), _ptr(g0), _ptr(post), _ptr(phi), int(length), _ptr(lf), _ptr(lg), _ptr(work), _ptr(grads)))
 
 
 def lb_mask_index(ctx, mask, index, count):

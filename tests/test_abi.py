@@ -25,6 +25,12 @@ def lib():
     return lb.load()
 
 
+# The argument checks below hand the library made-up device addresses; a
+# check that wrongly let one through would queue a kernel on them.  Without a
+# GPU that launch only fails; with one it would fault, so they run GPU-less.
+no_device = pytest.mark.skipif(os.path.exists("/dev/kfd"), reason="fake device pointers: run where no GPU is visible")
+
+
 def test_header_declares_the_boundary():
     syms = _declared_symbols()
     for name in ("lb_create", "lb_init_equilibrium", "lb_collide", "lb_propagate", "lb_step",
@@ -123,6 +129,7 @@ def test_vvl_values(lib):
         assert (_ws(p)[0] == lb.LB_OK) == ok, v
 
 
+@no_device
 def test_create_checks_workspace_without_device_work(lib):
     p = lb.make_params(6, 5, 4, model=lb.LB_BINARY)
     _, need = _ws(p)
@@ -153,6 +160,20 @@ def test_create_checks_workspace_without_device_work(lib):
         assert lib.lb_adjoint_step_binary(ctx, fake, a, None, 0, b2, c2, d2, None, fake) == lb.LB_EINVAL
         assert lib.lb_adjoint_step_binary(ctx, fake, a, e2, 0, b2, c2, e2, d2, fake) == lb.LB_EINVAL  # phi aliased
         assert lib.lb_adjoint_init_binary(ctx, fake, fake, fake, fake, fake, None, fake, fake, fake) == lb.LB_EINVAL
+        # segment sweeps: bad lengths, missing records and overlapping arrays are refused before any launch
+        n = 6 * 5 * 4
+        w = ctypes.c_void_p(9 << 20)
+        seg = lib.lb_adjoint_segment_binary
+        assert seg(ctx, fake, a, b2, None, 0, c2, d2, w, e2) == lb.LB_EINVAL               # length 0
+        assert seg(ctx, fake, a, None, None, 2, c2, d2, w, e2) == lb.LB_EINVAL             # no records
+        assert seg(ctx, fake, a, b2, None, 1, c2, c2, w, e2) == lb.LB_EINVAL               # lf == lg
+        inside_work = ctypes.c_void_p((9 << 20) + 8 * 19 * n)                             # work holds 38 N
+        assert seg(ctx, fake, a, b2, None, 1, c2, inside_work, w, e2) == lb.LB_EINVAL
+        inside_post = ctypes.c_void_p(b2.value + 8 * 38 * n)                              # post holds 2 x 38 N
+        assert seg(ctx, fake, a, b2, None, 3, inside_post, d2, w, e2) == lb.LB_EINVAL
+        assert seg(ctx, fake, a, b2, None, 1, c2, d2, w, c2) == lb.LB_EINVAL               # grads inside lf
+        assert seg(ctx, fake, a, b2, None, 1, c2, d2, w, None) == lb.LB_EINVAL
+        assert lib.lb_adjoint_segment(ctx, fake, None, 1, c2, d2, e2) == lb.LB_ENOTSUP     # binary context
         # set_params: physics may change, layout and deviation references may not
         q = lb.make_params(6, 5, 4, model=lb.LB_BINARY, kappa=0.05, mobility=0.3)
         assert lib.lb_set_params(ctx, ctypes.byref(q)) == lb.LB_OK
@@ -168,6 +189,7 @@ def test_create_checks_workspace_without_device_work(lib):
         assert lib.lb_destroy(ctx) == lb.LB_OK
 
 
+@no_device
 def test_single_model_rejects_phi(lib):
     p = lb.make_params(4, 4, 4)
     _, need = _ws(p)
@@ -184,6 +206,14 @@ def test_single_model_rejects_phi(lib):
         a = [ctypes.c_void_p((k + 2) << 20) for k in range(7)]
         assert lib.lb_adjoint_step_binary(ctx, a[0], a[1], None, 0, a[2], a[3], a[4], a[5], a[6]) == lb.LB_ENOTSUP
         assert lib.lb_adjoint_init_binary(ctx, *a, fake, fake, fake) == lb.LB_ENOTSUP
+        n19 = 19 * 4 * 4 * 4
+        assert lib.lb_adjoint_segment(ctx, a[0], None, 0, a[1], a[2], a[3]) == lb.LB_EINVAL   # length 0
+        assert lib.lb_adjoint_segment(ctx, a[0], None, 2, a[1], a[2], a[3]) == lb.LB_EINVAL   # no records
+        assert lib.lb_adjoint_segment(ctx, a[0], None, 1, a[1], a[1], a[3]) == lb.LB_EINVAL   # work == lam
+        assert lib.lb_adjoint_segment(ctx, a[0], None, 1, a[1], a[2], a[0]) == lb.LB_EINVAL   # domega is f0
+        lam_in_post = ctypes.c_void_p(a[4].value + 8 * n19)                                   # post holds 2 x 19 N
+        assert lib.lb_adjoint_segment(ctx, a[0], a[4], 3, lam_in_post, a[2], a[3]) == lb.LB_EINVAL
+        assert lib.lb_adjoint_segment_binary(ctx, a[0], a[1], None, None, 1, a[2], a[3], a[4], a[5]) == lb.LB_ENOTSUP
     finally:
         assert lib.lb_destroy(ctx) == lb.LB_OK
 

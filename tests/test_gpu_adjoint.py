@@ -150,3 +150,52 @@ def test_shear_wave_64_adjoint_vs_finite_differences(lbgpu):
     print("adjoint vs FD: worst component %.2e, tau rel %.2e (dL/dtau %.4e)"
           % (worst, abs(fd_tau - taut.grad.item()) / abs(fd_tau), taut.grad.item()), flush=True)
     assert abs(fd_tau - taut.grad.item()) <= 1e-6 * abs(fd_tau)
+
+
+@pytest.mark.parametrize("length", [1, 2, 5])
+def test_segment_sweep_equals_per_step_calls(lbgpu, length):
+    """lb_adjoint_segment over a recorded segment: the same kernels in the
+    same order as `length` per-step calls, so equal bit for bit (lambda and
+    the accumulated dL/domega), whichever buffer the last step lands in; and
+    the oracle's reverse sweep over the same states."""
+    nx, ny, nz, tau = 67, 9, 5, 0.85
+    print("case single segment length=%d" % length, flush=True)
+    f0 = _state(nx, ny, nz, seed=21)
+    rng = np.random.default_rng(22)
+    lam_T = rng.standard_normal(f0.shape)
+    lat = lbgpu.Lattice(nx, ny, nz, tau_f=tau)
+    lat.set_state(f0)
+    dev = lambda a: torch.as_tensor(a, device="cuda").contiguous()
+    f0t = dev(f0)
+    post = None
+    if length > 1:
+        post = torch.empty((length - 1, 19, nz, ny, nx), dtype=torch.float64, device="cuda")
+        lbgpu.lb_set_stream(lat.ctx, lbgpu._stream())
+        lbgpu.lb_step_record(lat.ctx, length - 1, post)
+    # per-step calls
+    lam = dev(lam_T)
+    dw_steps = torch.full((1,), 0.125, dtype=torch.float64, device="cuda")
+    for n in range(length - 1, -1, -1):
+        out = torch.empty_like(lam)
+        if n == 0:
+            lbgpu.lb_adjoint_step(lat.ctx, f0t, lam, out, dw_steps)
+        else:
+            lbgpu.lb_adjoint_step(lat.ctx, post[n - 1], lam, out, dw_steps, f_pending=True)
+        lam = out
+    # one segment call
+    lam_seg = dev(lam_T)
+    work = torch.empty_like(lam_seg)
+    dw_seg = torch.full((1,), 0.125, dtype=torch.float64, device="cuda")
+    lbgpu.lb_adjoint_segment(lat.ctx, f0t, post, length, lam_seg, work, dw_seg)
+    assert torch.equal(lam_seg, lam)
+    assert torch.equal(dw_seg, dw_steps)
+    # the oracle over the same states
+    states = [f0]
+    for _ in range(length - 1):
+        states.append(O.step_single(states[-1], tau, 1))
+    lam_o, dw_o = lam_T, 0.0
+    for n in range(length - 1, -1, -1):
+        lam_o, d = O.adjoint_step_single(states[n], lam_o, tau)
+        dw_o += d
+    assert relerr(lam_seg.cpu().numpy(), lam_o) < 1e-12
+    assert abs(dw_seg.item() - 0.125 - dw_o) <= 1e-12 * max(abs(dw_o), np.abs(lam_o).max())

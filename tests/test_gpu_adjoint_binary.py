@@ -196,3 +196,65 @@ def test_binary_rollout_central_differences_32(lbgpu):
     fd_m = (L(phi, mobility=prm.mobility + eps) - L(phi, mobility=prm.mobility - eps)) / (2 * eps)
     assert abs(fd_k - gk) <= 1e-6 * abs(gk), (fd_k, gk)
     assert abs(fd_m - gm) <= 1e-6 * abs(gm), (fd_m, gm)
+
+
+@pytest.mark.parametrize("given_phi", [False, True])
+@pytest.mark.parametrize("length", [1, 2, 5])
+def test_binary_segment_sweep(lbgpu, length, given_phi):
+    """lb_adjoint_segment_binary, which carries lambda_g between steps as the
+    pair (P, b), against `length` per-step calls on the same recorded segment
+    (the same arithmetic on the same operands: equal to rounding), and
+    against the oracle's reverse sweep over the same states."""
+    nx, ny, nz = 67, 9, 5
+    print("case binary segment length=%d phi=%s" % (length, given_phi), flush=True)
+    prm = O.Params(tau_f=0.9, kappa=0.05, mobility=0.3)
+    f0, g0 = _state(nx, ny, nz, seed=23)
+    rng = np.random.default_rng(24)
+    lf_T, lg_T = rng.standard_normal(f0.shape), rng.standard_normal(g0.shape)
+    lat = lbgpu.Lattice(nx, ny, nz, model=lbgpu.LB_BINARY, **_params(prm))
+    lat.set_state(f0, g0)
+    f0t, g0t = dev(f0), dev(g0)
+    post = phi = None
+    lbgpu.lb_set_stream(lat.ctx, lbgpu._stream())
+    if length > 1:
+        post = torch.empty((length - 1, 38, nz, ny, nx), dtype=torch.float64, device="cuda")
+        phi = torch.empty((length - 1, nz, ny, nx), dtype=torch.float64, device="cuda") if given_phi else None
+        lbgpu.lb_step_record(lat.ctx, length - 1, post, phi)
+    # per-step calls
+    lf, lg = dev(lf_T), dev(lg_T)
+    g_steps = torch.full((3,), 0.25, dtype=torch.float64, device="cuda")
+    for n in range(length - 1, -1, -1):
+        lf_n, lg_n = torch.empty_like(lf), torch.empty_like(lg)
+        ph = phi[n] if phi is not None and n < length - 1 else None
+        if n == 0:
+            lbgpu.lb_adjoint_step_binary(lat.ctx, f0t, g0t, lf, lg, lf_n, lg_n, g_steps, phi=ph)
+        else:
+            lbgpu.lb_adjoint_step_binary(lat.ctx, post[n - 1, :19], post[n - 1, 19:], lf, lg, lf_n, lg_n, g_steps,
+                                         pending=True, phi=ph)
+        lf, lg = lf_n, lg_n
+    # one segment call
+    lf_s, lg_s = dev(lf_T), dev(lg_T)
+    work = torch.empty((38, nz, ny, nx), dtype=torch.float64, device="cuda")
+    g_seg = torch.full((3,), 0.25, dtype=torch.float64, device="cuda")
+    lbgpu.lb_adjoint_segment_binary(lat.ctx, f0t, g0t, post, phi, length, lf_s, lg_s, work, g_seg)
+    a, b = lf_s.cpu().numpy(), lf.cpu().numpy()
+    print("  max |diff| lf %.3g lg %.3g grads %.3g" % (np.abs(a - b).max(), (lg_s - lg).abs().max().item(),
+                                                      (g_seg - g_steps).abs().max().item()), flush=True)
+    assert relerr(a, b) < 1e-14
+    assert relerr(lg_s.cpu().numpy(), lg.cpu().numpy()) < 1e-14
+    assert relerr(g_seg.cpu().numpy() - 0.25, g_steps.cpu().numpy() - 0.25) < 1e-13
+    # the oracle over the same states
+    states = [(f0, g0)]
+    for _ in range(length - 1):
+        states.append(O.step_binary(*states[-1], prm, 1))
+    lf_o, lg_o = lf_T, lg_T
+    tot = {"omega_f": 0.0, "omega_g": 0.0, "kappa": 0.0}
+    for n in range(length - 1, -1, -1):
+        lf_o, lg_o, d = O.adjoint_step_binary(*states[n], lf_o, lg_o, prm)
+        for k in tot:
+            tot[k] += d[k]
+    assert relerr(lf_s.cpu().numpy(), lf_o) < 1e-12
+    assert relerr(lg_s.cpu().numpy(), lg_o) < 1e-12
+    got = g_seg.cpu().numpy() - 0.25
+    for k, name in enumerate(("omega_f", "omega_g", "kappa")):
+        assert abs(got[k] - tot[name]) <= 1e-12 * max(abs(tot[name]), 1.0), name

@@ -26,7 +26,7 @@ class _Lattice:
                                             gamma=prm.gamma)
         self.ctx = self
         self.f = self.g = None
-        self.calls = {"record": 0, "adjoint": 0, "phi_given": 0}
+        self.calls = {"record": 0, "adjoint": 0, "phi_given": 0, "segment": 0}
 
     def set_params(self, **kw):
         for k, v in kw.items():
@@ -108,14 +108,45 @@ def _adjoint_single(ctx, f, lam, lam_n, domega, f_pending=False):
     domega += dw
 
 
+def _segment_binary(ctx, f0, g0, post, phi, length, lf, lg, work, grads):
+    """The segment sweep as `length` oracle steps, updating lf, lg in place."""
+    assert work.shape[0] == 38 and length >= 1 and (post is not None or length == 1)
+    ctx.calls["segment"] += 1
+    a, b = lf.clone(), lg.clone()
+    for n in range(length - 1, -1, -1):
+        ph = phi[n] if phi is not None and n < length - 1 else None
+        a_n, b_n = torch.empty_like(a), torch.empty_like(b)
+        if n == 0:
+            _adjoint_binary(ctx, f0, g0, a, b, a_n, b_n, grads, phi=ph)
+        else:
+            _adjoint_binary(ctx, post[n - 1, :19], post[n - 1, 19:], a, b, a_n, b_n, grads, pending=True, phi=ph)
+        a, b = a_n, b_n
+    lf.copy_(a)
+    lg.copy_(b)
+
+
+def _segment_single(ctx, f0, post, length, lam, work, domega):
+    assert work.shape == lam.shape and length >= 1 and (post is not None or length == 1)
+    ctx.calls["segment"] += 1
+    a = lam.clone()
+    for n in range(length - 1, -1, -1):
+        a_n = torch.empty_like(a)
+        if n == 0:
+            _adjoint_single(ctx, f0, a, a_n, domega)
+        else:
+            _adjoint_single(ctx, post[n - 1], a, a_n, domega, f_pending=True)
+        a = a_n
+    lam.copy_(a)
+
+
 @pytest.fixture
 def fake_lib(monkeypatch):
     monkeypatch.setattr(lb, "_stream", lambda: None)
     monkeypatch.setattr(lb, "lb_set_stream", lambda ctx, s: None)
     monkeypatch.setattr(lb, "lb_step_record", _record)
-    monkeypatch.setattr(lb, "lb_adjoint_step_binary", _adjoint_binary)
+    monkeypatch.setattr(lb, "lb_adjoint_segment_binary", _segment_binary)
     monkeypatch.setattr(lb, "lb_adjoint_init_binary", _adjoint_init_binary)
-    monkeypatch.setattr(lb, "lb_adjoint_step", _adjoint_single)
+    monkeypatch.setattr(lb, "lb_adjoint_segment", _segment_single)
 
 
 @pytest.mark.parametrize("T,K", [(0, 3), (1, 1), (5, 1), (5, 5), (5, 8), (7, 3), (6, 2)])
@@ -134,6 +165,7 @@ def test_binary_rollout_checkpoint_logic(fake_lib, T, K):
     assert abs(loss.item() - loss_o) <= 1e-14 * abs(loss_o)
     loss.backward()
     assert lat.calls["adjoint"] == T                       # one adjoint step per step
+    assert lat.calls["segment"] == len(range(0, T, K))     # one sweep call per segment
     assert lat.calls["record"] == sum(1 for s in range(0, T, K) if min(K, T - s) > 1)
     # every step but the last of each segment longer than one step reads a recorded phi
     assert lat.calls["phi_given"] == sum(min(K, T - s) - 1 for s in range(0, T, K) if min(K, T - s) > 1)
@@ -162,6 +194,7 @@ def test_single_rollout_checkpoint_logic(fake_lib, T, K):
     assert abs(loss.item() - loss_o) <= 1e-14 * abs(loss_o)
     loss.backward()
     assert lat.calls["adjoint"] == T
+    assert lat.calls["segment"] == len(range(0, T, K))
     np.testing.assert_allclose(f.grad.numpy(), g_o, rtol=0, atol=1e-13 * np.abs(g_o).max())
     if T > 0:
         assert abs(t.grad.item() - dtau_o) <= 1e-12 * abs(dtau_o)
