@@ -292,7 +292,9 @@ int lb_set_sites(lb_ctx* ctx, const int32_t* index, int64_t m, const void* f_pac
 
 /* Per-kernel timing with HIP events on the context's stream.
  * lb_profile(ctx, 1) starts recording an event pair around every kernel
- * launch (and clears earlier records); lb_profile(ctx, 0) stops.
+ * launch (and clears earlier records); lb_profile(ctx, 0) stops.  The events
+ * are created without the system-scope fence (hipEventDisableSystemFence):
+ * they time the work between them but do not publish its memory to the host.
  * lb_kernel_times waits for the recorded events and returns, for kernel
  * class `kind`, the summed duration in milliseconds and the launch count. */
 #define LB_K_COLLIDE  0   /* collide / fused pull-stream + collide */
