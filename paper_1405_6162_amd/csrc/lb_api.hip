@@ -175,9 +175,10 @@ struct lb_ctx {
 
     // Timing-only events.  An ordinary event record ends with a system-scope
     // fence (cache write-back and invalidation); between two dependent
-    // launches that left an 11 us gap in the kernel trace of the 128^3 binary
-    // step with profiling on.  Without it the profiled 64^3 adjoint rollout
-    // runs 12% faster and the 128^3 binary step 1%.  The events are only
+    // launches of the 128^3 binary step with profiling on, the rocprofv3
+    // kernel trace shows 11 us gaps with it and 8.5 us without.  Without it
+    // the profiled 64^3 adjoint rollout runs 12% faster and the 128^3 binary
+    // step 1%.  The events are only
     // ever read by lb_kernel_times.
     hipEvent_t take_event() {
         if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
