@@ -143,6 +143,27 @@ def copy_probe(torch, nbytes=2 << 30, reps=10):
     return {"bytes_per_launch": 2 * nbytes, "GB/s": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
 
 
+def pull_copy_ceiling(lb, lat, bytes_per_launch, launches=10):
+    """What the step's memory access pattern reaches with no arithmetic:
+    lb_propagate on the same lattice (the same 19 pulls and 19 nontemporal
+    stores per distribution and site as the step, the same tiles, strides and
+    launch shape; both distributions of the binary fluid in one launch),
+    timed with the same events.  It changes the lattice state."""
+    lb.lb_set_stream(lat.ctx, lb._stream())
+    lb.lb_propagate(lat.ctx)          # after lb_step the state is pending: from here every call launches
+    lb.lb_profile(lat.ctx, True)
+    for _ in range(launches):
+        lb.lb_propagate(lat.ctx)
+    lb.lb_profile(lat.ctx, False)
+    ms, n = lb.lb_kernel_times(lat.ctx, lb.LB_K_STREAM)
+    avg = ms / max(n, 1)
+    gbs = bytes_per_launch / (avg * 1e-3) / 1e9 if n else 0.0
+    kernel = "k_stream2 (f and g)" if lat.model == lb.LB_BINARY else "k_stream"
+    return {"kernel": kernel + ": the step's pulls and stores without its arithmetic (lb_propagate)",
+            "GB/s": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4), "avg_launch_ms": round(avg, 5),
+            "launches": n}
+
+
 def bench_adjoint(args, n, desc, T=200, K=20):
     """Forward rollout + backward (recompute + adjoint kernel) per timed
     iteration; a step here is one forward step plus one adjoint step."""
@@ -506,6 +527,9 @@ def main():
     nsite = n ** 3
     sums = lat.conserved_sums().cpu()
     finite = bool(torch.isfinite(sums).all())
+    alg = algorithmic_bytes(model, storage)
+    ceiling = pull_copy_ceiling(lb, lat, alg["collide"] * nsite)
+    log("bench: pull-copy ceiling %s GB/s" % ceiling["GB/s"])
     lat.close()
     if not finite:
         print("non-finite state after the timed steps", file=sys.stderr)
@@ -513,7 +537,6 @@ def main():
 
     seconds = wall
     mlups = nsite * args.steps / seconds / 1e6
-    alg = algorithmic_bytes(model, storage)
     col_avg_ms = col_ms / max(col_n, 1)
     achieved = alg["collide"] * nsite / (col_avg_ms * 1e-3) / 1e9
     step_bytes = alg["collide"]
@@ -545,7 +568,9 @@ def main():
             "bytes_per_site": alg["collide"],
             "avg_launch_ms": round(col_avg_ms, 5),
             "launches": col_n,
+            "frac_of_pull_copy": round(achieved / ceiling["GB/s"], 4) if ceiling["GB/s"] else None,
         },
+        "pull_copy_ceiling": ceiling,
         "step_roofline": {
             "bytes_per_site": step_bytes,
             "GB/s": round(step_bytes * nsite * args.steps / seconds / 1e9, 1),

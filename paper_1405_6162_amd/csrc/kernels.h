@@ -526,6 +526,31 @@ __global__ __launch_bounds__(P::TPB) void k_stream(const S* __restrict__ src, S*
     }
 }
 
+// Both distributions of the binary fluid in one launch: 38 pulls and 38
+// stores per site, the memory traffic of the binary step without its
+// arithmetic (what the step's access pattern can reach on this memory
+// system), and one launch instead of two for lb_propagate.
+template <class P, class S>
+__global__ __launch_bounds__(P::TPB) void k_stream2(const S* __restrict__ fsrc, const S* __restrict__ gsrc,
+                                                    S* __restrict__ fdst, S* __restrict__ gdst, Geo geo,
+                                                    int64_t dst_stride) {
+    const Column col = column_of_thread<P>(geo);
+#pragma unroll
+    for (int v = 0; v < P::TZ; ++v) {
+        const Site st = site_at(col, v, geo);
+        if (!st.active) continue;
+        const uint32_t off = offset_at<0, 0, 0>(st, geo);
+        static_for<0, Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            const uint32_t up = src_offset<i, true>(st, geo);
+            const S fv = ldg<P::nt_load>(fsrc + i * geo.dstride, up);
+            const S gv = ldg<P::nt_load>(gsrc + i * geo.dstride, up);
+            stg<P::nt_store>(fdst + i * dst_stride, off, fv);
+            stg<P::nt_store>(gdst + i * dst_stride, off, gv);
+        });
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Equilibrium initialisation (FP64 arithmetic, stored in S as deviations).
 // ---------------------------------------------------------------------------

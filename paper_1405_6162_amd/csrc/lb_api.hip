@@ -346,9 +346,11 @@ int run_collide(lb_ctx* c) {
 template <class S>
 int run_stream_into(lb_ctx* c, int src, S* f, S* g, int64_t stride) {
     Timed t(c, LB_K_STREAM);
-    k_stream<Pol, S><<<c->grid(), c->block(), 0, c->stream>>>((const S*)c->fbuf(src), f, c->geo(), stride);
     if (c->p.model == LB_BINARY)
-        k_stream<Pol, S><<<c->grid(), c->block(), 0, c->stream>>>((const S*)c->gbuf(src), g, c->geo(), stride);
+        k_stream2<Pol, S><<<c->grid(), c->block(), 0, c->stream>>>((const S*)c->fbuf(src), (const S*)c->gbuf(src), f,
+                                                                   g, c->geo(), stride);
+    else
+        k_stream<Pol, S><<<c->grid(), c->block(), 0, c->stream>>>((const S*)c->fbuf(src), f, c->geo(), stride);
     return launch_status();
 }
 
