@@ -287,15 +287,21 @@ def bench_adjoint_binary(args, n, desc, T=200, K=20):
     print(json.dumps(out), flush=True)
 
 
+def relative_errors(name, a, ref):
+    """{name: max|a - ref| / max|ref|, name_l2: ||a - ref||_2 / ||ref||_2}, the
+    two per-moment metrics (a vector moment is one array of all components)."""
+    d = a - ref
+    return {name: float(d.abs().max() / ref.abs().max()), name + "_l2": float(d.norm() / ref.norm())}
+
+
 def _moment_errors(lb, ref, other):
-    """Per-moment max-norm relative errors of `other` against `ref` (Lattice
-    objects on the same lattice), and each one's conserved sums."""
+    """Per-moment relative errors (max norm, and L2 as name_l2) of `other`
+    against `ref` (Lattice objects on the same lattice), and both phi fields."""
     r0, u0, p0 = ref.moments()
     r1, u1, p1 = other.moments()
-    rel = lambda a, b: float((a - b).abs().max() / b.abs().max())
-    err = {"rho": rel(r1, r0), "u": rel(u1, u0)}
+    err = dict(relative_errors("rho", r1, r0), **relative_errors("u", u1, u0))
     if p0 is not None:
-        err["phi"] = rel(p1, p0)
+        err.update(relative_errors("phi", p1, p0))
     return err, p0, p1
 
 
@@ -431,16 +437,15 @@ def bench_precision_single(args, n, desc, steps=500):
         s1 = lat.conserved_sums().cpu()
         res[sto] = {"MLUPS": n ** 3 * steps / dt / 1e6, "mass_drift": float(abs(s1[0] - s0[0]) / abs(s0[0]))}
         lats[sto] = lat
-    r0, u0, _ = lats["f64"].moments()
-    r1, u1, _ = lats["f32"].moments()
-    rel = lambda a, b: float((a - b).abs().max() / b.abs().max())
+    err, _, _ = _moment_errors(lb, lats["f64"], lats["f32"])
+    u0 = lats["f64"].moments()[1]
     out = {"metric": METRIC, "value": round(res["f32"]["MLUPS"], 2), "unit": "MLUPS", "n_gpus": 1,
            "steps": steps, "warmup": 0, "ms_per_step": round(n ** 3 / res["f32"]["MLUPS"] / 1e3, 5),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
            "data": "synthetic", "config": {"workload": desc, "nx": n, "ny": n, "nz": n, "seed": 0},
            "reference": {"storage": "f64", "MLUPS": round(res["f64"]["MLUPS"], 2),
                          "speedup": round(res["f32"]["MLUPS"] / res["f64"]["MLUPS"], 3)},
-           "errors_vs_reference": {"rho": rel(r1, r0), "u": rel(u1, u0)},
+           "errors_vs_reference": err,
            "drift": {"f32_mass_rel": res["f32"]["mass_drift"], "f64_mass_rel": res["f64"]["mass_drift"]}}
     out["final_max_abs_u"] = {"f64": float(u0.abs().max())}
     for lat in lats.values():

@@ -108,8 +108,14 @@ def test_bench_host_helpers():
     assert bench.algorithmic_bytes("binary", "f16") == {"collide": 152}
     assert bench.algorithmic_bytes("adjoint", "f64")["adjoint"] == 456
     assert bench.algorithmic_bytes("adjoint_binary", "f64")["adjoint"] == 912
-    # one Fourier mode of wavenumber k: L = 2 pi / k
     import torch
+    # the two per-moment error metrics: max norm and L2, a vector moment as one array
+    ref = torch.tensor([[1.0, 2.5], [-2.0, 0.0]], dtype=torch.float64)
+    got = ref + torch.tensor([[0.0, -0.5], [0.0, 0.0]], dtype=torch.float64)
+    e = bench.relative_errors("u", got, ref)
+    assert e["u"] == pytest.approx(0.5 / 2.5, rel=1e-15)
+    assert e["u_l2"] == pytest.approx(0.5 / np.sqrt(1 + 6.25 + 4), rel=1e-15)
+    # one Fourier mode of wavenumber k: L = 2 pi / k
     n = 32
     x = torch.arange(n, dtype=torch.float64)
     phi = torch.cos(2 * np.pi * 4 * x / n).view(1, 1, n).expand(n, n, n).contiguous()
