@@ -522,6 +522,100 @@ def rollout_gradient(f0, tau, nsteps, seed=velocity_loss_seed):
 
 
 # ---------------------------------------------------------------------------
+# Adjoint of the single-fluid TRT and MRT steps
+# ---------------------------------------------------------------------------
+#
+# Every collision here is f* = f - Omega (f - f^eq(f)) with a constant 19x19
+# relaxation matrix Omega (omega I for BGK).  Its Jacobian is
+# I - Omega (I - J), J = d f^eq / d f, so the adjoint of the collision is
+# lambda -> lambda - (I - J)^T Omega^T lambda, and
+# dL/domega_k = sum_s lambda*^T (d f*/d omega_k) = sum_s (P_k^T lambda*).(f^eq - f)
+# where Omega = sum_k omega_k P_k over the rate groups.  These functions
+# build Omega, P_k and J as explicit matrices per site and apply their
+# transposes: slow, and free of the reductions the kernels use.
+
+MRT_RATES = ("shear", "flux", "bulk", "ghost_even", "ghost_odd")
+
+
+def relaxation_projectors():
+    """{group: P_k (19x19)} with Omega = sum_k P_k / tau_k for the MRT groups:
+    P_k = M^-1 E_k M, E_k selecting the moments of group k (conserved
+    moments belong to no group: f - f^eq has none of them)."""
+    M = mrt_basis()
+    Minv = np.linalg.inv(M)
+    out = {}
+    for k in MRT_RATES:
+        E = np.diag([1.0 if g == k else 0.0 for g in MRT_GROUP])
+        out[k] = Minv @ E @ M
+    return out
+
+
+def relaxation_matrix(taus):
+    """Omega for taus = (shear, flux, bulk, ghost_even, ghost_odd)."""
+    P = relaxation_projectors()
+    return sum(P[k] / t for k, t in zip(MRT_RATES, taus))
+
+
+def equilibrium_jacobian(f):
+    """J[i, j] = d f^eq_i / d f_j at every site, (19, 19, nz, ny, nx), from
+    f^eq_i = w_i rho E_i(u), rho = sum f, u = sum f c / rho:
+    d rho / d f_j = 1, d u_a / d f_j = (c_ja - u_a) / rho."""
+    u, rho = velocity(f)
+    feq = equilibrium_f(rho, u)
+    J = np.empty((NQ, NQ) + rho.shape, dtype=np.result_type(f, rho))
+    for i in range(NQ):
+        cu = C[i, 0] * u[0] + C[i, 1] * u[1] + C[i, 2] * u[2]
+        dEdu = [W[i] * rho * (3.0 * C[i, a] + 9.0 * cu * C[i, a] - 3.0 * u[a]) for a in range(3)]
+        for j in range(NQ):
+            acc = feq[i] / rho
+            for a in range(3):
+                acc = acc + dEdu[a] * (C[j, a] - u[a]) / rho
+            J[i, j] = acc
+    return J
+
+
+def adjoint_step_single_mrt(f_n, lam_next, taus):
+    """Reverse of one MRT step f^{n+1} = propagate(collide_single_mrt(f^n))
+    (TRT and BGK are the special cases of tied times).  lambda*_i(s) =
+    lambda^{n+1}_i(s + c_i); lambda^n = A^T lambda* per site with
+    A = I - Omega (I - J).  Returns (lambda^n, {group: dL/domega_group})."""
+    lam_star = np.empty_like(lam_next)
+    for i in range(NQ):
+        lam_star[i] = neighbour(lam_next[i], C[i])
+    Om = relaxation_matrix(taus)
+    J = equilibrium_jacobian(f_n)
+    eye = np.eye(NQ)
+    # A_ij(s) = delta_ij - sum_k Om_ik (delta_kj - J_kj(s))
+    A = eye[:, :, None, None, None] - np.einsum("ik,kj...->ij...", Om, eye[:, :, None, None, None] - J)
+    lam_n = np.einsum("i...,ij...->j...", lam_star, A)
+    u, rho = velocity(f_n)
+    neq_neg = equilibrium_f(rho, u) - f_n
+    P = relaxation_projectors()
+    grads = {k: np.einsum("i...,ij,j...->...", lam_star, P[k], neq_neg).sum() for k in MRT_RATES}
+    return lam_n, grads
+
+
+def rollout_gradient_mrt(f0, taus, nsteps, seed=velocity_loss_seed):
+    """Gradient of L(f^T) under MRT steps with respect to f^0 and the five
+    relaxation times, by a plain reverse sweep over every stored state.
+    Returns (L, dL/df0, {group: dL/dtau_group})."""
+    states = [f0]
+    f = f0
+    for _ in range(nsteps):
+        f = step_single_mrt(f, taus)
+        states.append(f)
+    loss = velocity_loss(f)
+    lam = seed(f)
+    dw = {k: 0.0 for k in MRT_RATES}
+    for n in range(nsteps - 1, -1, -1):
+        lam, g = adjoint_step_single_mrt(states[n], lam, taus)
+        for k in MRT_RATES:
+            dw[k] = dw[k] + g[k]
+    dtau = {k: -dw[k] / (t * t) for k, t in zip(MRT_RATES, taus)}
+    return loss, lam, dtau
+
+
+# ---------------------------------------------------------------------------
 # Adjoint of the binary-fluid step
 # ---------------------------------------------------------------------------
 #

@@ -142,6 +142,16 @@ def _mut_mrt_bulk_group():
     return tuple(g)
 
 
+def _mut_jacobian_transposed(f):
+    return np.swapaxes(O.equilibrium_jacobian.__wrapped__(f), 0, 1)
+
+
+def _mut_projectors_swapped():
+    P = O.relaxation_projectors.__wrapped__()
+    P["bulk"], P["ghost_even"] = P["ghost_even"], P["bulk"]
+    return P
+
+
 def _swap_weights():
     w = O.W.copy()
     c2 = (O.C * O.C).sum(1)
@@ -180,6 +190,10 @@ MUTATIONS = {
                                     [pins.test_binary_loss_seed_complex_step]),
     "MRT energy-flux polynomial": ("mrt_basis", lambda: _mut_mrt_flux_polynomial(),
                                    [pins.test_mrt_basis_orthogonal_full_rank_and_parity]),
+    "MRT adjoint: equilibrium Jacobian transposed": ("equilibrium_jacobian", _mut_jacobian_transposed,
+                                                     [pins.test_mrt_adjoint_step_matches_complex_step]),
+    "MRT adjoint: bulk and even-ghost projectors swapped": ("relaxation_projectors", _mut_projectors_swapped,
+                                                            [pins.test_mrt_adjoint_step_matches_complex_step]),
 }
 
 # non-callable attributes replaced by a value

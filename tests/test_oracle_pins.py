@@ -434,6 +434,63 @@ def test_adjoint_rollout_matches_complex_step():
     assert abs(d_tau - dtau) <= 1e-11 * abs(d_tau)
 
 
+MRT_TAUS = (0.8, 1.1, 1.3, 0.9, 1.2)        # shear, flux, bulk, ghost_even, ghost_odd
+
+
+def _mrt_case():
+    f = _adjoint_case()
+    rng = np.random.default_rng(5)
+    return f + 1e-3 * rng.standard_normal(f.shape) * O.W[:, None, None, None]
+
+
+def test_mrt_adjoint_step_matches_complex_step():
+    """One MRT step: lambda^n and dL/domega_k of <lambda, step(f)> against
+    complex-step derivatives of the oracle's MRT forward, for f components
+    and for each of the five relaxation times."""
+    f = _mrt_case()
+    lam = np.random.default_rng(6).standard_normal(f.shape)
+    lam_n, g = O.adjoint_step_single_mrt(f, lam, MRT_TAUS)
+    h = 1e-30
+    proj = lambda fc, taus: (lam * O.step_single_mrt(fc, taus)).sum()
+    for (i, s) in inputs.sample_components(f[0].size, 12, seed=7):
+        fc = f.astype(np.complex128)
+        fc.reshape(19, -1)[i, s] += 1j * h
+        d = proj(fc, MRT_TAUS).imag / h
+        assert abs(d - lam_n.reshape(19, -1)[i, s]) <= 1e-13 * np.abs(lam_n).max()
+    for k, name in enumerate(O.MRT_RATES):
+        taus = list(MRT_TAUS)
+        taus[k] = taus[k] + 1j * h
+        d = proj(f.astype(np.complex128), tuple(taus)).imag / h          # dL/dtau_k
+        assert abs(d + g[name] / MRT_TAUS[k] ** 2) <= 1e-12 * abs(d), name
+
+
+def test_mrt_adjoint_with_tied_times_is_bgk():
+    f = _mrt_case()
+    lam = np.random.default_rng(8).standard_normal(f.shape)
+    a, g = O.adjoint_step_single_mrt(f, lam, (0.85,) * 5)
+    b, dw = O.adjoint_step_single(f, lam, 0.85)
+    assert np.abs(a - b).max() <= 1e-13 * np.abs(b).max()
+    assert abs(sum(g.values()) - dw) <= 1e-12 * abs(dw)
+
+
+def test_mrt_rollout_gradient_matches_complex_step():
+    f0 = _adjoint_case()
+    T, h = 4, 1e-30
+    loss, grad_f0, dtau = O.rollout_gradient_mrt(f0, MRT_TAUS, T)
+    assert loss > 0
+    L = lambda fc, taus: O.velocity_loss(O.step_single_mrt(fc, taus, T))
+    for (i, s) in inputs.sample_components(f0[0].size, 8, seed=9):
+        fc = f0.astype(np.complex128)
+        fc.reshape(19, -1)[i, s] += 1j * h
+        d = L(fc, MRT_TAUS).imag / h
+        assert abs(d - grad_f0.reshape(19, -1)[i, s]) <= 1e-11 * np.abs(grad_f0).max()
+    for k, name in enumerate(O.MRT_RATES):
+        taus = list(MRT_TAUS)
+        taus[k] = taus[k] + 1j * h
+        d = L(f0.astype(np.complex128), tuple(taus)).imag / h
+        assert abs(d - dtau[name]) <= 1e-11 * abs(d), name
+
+
 def test_adjoint_rollout_central_differences():
     f0 = _adjoint_case()
     tau, T, eps = 0.9, 4, 1e-6
