@@ -47,6 +47,9 @@ WORKLOADS = {
                                             "+ adjoint with checkpoints every 20 steps"),
     "adjoint128_f64": ("adjoint", "f64", 128, "D3Q19 single-fluid BGK 128^3 shear wave, FP64, 200-step rollout "
                                               "+ adjoint with checkpoints every 20 steps"),
+    "adjoint64_mrt_f64": ("adjoint", "f64", 64, "D3Q19 single-fluid MRT 64^3 shear wave, FP64, 200-step rollout "
+                          "+ adjoint with checkpoints every 20 steps, gradients w.r.t. f0 and the five relaxation "
+                          "times (0.8, 1.1, 1.3, 0.9, 1.2)"),
     "adjoint_binary64_f64": ("adjoint_binary", "f64", 64, "D3Q19 binary fluid 64^3 spinodal quench, FP64, "
                              "200-step rollout + adjoint (gradients w.r.t. phi0, rho0, u0, kappa, M, tau_f) "
                              "with checkpoints every 20 steps"),
@@ -172,13 +175,19 @@ def bench_adjoint(args, n, desc, T=200, K=20):
     from paper_1405_6162_amd.adjoint import rollout, velocity_loss
     log("bench: %s" % desc)
     rho, u = inputs.shear_wave(n, n, n, amplitude=0.01, noise=1e-4, seed=0)
-    lat = lb.Lattice(n, n, n, tau_f=0.8)
+    mrt = "_mrt_" in args.workload
+    taus = (0.8, 1.1, 1.3, 0.9, 1.2) if mrt else 0.8
+    if mrt:
+        lat = lb.Lattice(n, n, n, collision=lb.LB_MRT, tau_f=taus[0], tau_minus=taus[1], tau_bulk=taus[2],
+                         tau_ghost_even=taus[3], tau_ghost_odd=taus[4])
+    else:
+        lat = lb.Lattice(n, n, n, tau_f=taus)
     lat.init_equilibrium(rho, u)
     f0 = lat.get_state()[0].clone()
 
     def once():
         f = f0.clone().requires_grad_(True)
-        tau = torch.tensor(0.8, dtype=torch.float64, device="cuda", requires_grad=True)
+        tau = torch.tensor(taus, dtype=torch.float64, device="cuda", requires_grad=True)
         loss = velocity_loss(rollout(f, tau, lat, T, K))
         loss.backward()
         return f.grad, tau.grad
@@ -195,7 +204,7 @@ def bench_adjoint(args, n, desc, T=200, K=20):
     wall = time.perf_counter() - t0
     lb.lb_profile(lat.ctx, False)
     adj_ms, adj_n = lb.lb_kernel_times(lat.ctx, lb.LB_K_ADJOINT)
-    finite = bool(torch.isfinite(g).all()) and bool(torch.isfinite(gt))
+    finite = bool(torch.isfinite(g).all()) and bool(torch.isfinite(gt).all())
     lat.close()
     if not finite:
         print("non-finite gradient", file=sys.stderr)
@@ -209,12 +218,13 @@ def bench_adjoint(args, n, desc, T=200, K=20):
         "n_gpus": 1, "steps": T * iters, "warmup": args.warmup,
         "ms_per_step": round(wall * 1e3 / (T * iters), 5), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": desc, "nx": n, "ny": n, "nz": n, "tau": 0.8, "rollout_steps": T,
+        "config": {"workload": desc, "nx": n, "ny": n, "nz": n, "tau": taus, "rollout_steps": T,
                    "checkpoint_every": K, "seed": 0},
-        "roofline": {"bound": "hbm", "kernel": "k_adjoint (adjoint of the fused step)",
+        "roofline": {"bound": "hbm", "kernel": "k_adjoint%s (adjoint of the fused step)" % (" (MRT)" if mrt else ""),
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(args.workload),
                      "bytes_per_site": alg["adjoint"], "avg_launch_ms": round(avg, 5), "launches": adj_n},
+        "gradients": {"dL/dtau": [float(x) for x in gt.reshape(-1)], "max_abs_df0": float(g.abs().max())},
     }
     if not args.no_copy:
         out["copy_probe"] = copy_probe(torch)

@@ -177,7 +177,8 @@ int lb_set_state(lb_ctx* ctx, const void* f, const void* g);
 /* Change tau_f (> 0.5) for subsequent collisions. */
 int lb_set_tau(lb_ctx* ctx, double tau_f);
 
-/* nsteps x (collide; propagate) like lb_step (BGK), recording each step's
+/* nsteps x (collide; propagate) like lb_step (LB_SINGLE: any collision;
+ * LB_BINARY: LB_BGK only, else LB_ENOTSUP), recording each step's
  * post-collision field (before its propagation) in caller memory, canonical
  * layout, storage dtype.  LB_SINGLE: step k (0-based) writes
  * post[k*19*N + i*N + s] (nsteps*19*N elements).  LB_BINARY: step k writes f*
@@ -190,14 +191,20 @@ int lb_set_tau(lb_ctx* ctx, double tau_f);
  * form.  nsteps == 0 is a no-op. */
 int lb_step_record(lb_ctx* ctx, int32_t nsteps, void* post, void* phi);
 
-/* Adjoint (reverse) of one single-fluid BGK step f^{n+1} = propagate(collide(f^n)),
- * LB_SINGLE + LB_F64 only.  f (19*N, canonical FP64) is f^n itself when
+/* Adjoint (reverse) of one single-fluid step f^{n+1} = propagate(collide(f^n)),
+ * LB_SINGLE + LB_F64 only, for the context's collision.  Every collision is
+ * f* = f - Omega (f - f^eq(f)) with a constant symmetric Omega (BGK: I/tau_f;
+ * TRT and MRT: the relaxation of lb_params' rate groups), so the adjoint is
+ * lambda^n = lambda* - (I - J)^T Omega lambda*, J = d f^eq / d f.
+ * f (19*N, canonical FP64) is f^n itself when
  * f_pending == 0, or the post-collision field of step n-1 (as written by
  * lb_step_record) when f_pending != 0, in which case f^n_i(s) = f_i(s - c_i).
  * lam_next[19*N] = dL/df^{n+1}, canonical FP64; lam_n[19*N] receives dL/df^n
- * (must not alias the inputs).  *domega (one device double) is INCREMENTED by
- * this step's dL/d(1/tau_f); the caller zeroes it first and converts with
- * dL/dtau = -dL/domega / tau^2.  Uses the context's tau_f. */
+ * (must not alias the inputs).  domega (device doubles) is INCREMENTED by
+ * this step's dL/d(1/tau) for each relaxation time: 1 value for LB_BGK
+ * (tau_f), 2 for LB_TRT (tau_f, tau_minus), 5 for LB_MRT (tau_f, tau_minus,
+ * tau_bulk, tau_ghost_even, tau_ghost_odd); the caller zeroes them first and
+ * converts with dL/dtau = -dL/domega / tau^2.  Uses the context's times. */
 int lb_adjoint_step(lb_ctx* ctx, const double* f, int f_pending, const double* lam_next,
                     double* lam_n, double* domega);
 
@@ -243,14 +250,14 @@ int lb_adjoint_init_binary(lb_ctx* ctx, const double* rho, const double* u, cons
  * n = s0+length-1 down to s0, with the adjoint fields kept on the device
  * between them (the checkpoint/recompute scheme of the adjoint section:
  * the segment is re-run from its checkpoint with lb_step_record, then
- * reversed here).  FP64, LB_BGK, same model restrictions as the per-step
- * calls (LB_ENOTSUP otherwise); length < 1 is LB_EINVAL.
+ * reversed here).  FP64, same model and collision restrictions as the
+ * per-step calls (LB_ENOTSUP otherwise); length < 1 is LB_EINVAL.
  *
- * lb_adjoint_segment (LB_SINGLE): f0[19*N] = f^{s0} (canonical, not pending);
+ * lb_adjoint_segment (LB_SINGLE, any collision): f0[19*N] = f^{s0} (canonical, not pending);
  * post = the length-1 post-collision fields lb_step_record(length-1) wrote
  * from f^{s0} (19*N each, consecutive; NULL when length == 1).  lam[19*N]
  * holds dL/df^{s0+length} on entry and dL/df^{s0} on return; work[19*N] is
- * scratch.  *domega is INCREMENTED as by lb_adjoint_step, step by step in
+ * scratch.  domega (1, 2 or 5 doubles) is INCREMENTED as by lb_adjoint_step, step by step in
  * the same order, so the result equals the per-step calls bit for bit.
  *
  * lb_adjoint_segment_binary (LB_BINARY): f0, g0 = f^{s0}, g^{s0}; post = the

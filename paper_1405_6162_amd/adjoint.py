@@ -21,14 +21,35 @@ import torch
 from . import lb
 
 
+# Relaxation times of the single fluid per collision, in the order of the
+# rate sums lb_adjoint_step accumulates.
+RATE_NAMES = {lb.LB_BGK: ("tau_f",), lb.LB_TRT: ("tau_f", "tau_minus"),
+              lb.LB_MRT: ("tau_f", "tau_minus", "tau_bulk", "tau_ghost_even", "tau_ghost_odd")}
+
+
+def _relaxation_times(tau, lattice):
+    """The rollout's relaxation times as floats, checked against the
+    lattice's collision: a 0-d (or one-element) tensor for BGK, two values
+    (tau_f, tau_minus) for TRT, five (tau_f, tau_minus, tau_bulk,
+    tau_ghost_even, tau_ghost_odd) for MRT."""
+    names = RATE_NAMES[lattice.params.collision]
+    vals = [float(v) for v in tau.detach().reshape(-1).cpu()]
+    if len(vals) != len(names):
+        raise ValueError("this lattice's collision takes %d relaxation time(s) (%s), got %d"
+                         % (len(names), ", ".join(names), len(vals)))
+    return dict(zip(names, vals))
+
+
 class LBRollout(torch.autograd.Function):
     """f_T = LBRollout.apply(f0, tau, lattice, nsteps, every).
 
     f0: (19, nz, ny, nx) float64 device tensor (pre-collision state);
-    tau: 0-d float64 tensor (BGK relaxation time, > 1/2);
+    tau: float64 tensor of relaxation times (each > 1/2): 0-d for a BGK
+    lattice, (tau_f, tau_minus) for TRT, (tau_f, tau_minus, tau_bulk,
+    tau_ghost_even, tau_ghost_odd) for MRT;
     lattice: an lb.Lattice with model LB_SINGLE and storage LB_F64, whose
-    state this call overwrites; nsteps: T >= 0; every: checkpoint interval
-    K >= 1.  Gradients flow to f0 and tau.
+    state and relaxation times this call overwrites; nsteps: T >= 0; every:
+    checkpoint interval K >= 1.  Gradients flow to f0 and tau.
     """
 
     @staticmethod
@@ -37,8 +58,8 @@ class LBRollout(torch.autograd.Function):
             raise ValueError("the adjoint is implemented for the single fluid in FP64")
         if nsteps < 0 or every < 1:
             raise ValueError("nsteps must be >= 0 and every >= 1")
-        tau_v = float(tau)
-        lattice.set_tau(tau_v)
+        taus = _relaxation_times(tau, lattice)
+        lattice.set_params(**taus)
         lattice.set_state(f0.detach())
         ckpts = [f0.detach().clone()]
         done = 0
@@ -49,17 +70,18 @@ class LBRollout(torch.autograd.Function):
             if done < nsteps:
                 ckpts.append(lattice.get_state()[0])
         fT = lattice.get_state()[0] if nsteps > 0 else f0.detach().clone()
-        ctx.lattice, ctx.nsteps, ctx.every, ctx.tau = lattice, nsteps, every, tau_v
+        ctx.lattice, ctx.nsteps, ctx.every, ctx.taus = lattice, nsteps, every, taus
+        ctx.tau_shape = tau.shape
         ctx.ckpts = ckpts
         return fT
 
     @staticmethod
     def backward(ctx, grad_fT):
-        lat, T, K, tau = ctx.lattice, ctx.nsteps, ctx.every, ctx.tau
+        lat, T, K, taus = ctx.lattice, ctx.nsteps, ctx.every, ctx.taus
         lam = grad_fT.detach().to(torch.float64).contiguous().clone()     # updated in place below
         work = torch.empty_like(lam)
-        domega = torch.zeros(1, dtype=torch.float64, device=lam.device)
-        lat.set_tau(tau)
+        domega = torch.zeros(len(taus), dtype=torch.float64, device=lam.device)
+        lat.set_params(**taus)
         nseg = len(ctx.ckpts)
         for seg in range(nseg - 1, -1, -1):
             start = seg * K
@@ -78,7 +100,8 @@ class LBRollout(torch.autograd.Function):
                 lb.lb_step_record(lat.ctx, length - 1, post)
             lb.lb_adjoint_segment(lat.ctx, ckpt, post, length, lam, work, domega)
             del post
-        grad_tau = (-domega[0] / (tau * tau)).reshape(())
+        tv = torch.tensor(list(taus.values()), dtype=torch.float64, device=lam.device)
+        grad_tau = (-domega / (tv * tv)).reshape(ctx.tau_shape)
         ctx.ckpts = None
         return lam, grad_tau, None, None, None
 
@@ -186,9 +209,11 @@ def binary_loss(f, g, beta=1.0):
 
 
 def rollout(f0, tau, lattice, nsteps, every=20):
-    """Convenience wrapper: LBRollout.apply with a tensor tau."""
+    """Convenience wrapper: LBRollout.apply with tau as a tensor (a number,
+    or a sequence of the lattice's relaxation times, is converted)."""
     if not torch.is_tensor(tau):
-        tau = torch.tensor(float(tau), dtype=torch.float64, device=f0.device)
+        tau = torch.tensor([float(t) for t in tau] if isinstance(tau, (list, tuple)) else float(tau),
+                           dtype=torch.float64, device=f0.device)
     return LBRollout.apply(f0, tau, lattice, int(nsteps), int(every))
 
 

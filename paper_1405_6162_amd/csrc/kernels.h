@@ -808,13 +808,31 @@ __global__ __launch_bounds__(P::TPB) void k_stats_final(const double* __restrict
 
 // F_PENDING: fn holds the post-collision field of step n-1 and f^n is pulled
 // from it (f^n_i(s) = fn_i(s - c_i)); otherwise fn is f^n itself.
-template <class P, bool F_PENDING>
+//
+// Every collision is f* = f - Omega (f - f^eq(f)) with a constant symmetric
+// Omega: omega I (BGK), omega_f P+ + omega_m P- (TRT, P+- the projections on
+// the parts even and odd under c -> -c), and for MRT that plus
+// (omega_k - its TRT rate) times the projection on each of the seven moments
+// with their own rates (M^-1 = M^T D^-1 for the orthogonal basis, so every
+// such projection is symmetric).  The transpose of the collision Jacobian
+// I - Omega (I - J), J = d f^eq / d f, then gives, with mu = Omega lambda*,
+//   lambda^n_j = lambda*_j - mu_j + S + sum_a T_a (c_ja - u_a),
+//   S = sum_i mu_i w_i E_i,  T_a = sum_i mu_i w_i (3 c_ia + 9 (c_i.u) c_ia - 3 u_a),
+// and dL/domega_k = sum_s (P_k lambda*).(f^eq - f) for each rate group k.
+// K (the number of rate sums) is 1 for BGK, 2 for TRT (omega_f, omega_m)
+// and 5 for MRT (shear, energy flux, energy, even ghosts, odd ghosts); they
+// go to partial[8 b + k].
+template <int COLL> struct AdjointRates { static constexpr int K = COLL == COLL_MRT ? 5 : (COLL == COLL_TRT ? 2 : 1); };
+
+template <class P, bool F_PENDING, int COLL = COLL_BGK>
 __global__ __launch_bounds__(P::TPB) void k_adjoint(const double* __restrict__ fn, const double* __restrict__ lam_next,
                                                     double* __restrict__ lam_n, double* __restrict__ partial, Geo geo,
-                                                    double omega) {
-    __shared__ double sh[1][P::TPB];
+                                                    CollParams<double> cp) {
+    constexpr int K = AdjointRates<COLL>::K;
+    __shared__ double sh[K][P::TPB];
     const Column col = column_of_thread<P>(geo);
-    double dw[1] = {0.0};
+    double dw[K];
+    for (int k = 0; k < K; ++k) dw[k] = 0.0;
     for (int v = 0; v < P::TZ; ++v) {
         const Site st = site_at(col, v, geo);
         if (!st.active) continue;
@@ -829,36 +847,113 @@ __global__ __launch_bounds__(P::TPB) void k_adjoint(const double* __restrict__ f
         moments_of(f, rho, jx, jy, jz);
         const double ux = jx / rho, uy = jy / rho, uz = jz / rho;
         const double usq = ux * ux + uy * uy + uz * uz;
-        // S = sum_i lambda*_i f^eq_i / rho = sum_i lambda*_i w_i E_i;
-        // T_a / rho = sum_i lambda*_i w_i (3 c_ia + 9 (c_i.u) c_ia - 3 u_a).
-        double Ssum = 0.0, lw = 0.0, tx = 0.0, ty = 0.0, tz = 0.0, dom = 0.0;
-        static_for<0, Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            const double cu = cdot<i>(ux, uy, uz);
-            const double E = 1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq;
-            const double lwi = ls[i] * weight<double>(i);
-            Ssum = Ssum + lwi * E;
-            lw = lw + lwi;
-            const double h = lwi * (3.0 + 9.0 * cu);
-            if constexpr (cx(i) > 0) tx = tx + h;
-            if constexpr (cx(i) < 0) tx = tx - h;
-            if constexpr (cy(i) > 0) ty = ty + h;
-            if constexpr (cy(i) < 0) ty = ty - h;
-            if constexpr (cz(i) > 0) tz = tz + h;
-            if constexpr (cz(i) < 0) tz = tz - h;
-            dom = dom + ls[i] * (weight<double>(i) * rho * E - f[i]);
-        });
-        const double Tx = tx - 3.0 * ux * lw, Ty = ty - 3.0 * uy * lw, Tz = tz - 3.0 * uz * lw;
-        const double TU = Tx * ux + Ty * uy + Tz * uz;
-        static_for<0, Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            const double tc = cdot<i>(Tx, Ty, Tz);
-            *at(lam_n + i * geo.dstride, off) = (1.0 - omega) * ls[i] + omega * (Ssum + tc - TU);
-        });
-        dw[0] = dw[0] + dom;
+        if constexpr (COLL == COLL_BGK) {
+            const double omega = cp.omega_f;
+            // S = sum_i lambda*_i f^eq_i / rho = sum_i lambda*_i w_i E_i;
+            // T_a / rho = sum_i lambda*_i w_i (3 c_ia + 9 (c_i.u) c_ia - 3 u_a).
+            double Ssum = 0.0, lw = 0.0, tx = 0.0, ty = 0.0, tz = 0.0, dom = 0.0;
+            static_for<0, Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                const double cu = cdot<i>(ux, uy, uz);
+                const double E = 1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq;
+                const double lwi = ls[i] * weight<double>(i);
+                Ssum = Ssum + lwi * E;
+                lw = lw + lwi;
+                const double h = lwi * (3.0 + 9.0 * cu);
+                if constexpr (cx(i) > 0) tx = tx + h;
+                if constexpr (cx(i) < 0) tx = tx - h;
+                if constexpr (cy(i) > 0) ty = ty + h;
+                if constexpr (cy(i) < 0) ty = ty - h;
+                if constexpr (cz(i) > 0) tz = tz + h;
+                if constexpr (cz(i) < 0) tz = tz - h;
+                dom = dom + ls[i] * (weight<double>(i) * rho * E - f[i]);
+            });
+            const double Tx = tx - 3.0 * ux * lw, Ty = ty - 3.0 * uy * lw, Tz = tz - 3.0 * uz * lw;
+            const double TU = Tx * ux + Ty * uy + Tz * uz;
+            static_for<0, Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                const double tc = cdot<i>(Tx, Ty, Tz);
+                *at(lam_n + i * geo.dstride, off) = (1.0 - omega) * ls[i] + omega * (Ssum + tc - TU);
+            });
+            dw[0] = dw[0] + dom;
+        } else {
+            // the seven moments with their own MRT rates, of lambda* (for mu)
+            // and of n = f^eq - f (for the rate sums)
+            double a[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            double dpm[2] = {0.0, 0.0};          // (lambda*+).n, (lambda*-).n
+            if constexpr (COLL == COLL_MRT) {
+                static_for<0, 7>([&](auto Kx) {
+                    constexpr int k = decltype(Kx)::value;
+                    constexpr int m = mrt_extra(k);
+                    double ml = 0.0, mn = 0.0;
+                    static_for<0, Q>([&](auto I) {
+                        constexpr int i = decltype(I)::value;
+                        constexpr int c = mrt_poly(m, i);
+                        if constexpr (c != 0) {
+                            const double cu = cdot<i>(ux, uy, uz);
+                            const double n = weight<double>(i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq) - f[i];
+                            ml = ml + double(c) * ls[i];
+                            mn = mn + double(c) * n;
+                        }
+                    });
+                    const double d = ml * mn / double(mrt_norm(m));
+                    // k = 0: e (bulk); 1-3: even ghosts; 4-6: odd ghosts
+                    if constexpr (k == 0) dw[2] = dw[2] + d;
+                    else if constexpr (k < 4) dw[3] = dw[3] + d;
+                    else dw[4] = dw[4] + d;
+                    if constexpr (k < 4) dpm[0] = dpm[0] - d;      // shear = even - bulk - even ghosts
+                    else dpm[1] = dpm[1] - d;                       // flux = odd - odd ghosts
+                    const double dom = k == 0 ? cp.omega_b - cp.omega_f
+                                              : (k < 4 ? cp.omega_ge - cp.omega_f : cp.omega_go - cp.omega_m);
+                    a[k] = dom * ml / double(mrt_norm(m));
+                });
+            }
+            auto mu_of = [&](auto I) {
+                constexpr int i = decltype(I)::value;
+                constexpr int o = opp(i);
+                double corr = 0.0;
+                if constexpr (COLL == COLL_MRT) {
+                    static_for<0, 7>([&](auto Kx) {
+                        constexpr int k = decltype(Kx)::value;
+                        constexpr int c = mrt_poly(mrt_extra(k), i);
+                        if constexpr (c != 0) corr = corr + double(c) * a[k];
+                    });
+                }
+                return cp.omega_f * 0.5 * (ls[i] + ls[o]) + cp.omega_m * 0.5 * (ls[i] - ls[o]) + corr;
+            };
+            double Ssum = 0.0, lw = 0.0, tx = 0.0, ty = 0.0, tz = 0.0;
+            static_for<0, Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                constexpr int o = opp(i);
+                const double cu = cdot<i>(ux, uy, uz);
+                const double E = 1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq;
+                const double mwi = mu_of(I) * weight<double>(i);
+                Ssum = Ssum + mwi * E;
+                lw = lw + mwi;
+                const double h = mwi * (3.0 + 9.0 * cu);
+                if constexpr (cx(i) > 0) tx = tx + h;
+                if constexpr (cx(i) < 0) tx = tx - h;
+                if constexpr (cy(i) > 0) ty = ty + h;
+                if constexpr (cy(i) < 0) ty = ty - h;
+                if constexpr (cz(i) > 0) tz = tz + h;
+                if constexpr (cz(i) < 0) tz = tz - h;
+                const double n = weight<double>(i) * rho * E - f[i];
+                dpm[0] = dpm[0] + 0.5 * (ls[i] + ls[o]) * n;
+                dpm[1] = dpm[1] + 0.5 * (ls[i] - ls[o]) * n;
+            });
+            const double Tx = tx - 3.0 * ux * lw, Ty = ty - 3.0 * uy * lw, Tz = tz - 3.0 * uz * lw;
+            const double TU = Tx * ux + Ty * uy + Tz * uz;
+            static_for<0, Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                const double tc = cdot<i>(Tx, Ty, Tz);
+                *at(lam_n + i * geo.dstride, off) = ls[i] - mu_of(I) + (Ssum + tc - TU);
+            });
+            dw[0] = dw[0] + dpm[0];
+            dw[1] = dw[1] + dpm[1];
+        }
     }
-    block_tree_sum<P::TPB, 1>(dw, sh);
-    if (threadIdx.x == 0) partial[8 * (size_t)blockIdx.x] = sh[0][0];
+    block_tree_sum<P::TPB, K>(dw, sh);
+    if ((int)threadIdx.x < K) partial[8 * (size_t)blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
 }
 
 // ---------------------------------------------------------------------------

@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/lb.h"
@@ -517,21 +518,28 @@ int run_step_record(lb_ctx* c, int32_t n, S* post, typename Compute<S>::T* phi) 
     const int64_t N = c->L.nsite;
     const auto cp = coll_params<S>(c);
     const dim3 grid = c->grid(), block = c->block();
+    // one strided collision (pull from a pending src when GATHER), for the context's collision
+    auto collide = [&](auto gather, const S* src, int64_t src_stride, S* dst) {
+        constexpr bool G = decltype(gather)::value;
+        if (c->p.collision == LB_TRT)
+            k_collide_single_strided<Pol, S, G, COLL_TRT><<<grid, block, 0, c->stream>>>(src, src_stride, dst, N,
+                                                                                         c->geo(), cp);
+        else if (c->p.collision == LB_MRT)
+            k_collide_single_strided<Pol, S, G, COLL_MRT><<<grid, block, 0, c->stream>>>(src, src_stride, dst, N,
+                                                                                         c->geo(), cp);
+        else
+            k_collide_single_strided<Pol, S, G><<<grid, block, 0, c->stream>>>(src, src_stride, dst, N, c->geo(), cp);
+    };
     for (int32_t k = 0; k < n; ++k) {
         S* dst = post + (size_t)k * Q * N;
         {
             Timed t(c, LB_K_COLLIDE);
             if (k == 0) {
                 const S* src = (const S*)c->fbuf(c->cur);
-                if (c->pending)
-                    k_collide_single_strided<Pol, S, true><<<grid, block, 0, c->stream>>>(src, c->L.dstride, dst, N,
-                                                                                         c->geo(), cp);
-                else
-                    k_collide_single_strided<Pol, S, false><<<grid, block, 0, c->stream>>>(src, c->L.dstride, dst, N,
-                                                                                          c->geo(), cp);
+                if (c->pending) collide(std::true_type{}, src, c->L.dstride, dst);
+                else collide(std::false_type{}, src, c->L.dstride, dst);
             } else {
-                const S* src = post + (size_t)(k - 1) * Q * N;
-                k_collide_single_strided<Pol, S, true><<<grid, block, 0, c->stream>>>(src, N, dst, N, c->geo(), cp);
+                collide(std::true_type{}, post + (size_t)(k - 1) * Q * N, N, dst);
             }
         }
         int rc = launch_status();
@@ -597,6 +605,41 @@ void launch_adjoint_binary_local(lb_ctx* c, bool pending, const double* f, const
     else
         k_adjoint_binary<Pol, false, LG><<<c->grid(), c->block(), 0, c->stream>>>(
             f, g, phi, lf_next, lg_next, b_next, lf_n, p_out, afield, c->partial(), geo, cp);
+}
+
+// Rate sums an adjoint step of the single fluid accumulates: 1 (BGK), 2
+// (TRT) or 5 (MRT), in the order of lb_params' relaxation times.
+int adjoint_rate_count(const lb_ctx* c) {
+    return c->p.collision == LB_MRT ? 5 : (c->p.collision == LB_TRT ? 2 : 1);
+}
+
+template <bool PEND, int COLL>
+void adjoint_single_launch(lb_ctx* c, const double* f, const double* lam_next, double* lam_n, const Geo& geo,
+                           const CollParams<double>& cp, double* domega) {
+    {
+        Timed t(c, LB_K_ADJOINT);
+        k_adjoint<Pol, PEND, COLL><<<c->grid(), c->block(), 0, c->stream>>>(f, lam_next, lam_n, c->partial(), geo, cp);
+    }
+    k_sums_final<Pol, AdjointRates<COLL>::K><<<1, c->block(), 0, c->stream>>>(c->partial(), c->L.nblocks, domega,
+                                                                               0.0, 0.0, 1);
+}
+
+// One single-fluid adjoint step (kernel + the accumulation of its rate sums).
+void adjoint_single_step(lb_ctx* c, const double* f, bool pending, const double* lam_next, double* lam_n,
+                         const Geo& geo, const CollParams<double>& cp, double* domega) {
+    switch (c->p.collision) {
+    case LB_TRT:
+        if (pending) adjoint_single_launch<true, COLL_TRT>(c, f, lam_next, lam_n, geo, cp, domega);
+        else adjoint_single_launch<false, COLL_TRT>(c, f, lam_next, lam_n, geo, cp, domega);
+        break;
+    case LB_MRT:
+        if (pending) adjoint_single_launch<true, COLL_MRT>(c, f, lam_next, lam_n, geo, cp, domega);
+        else adjoint_single_launch<false, COLL_MRT>(c, f, lam_next, lam_n, geo, cp, domega);
+        break;
+    default:
+        if (pending) adjoint_single_launch<true, COLL_BGK>(c, f, lam_next, lam_n, geo, cp, domega);
+        else adjoint_single_launch<false, COLL_BGK>(c, f, lam_next, lam_n, geo, cp, domega);
+    }
 }
 
 }  // namespace
@@ -744,7 +787,7 @@ int lb_step_record(lb_ctx* c, int32_t nsteps, void* post, void* phi) {
     if (phi && c->p.model != LB_BINARY) return LB_EINVAL;
     if (nsteps == 0) return LB_OK;
     if (!post) return LB_EINVAL;
-    if (c->p.collision != LB_BGK) return LB_ENOTSUP;
+    if (c->p.model == LB_BINARY && c->p.collision != LB_BGK) return LB_ENOTSUP;
     return by_storage(c, [&](auto tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
         return run_step_record<S>(c, nsteps, (S*)post, (typename Compute<S>::T*)phi);
@@ -824,19 +867,10 @@ int lb_adjoint_init_binary(lb_ctx* c, const double* rho, const double* u, const 
 int lb_adjoint_step(lb_ctx* c, const double* f, int f_pending, const double* lam_next, double* lam_n,
                     double* domega) {
     if (!c || !f || !lam_next || !lam_n || !domega) return LB_EINVAL;
-    if (c->p.model != LB_SINGLE || c->p.storage != LB_F64 || c->p.collision != LB_BGK) return LB_ENOTSUP;
+    if (c->p.model != LB_SINGLE || c->p.storage != LB_F64) return LB_ENOTSUP;
     if (lam_n == lam_next || lam_n == f) return LB_EINVAL;
     c->launched = true;
-    {
-        Timed t(c, LB_K_ADJOINT);
-        if (f_pending)
-            k_adjoint<Pol, true><<<c->grid(), c->block(), 0, c->stream>>>(f, lam_next, lam_n, c->partial(),
-                                                                        c->canonical_geo(), 1.0 / c->p.tau_f);
-        else
-            k_adjoint<Pol, false><<<c->grid(), c->block(), 0, c->stream>>>(f, lam_next, lam_n, c->partial(),
-                                                                         c->canonical_geo(), 1.0 / c->p.tau_f);
-    }
-    k_sums_final<Pol, 1><<<1, c->block(), 0, c->stream>>>(c->partial(), c->L.nblocks, domega, 0.0, 0.0, 1);
+    adjoint_single_step(c, f, f_pending != 0, lam_next, lam_n, c->canonical_geo(), coll_params<double>(c), domega);
     return launch_status();
 }
 
@@ -844,28 +878,22 @@ int lb_adjoint_segment(lb_ctx* c, const double* f0, const double* post, int32_t 
                        double* domega) {
     if (!c || !f0 || !lam || !work || !domega || length < 1) return LB_EINVAL;
     if (length > 1 && !post) return LB_EINVAL;
-    if (c->p.model != LB_SINGLE || c->p.storage != LB_F64 || c->p.collision != LB_BGK) return LB_ENOTSUP;
+    if (c->p.model != LB_SINGLE || c->p.storage != LB_F64) return LB_ENOTSUP;
     const size_t n19 = (size_t)Q * c->L.nsite;
     const size_t npost = length > 1 ? (size_t)(length - 1) * n19 : 0;
+    const size_t nw = (size_t)adjoint_rate_count(c);
     if (overlaps(lam, n19, work, n19) || overlaps(lam, n19, f0, n19) || overlaps(work, n19, f0, n19) ||
-        overlaps(lam, n19, post, npost) || overlaps(work, n19, post, npost) || overlaps(domega, 1, lam, n19) ||
-        overlaps(domega, 1, work, n19) || overlaps(domega, 1, f0, n19) || overlaps(domega, 1, post, npost))
+        overlaps(lam, n19, post, npost) || overlaps(work, n19, post, npost) || overlaps(domega, nw, lam, n19) ||
+        overlaps(domega, nw, work, n19) || overlaps(domega, nw, f0, n19) || overlaps(domega, nw, post, npost))
         return LB_EINVAL;
     c->launched = true;
     const Geo geo = c->canonical_geo();
-    const double omega = 1.0 / c->p.tau_f;
+    const auto cp = coll_params<double>(c);
     double* cur = lam;            // lambda^{n+1}
     double* nxt = work;
     for (int32_t n = length - 1; n >= 0; --n) {
-        {
-            Timed t(c, LB_K_ADJOINT);
-            if (n > 0)
-                k_adjoint<Pol, true><<<c->grid(), c->block(), 0, c->stream>>>(post + (size_t)(n - 1) * n19, cur, nxt,
-                                                                            c->partial(), geo, omega);
-            else
-                k_adjoint<Pol, false><<<c->grid(), c->block(), 0, c->stream>>>(f0, cur, nxt, c->partial(), geo, omega);
-        }
-        k_sums_final<Pol, 1><<<1, c->block(), 0, c->stream>>>(c->partial(), c->L.nblocks, domega, 0.0, 0.0, 1);
+        if (n > 0) adjoint_single_step(c, post + (size_t)(n - 1) * n19, true, cur, nxt, geo, cp, domega);
+        else adjoint_single_step(c, f0, false, cur, nxt, geo, cp, domega);
         std::swap(cur, nxt);
     }
     if (cur != lam) {

@@ -218,6 +218,23 @@ def test_single_model_rejects_phi(lib):
         assert lib.lb_destroy(ctx) == lb.LB_OK
 
 
+@no_device
+def test_collision_support_of_the_adjoint_calls(lib):
+    """The binary adjoint and the binary record are BGK only (LB_ENOTSUP before
+    any launch); the single-fluid adjoint takes every collision."""
+    fake = [ctypes.c_void_p((k + 2) << 20) for k in range(8)]
+    p = lb.make_params(6, 5, 4, model=lb.LB_BINARY, collision=lb.LB_TRT, tau_minus=1.2)
+    _, need = _ws(p)
+    ctx = ctypes.c_void_p()
+    assert lib.lb_create(ctypes.byref(p), ctypes.c_void_p(1 << 20), need, None, ctypes.byref(ctx)) == lb.LB_OK
+    try:
+        assert lib.lb_step_record(ctx, 2, fake[0], None) == lb.LB_ENOTSUP
+        assert lib.lb_adjoint_step_binary(ctx, *fake[:3], 0, *fake[3:7], fake[7]) == lb.LB_ENOTSUP
+        assert lib.lb_adjoint_segment_binary(ctx, fake[0], fake[1], None, None, 1, *fake[2:6]) == lb.LB_ENOTSUP
+    finally:
+        assert lib.lb_destroy(ctx) == lb.LB_OK
+
+
 def test_null_handles(lib):
     assert lib.lb_destroy(None) == lb.LB_OK
     assert lib.lb_step(None, 1) == lb.LB_EINVAL

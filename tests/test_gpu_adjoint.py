@@ -199,3 +199,150 @@ def test_segment_sweep_equals_per_step_calls(lbgpu, length):
         dw_o += d
     assert relerr(lam_seg.cpu().numpy(), lam_o) < 1e-12
     assert abs(dw_seg.item() - 0.125 - dw_o) <= 1e-12 * max(abs(dw_o), np.abs(lam_o).max())
+
+
+# ---------------------------------------------------------------------------
+# TRT and MRT: the same kernel with mu = Omega lambda* in place of
+# omega lambda*, and one rate sum per relaxation time
+# ---------------------------------------------------------------------------
+
+MRT_TAUS = (0.8, 1.1, 1.3, 0.9, 1.2)        # tau_f (shear), tau_minus (flux), tau_bulk, ghost even, ghost odd
+TRT_TAUS = (0.85, 1.15)
+
+
+def _collision_lattice(lbgpu, nx, ny, nz, coll):
+    if coll == "trt":
+        return lbgpu.Lattice(nx, ny, nz, collision=lbgpu.LB_TRT, tau_f=TRT_TAUS[0], tau_minus=TRT_TAUS[1])
+    t = MRT_TAUS
+    return lbgpu.Lattice(nx, ny, nz, collision=lbgpu.LB_MRT, tau_f=t[0], tau_minus=t[1], tau_bulk=t[2],
+                         tau_ghost_even=t[3], tau_ghost_odd=t[4])
+
+
+def _oracle_taus(coll):
+    """The five MRT times of the collision (TRT: the even ones tied to tau_f,
+    the odd ones to tau_minus) and how the oracle's group sums add up to the
+    library's rate sums."""
+    if coll == "trt":
+        tp, tm = TRT_TAUS
+        return (tp, tm, tp, tp, tm), [("shear", "bulk", "ghost_even"), ("flux", "ghost_odd")]
+    return MRT_TAUS, [(k,) for k in O.MRT_RATES]
+
+
+@pytest.mark.parametrize("pending", [False, True])
+@pytest.mark.parametrize("coll", ["trt", "mrt"])
+@pytest.mark.parametrize("nx,ny,nz", [(5, 6, 7), (67, 9, 5)])
+def test_adjoint_step_kernel_trt_mrt(lbgpu, nx, ny, nz, coll, pending):
+    print("case adjoint step", coll, nx, ny, nz, "pending" if pending else "direct", flush=True)
+    taus, groups = _oracle_taus(coll)
+    f = _state(nx, ny, nz, seed=31)
+    src = O.collide_single_mrt(f, taus) if pending else f     # pending: f^n = propagate(src)
+    fn = O.propagate(src) if pending else f
+    lam_next = np.random.default_rng(32).standard_normal(f.shape)
+    want, g = O.adjoint_step_single_mrt(fn, lam_next, taus)
+    want_dw = [sum(g[k] for k in grp) for grp in groups]
+    lat = _collision_lattice(lbgpu, nx, ny, nz, coll)
+    dev = lambda a: torch.as_tensor(a, device="cuda").contiguous()
+    out = torch.empty_like(dev(lam_next))
+    dw = torch.full((len(groups),), 0.5, dtype=torch.float64, device="cuda")      # incremented
+    lbgpu.lb_set_stream(lat.ctx, lbgpu._stream())
+    lbgpu.lb_adjoint_step(lat.ctx, dev(src), dev(lam_next), out, dw, f_pending=pending)
+    assert relerr(out.cpu().numpy(), want) < 1e-12
+    got = dw.cpu().numpy() - 0.5
+    for k in range(len(groups)):
+        assert abs(got[k] - want_dw[k]) <= 1e-12 * max(abs(want_dw[k]), np.abs(want).max()), (coll, k)
+
+
+@pytest.mark.parametrize("coll", ["trt", "mrt"])
+def test_segment_sweep_trt_mrt_equals_per_step_calls(lbgpu, coll):
+    nx, ny, nz, length = 13, 7, 6, 4
+    f0 = _state(nx, ny, nz, seed=33)
+    lam_T = np.random.default_rng(34).standard_normal(f0.shape)
+    lat = _collision_lattice(lbgpu, nx, ny, nz, coll)
+    lat.set_state(f0)
+    dev = lambda a: torch.as_tensor(a, device="cuda").contiguous()
+    f0t = dev(f0)
+    post = torch.empty((length - 1, 19, nz, ny, nx), dtype=torch.float64, device="cuda")
+    lbgpu.lb_set_stream(lat.ctx, lbgpu._stream())
+    lbgpu.lb_step_record(lat.ctx, length - 1, post)
+    K = 2 if coll == "trt" else 5
+    lam, dw = dev(lam_T), torch.zeros(K, dtype=torch.float64, device="cuda")
+    for n in range(length - 1, -1, -1):
+        out = torch.empty_like(lam)
+        if n == 0:
+            lbgpu.lb_adjoint_step(lat.ctx, f0t, lam, out, dw)
+        else:
+            lbgpu.lb_adjoint_step(lat.ctx, post[n - 1], lam, out, dw, f_pending=True)
+        lam = out
+    lam_s, dw_s = dev(lam_T), torch.zeros(K, dtype=torch.float64, device="cuda")
+    lbgpu.lb_adjoint_segment(lat.ctx, f0t, post, length, lam_s, torch.empty_like(lam_s), dw_s)
+    assert torch.equal(lam_s, lam) and torch.equal(dw_s, dw)
+
+
+@pytest.mark.parametrize("coll", ["trt", "mrt"])
+def test_rollout_gradient_trt_mrt_vs_oracle(lbgpu, coll):
+    """The checkpointed rollout on a TRT / MRT lattice against the oracle's
+    plain reverse sweep: dL/df0 and dL/dtau for every relaxation time."""
+    from paper_1405_6162_amd.adjoint import rollout, velocity_loss
+    nx, ny, nz, T, K = 8, 8, 8, 7, 3
+    taus, groups = _oracle_taus(coll)
+    f0 = _state(nx, ny, nz, seed=35)
+    loss_o, g_o, dtau_o = O.rollout_gradient_mrt(f0, taus, T)
+    # d/dtau_f of a TRT lattice moves the three even groups together: sum of
+    # their dL/domega, converted with the shared tau
+    lib_taus = TRT_TAUS if coll == "trt" else MRT_TAUS
+    want_tau = []
+    for grp, t in zip(groups, lib_taus):
+        dom = sum(-dtau_o[k] * taus[O.MRT_RATES.index(k)] ** 2 for k in grp)   # dL/domega of the group
+        want_tau.append(-dom / (t * t))
+    lat = _collision_lattice(lbgpu, nx, ny, nz, coll)
+    f0t = torch.tensor(f0, device="cuda", requires_grad=True)
+    taut = torch.tensor(lib_taus, dtype=torch.float64, device="cuda", requires_grad=True)
+    loss = velocity_loss(rollout(f0t, taut, lat, T, K))
+    loss.backward()
+    assert abs(loss.item() - loss_o) <= 1e-12 * loss_o
+    assert relerr(f0t.grad.cpu().numpy(), g_o) < 1e-10
+    got = taut.grad.cpu().numpy()
+    for k in range(len(groups)):
+        assert abs(got[k] - want_tau[k]) <= 1e-10 * abs(want_tau[k]), (coll, k)
+
+
+def test_mrt_shear_wave_32_adjoint_vs_finite_differences(lbgpu):
+    """MRT at 32^3: a shear wave with noise, 60 steps, checkpoints every 20;
+    dL/df0 on sampled components and dL/dtau for all five relaxation times
+    against central differences (eps 1e-6) of the GPU forward."""
+    from paper_1405_6162_amd.adjoint import rollout, velocity_loss
+    n, T, K, eps = 32, 60, 20, 1e-6
+    rho, u = inputs.shear_wave(n, n, n, amplitude=0.01, noise=1e-3, seed=36)
+    lat = _collision_lattice(lbgpu, n, n, n, "mrt")
+    lat.init_equilibrium(rho, u)
+    f0 = lat.get_state()[0].clone()
+    f0t = f0.clone().requires_grad_(True)
+    taut = torch.tensor(MRT_TAUS, dtype=torch.float64, device="cuda", requires_grad=True)
+    loss = velocity_loss(rollout(f0t, taut, lat, T, K))
+    loss.backward()
+    g = f0t.grad.reshape(19, -1)
+    names = ("tau_f", "tau_minus", "tau_bulk", "tau_ghost_even", "tau_ghost_odd")
+
+    def L(f, taus):
+        lat.set_params(**dict(zip(names, taus)))
+        lat.set_state(f)
+        lat.step(T)
+        return velocity_loss(lat.get_state()[0]).item()
+
+    # 1e-6 relative, with a floor at the rounding of a central difference in
+    # FP64: each loss carries a few ulp, divided by 2 eps
+    floor = 4 * np.finfo(np.float64).eps * abs(loss.item()) / eps
+    for (i, s) in inputs.sample_components(n ** 3, 6, seed=37):
+        fp, fm = f0.clone(), f0.clone()
+        fp.reshape(19, -1)[i, s] += eps
+        fm.reshape(19, -1)[i, s] -= eps
+        fd = (L(fp, MRT_TAUS) - L(fm, MRT_TAUS)) / (2 * eps)
+        assert abs(fd - g[i, s].item()) <= 1e-6 * abs(g[i, s].item()) + floor, (i, s, fd, g[i, s].item())
+    for k in range(5):
+        tp, tm = list(MRT_TAUS), list(MRT_TAUS)
+        tp[k] += eps
+        tm[k] -= eps
+        fd = (L(f0, tp) - L(f0, tm)) / (2 * eps)
+        gk = taut.grad[k].item()
+        print("  dL/d%s adjoint %.9e fd %.9e" % (names[k], gk, fd), flush=True)
+        assert abs(fd - gk) <= 1e-6 * abs(gk) + floor, names[k]

@@ -23,15 +23,21 @@ class _Lattice:
         self.model, self.storage = model, lb.LB_F64
         self.prm = prm
         self.params = types.SimpleNamespace(kappa=prm.kappa, mobility=prm.mobility, tau_f=prm.tau_f,
-                                            gamma=prm.gamma)
+                                            gamma=prm.gamma, collision=lb.LB_BGK, tau_minus=prm.tau_f,
+                                            tau_bulk=prm.tau_f, tau_ghost_even=prm.tau_f, tau_ghost_odd=prm.tau_f)
         self.ctx = self
         self.f = self.g = None
         self.calls = {"record": 0, "adjoint": 0, "phi_given": 0, "segment": 0}
 
     def set_params(self, **kw):
         for k, v in kw.items():
-            setattr(self.prm, k, float(v))
+            if hasattr(self.prm, k):
+                setattr(self.prm, k, float(v))
             setattr(self.params, k, float(v))
+
+    def mrt_taus(self):
+        p = self.params
+        return (p.tau_f, p.tau_minus, p.tau_bulk, p.tau_ghost_even, p.tau_ghost_odd)
 
     def set_tau(self, tau):
         self.set_params(tau_f=tau)
@@ -46,6 +52,8 @@ class _Lattice:
     def _step(self):
         if self.model == lb.LB_BINARY:
             self.f, self.g = O.step_binary(self.f, self.g, self.prm, 1)
+        elif self.params.collision == lb.LB_MRT:
+            self.f = O.step_single_mrt(self.f, self.mrt_taus(), 1)
         else:
             self.f = O.step_single(self.f, self.prm.tau_f, 1)
 
@@ -73,7 +81,10 @@ def _record(ctx, n, post, phi=None):
             post[k, 19:] = torch.from_numpy(pg)
             ctx.f, ctx.g = O.propagate(pf), O.propagate(pg)
         else:
-            pf = O.collide_single(ctx.f, ctx.prm.tau_f)
+            if ctx.params.collision == lb.LB_MRT:
+                pf = O.collide_single_mrt(ctx.f, ctx.mrt_taus())
+            else:
+                pf = O.collide_single(ctx.f, ctx.prm.tau_f)
             post[k] = torch.from_numpy(pf)
             ctx.f = O.propagate(pf)
 
@@ -103,9 +114,15 @@ def _adjoint_init_binary(ctx, rho, u, phi, lf, lg, dphi, drho, du, dkappa):
 def _adjoint_single(ctx, f, lam, lam_n, domega, f_pending=False):
     ctx.calls["adjoint"] += 1
     fn = O.propagate(f.numpy()) if f_pending else f.numpy()
-    a, dw = O.adjoint_step_single(fn, lam.numpy(), ctx.prm.tau_f)
+    if ctx.params.collision == lb.LB_MRT:
+        assert domega.shape == (5,)
+        a, g = O.adjoint_step_single_mrt(fn, lam.numpy(), ctx.mrt_taus())
+        domega += torch.tensor([g[k] for k in O.MRT_RATES], dtype=torch.float64)
+    else:
+        assert domega.shape == (1,)
+        a, dw = O.adjoint_step_single(fn, lam.numpy(), ctx.prm.tau_f)
+        domega += dw
     lam_n.copy_(torch.from_numpy(a))
-    domega += dw
 
 
 def _segment_binary(ctx, f0, g0, post, phi, length, lf, lg, work, grads):
@@ -198,3 +215,27 @@ def test_single_rollout_checkpoint_logic(fake_lib, T, K):
     np.testing.assert_allclose(f.grad.numpy(), g_o, rtol=0, atol=1e-13 * np.abs(g_o).max())
     if T > 0:
         assert abs(t.grad.item() - dtau_o) <= 1e-12 * abs(dtau_o)
+
+
+@pytest.mark.parametrize("T,K", [(5, 2), (4, 4)])
+def test_single_mrt_rollout_checkpoint_logic(fake_lib, T, K):
+    """An MRT lattice: five relaxation times in, five gradients out, each
+    dL/dtau_k = -dL/domega_k / tau_k^2, against the oracle's plain sweep."""
+    nx, ny, nz = 5, 4, 3
+    rho, u = inputs.shear_wave(nx, ny, nz, amplitude=0.01, noise=1e-3, seed=17)
+    f0 = O.init_single(rho, u)
+    taus = (0.8, 1.1, 1.3, 0.9, 1.2)
+    loss_o, g_o, dtau_o = O.rollout_gradient_mrt(f0, taus, T)
+    lat = _Lattice(lb.LB_SINGLE, O.Params(tau_f=taus[0]))
+    lat.params.collision = lb.LB_MRT
+    f = torch.from_numpy(f0.copy()).requires_grad_(True)
+    t = torch.tensor(taus, dtype=torch.float64, requires_grad=True)
+    loss = adjoint.velocity_loss(adjoint.rollout(f, t, lat, T, K))
+    assert abs(loss.item() - loss_o) <= 1e-14 * abs(loss_o)
+    loss.backward()
+    assert lat.calls["adjoint"] == T
+    np.testing.assert_allclose(f.grad.numpy(), g_o, rtol=0, atol=1e-13 * np.abs(g_o).max())
+    for k, name in enumerate(O.MRT_RATES):
+        assert abs(t.grad[k].item() - dtau_o[name]) <= 1e-12 * abs(dtau_o[name]), name
+    with pytest.raises(ValueError):              # an MRT lattice takes five times
+        adjoint.rollout(f.detach(), torch.tensor(0.8, dtype=torch.float64), lat, T, K)
