@@ -196,7 +196,7 @@ def bench_adjoint(args, n, desc, T=200, K=20):
         once()
     torch.cuda.synchronize()
     iters = max(args.steps // 100, 1)
-    lb.lb_profile(lat.ctx, True)
+    lb.lb_profile_mask(lat.ctx, [lb.LB_K_ADJOINT])      # events on the adjoint kernels only
     t0 = time.perf_counter()
     for _ in range(iters):
         g, gt = once()
@@ -255,7 +255,7 @@ def bench_adjoint_binary(args, n, desc, T=200, K=20):
         once()
     torch.cuda.synchronize()
     iters = max(args.steps // 100, 1)
-    lb.lb_profile(lat.ctx, True)
+    lb.lb_profile_mask(lat.ctx, [lb.LB_K_ADJOINT])      # events on the adjoint kernels only
     t0 = time.perf_counter()
     for _ in range(iters):
         gphi, gpar = once()

@@ -310,6 +310,11 @@ int lb_set_sites(lb_ctx* ctx, const int32_t* index, int64_t m, const void* f_pac
 #define LB_K_ADJOINT  3   /* adjoint step (binary: its phi, local and stencil kernels) */
 #define LB_K_OTHER    4   /* init, moments, sums, copies */
 int lb_profile(lb_ctx* ctx, int enable);
+/* As lb_profile, but only launches of the kernel classes whose bits are set
+ * in `kinds` (bit k = 1 << LB_K_...) get an event pair; the others run
+ * unbracketed, so a measurement of one class perturbs the rest less.
+ * kinds = 0 stops; bits above LB_K_OTHER are LB_EINVAL. */
+int lb_profile_mask(lb_ctx* ctx, unsigned kinds);
 int lb_kernel_times(lb_ctx* ctx, int kind, double* total_ms, int64_t* launches);
 
 /* Destroy a context (waits for its stream).  NULL is allowed (LB_OK).

@@ -134,6 +134,7 @@ struct lb_ctx {
     int cur;          // buffer index holding the state
     bool pending;     // true: the state is propagate(buffer[cur])
     bool profiling;
+    unsigned profile_kinds;   // bit k: time launches of kernel class k
     bool launched;    // any device work queued (lb_destroy waits for it)
     std::vector<Rec> recs;
     std::vector<hipEvent_t> pool;
@@ -199,13 +200,13 @@ namespace {
 struct Timed {
     lb_ctx* c; int kind; hipEvent_t a = nullptr, b = nullptr;
     Timed(lb_ctx* c_, int kind_) : c(c_), kind(kind_) {
-        if (c->profiling) {
+        if (c->profiling && ((c->profile_kinds >> kind) & 1u)) {
             a = c->take_event(); b = c->take_event();
             if (a && b) (void)hipEventRecord(a, c->stream);
         }
     }
     ~Timed() {
-        if (c->profiling && a && b) {
+        if (a && b) {
             (void)hipEventRecord(b, c->stream);
             c->recs.push_back({kind, a, b});
         } else {
@@ -671,6 +672,7 @@ int lb_create(const lb_params* p, void* workspace, size_t workspace_bytes, void*
     c->cur = 0;
     c->pending = false;
     c->profiling = false;
+    c->profile_kinds = 0;
     c->launched = false;
     *out = c;
     return LB_OK;
@@ -1000,14 +1002,19 @@ int lb_set_sites(lb_ctx* c, const int32_t* index, int64_t m, const void* f, cons
     });
 }
 
-int lb_profile(lb_ctx* c, int enable) {
-    if (!c) return LB_EINVAL;
-    if (enable) {
+int lb_profile_mask(lb_ctx* c, unsigned kinds) {
+    if (!c || (kinds >> (LB_K_OTHER + 1)) != 0) return LB_EINVAL;
+    if (kinds) {
         if (hipStreamSynchronize(c->stream) != hipSuccess) return LB_EDEVICE;
         c->release_records();
     }
-    c->profiling = enable != 0;
+    c->profiling = kinds != 0;
+    c->profile_kinds = kinds;
     return LB_OK;
+}
+
+int lb_profile(lb_ctx* c, int enable) {
+    return lb_profile_mask(c, enable ? (1u << (LB_K_OTHER + 1)) - 1u : 0u);
 }
 
 int lb_kernel_times(lb_ctx* c, int kind, double* total_ms, int64_t* launches) {

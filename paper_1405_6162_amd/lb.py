@@ -87,6 +87,7 @@ _SIGNATURES = {
     "lb_get_sites": (_int, [_vp, _vp, ctypes.c_int64, _vp, _vp]),
     "lb_set_sites": (_int, [_vp, _vp, ctypes.c_int64, _vp, _vp]),
     "lb_profile": (_int, [_vp, _int]),
+    "lb_profile_mask": (_int, [_vp, ctypes.c_uint]),
     "lb_kernel_times": (_int, [_vp, _int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     "lb_destroy": (_int, [_vp]),
     "lb_strerror": (ctypes.c_char_p, [_int]),
@@ -238,6 +239,15 @@ def lb_set_sites(ctx, index, m, f_packed, g_packed=None):
 
 def lb_profile(ctx, enable):
     _check("lb_profile", _lib.lb_profile(ctx, 1 if enable else 0))
+
+
+def lb_profile_mask(ctx, kinds):
+    """Time only the launches of the given kernel classes (an iterable of
+    LB_K_* values); an empty one stops."""
+    mask = 0
+    for k in kinds:
+        mask |= 1 << int(k)
+    _check("lb_profile_mask", _lib.lb_profile_mask(ctx, mask))
 
 
 def lb_kernel_times(ctx, kind):

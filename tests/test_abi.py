@@ -181,6 +181,8 @@ def test_create_checks_workspace_without_device_work(lib):
                     lb.make_params(6, 5, 4, model=lb.LB_BINARY, storage=lb.LB_F32),
                     lb.make_params(6, 5, 4, model=lb.LB_BINARY, mobility=-1.0)):
             assert lib.lb_set_params(ctx, ctypes.byref(bad)) == lb.LB_EINVAL
+        assert lib.lb_profile_mask(ctx, 1 << (lb.LB_K_OTHER + 1)) == lb.LB_EINVAL      # no such kernel class
+        assert lib.lb_profile_mask(ctx, 0) == lb.LB_OK                                  # stop: no device work
         ms, n = ctypes.c_double(), ctypes.c_int64()
         assert lib.lb_kernel_times(ctx, 7, ctypes.byref(ms), ctypes.byref(n)) == lb.LB_EINVAL
         assert lib.lb_kernel_times(ctx, lb.LB_K_COLLIDE, ctypes.byref(ms), ctypes.byref(n)) == lb.LB_OK

@@ -78,3 +78,27 @@ def test_field_stats_deviation_storage(lbgpu, storage):
     got = lat.field_stats().cpu().numpy()
     want = _stats(f, g, 1.0, 0.0)
     assert _close(got, want, nx * ny * nz).all(), (got, want)
+
+
+def test_profile_mask_times_only_the_chosen_kernel_classes(lbgpu):
+    """lb_profile_mask: launches of the chosen classes get an event pair
+    each, the others none; lb_profile times every class."""
+    n, steps = 24, 3
+    lat = lbgpu.Lattice(n, n, n, model=lbgpu.LB_BINARY)
+    rho, u, phi = inputs.spinodal_quench(n, n, n, seed=3)
+    lat.init_equilibrium(rho, u, phi)
+    lbgpu.lb_set_stream(lat.ctx, lbgpu._stream())
+    lbgpu.lb_profile_mask(lat.ctx, [lbgpu.LB_K_STREAM])
+    lat.step(steps)
+    lat.get_state()                              # the pending state is materialised by one stream launch
+    lbgpu.lb_profile(lat.ctx, False)
+    assert lbgpu.lb_kernel_times(lat.ctx, lbgpu.LB_K_COLLIDE)[1] == 0
+    ms, launches = lbgpu.lb_kernel_times(lat.ctx, lbgpu.LB_K_STREAM)
+    assert launches == 1 and ms > 0
+    lbgpu.lb_profile(lat.ctx, True)
+    lat.step(steps)
+    lat.get_state()
+    lbgpu.lb_profile(lat.ctx, False)
+    assert lbgpu.lb_kernel_times(lat.ctx, lbgpu.LB_K_COLLIDE)[1] >= steps
+    assert lbgpu.lb_kernel_times(lat.ctx, lbgpu.LB_K_STREAM)[1] == 1
+    lat.close()
