@@ -821,13 +821,18 @@ __global__ __launch_bounds__(P::TPB) void k_stats_final(const double* __restrict
 // and dL/domega_k = sum_s (P_k lambda*).(f^eq - f) for each rate group k.
 // K (the number of rate sums) is 1 for BGK, 2 for TRT (omega_f, omega_m)
 // and 5 for MRT (shear, energy flux, energy, even ghosts, odd ghosts); they
-// go to partial[8 b + k].
+// go to partial[8 b + k].  With prev_partial given, block 0 also adds the
+// previous step's block partials (prev_nblocks of them, in block order) into
+// sums[0..K): a sweep over several steps alternates two partial arrays and
+// saves one reduction launch per step.
 template <int COLL> struct AdjointRates { static constexpr int K = COLL == COLL_MRT ? 5 : (COLL == COLL_TRT ? 2 : 1); };
 
 template <class P, bool F_PENDING, int COLL = COLL_BGK>
 __global__ __launch_bounds__(P::TPB) void k_adjoint(const double* __restrict__ fn, const double* __restrict__ lam_next,
                                                     double* __restrict__ lam_n, double* __restrict__ partial, Geo geo,
-                                                    CollParams<double> cp) {
+                                                    CollParams<double> cp,
+                                                    const double* __restrict__ prev_partial = nullptr,
+                                                    int prev_nblocks = 0, double* sums = nullptr) {
     constexpr int K = AdjointRates<COLL>::K;
     __shared__ double sh[K][P::TPB];
     const Column col = column_of_thread<P>(geo);
@@ -954,6 +959,7 @@ __global__ __launch_bounds__(P::TPB) void k_adjoint(const double* __restrict__ f
     }
     block_tree_sum<P::TPB, K>(dw, sh);
     if ((int)threadIdx.x < K) partial[8 * (size_t)blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
+    if (prev_partial != nullptr && blockIdx.x == 0) final_sums<P::TPB, K>(prev_partial, prev_nblocks, sums, 0.0, 0.0, 1);
 }
 
 // ---------------------------------------------------------------------------

@@ -614,33 +614,45 @@ int adjoint_rate_count(const lb_ctx* c) {
     return c->p.collision == LB_MRT ? 5 : (c->p.collision == LB_TRT ? 2 : 1);
 }
 
+// One single-fluid adjoint kernel launch writing its block partials to
+// `partial`; with prev given, its block 0 also accumulates the previous
+// step's partials into domega.
 template <bool PEND, int COLL>
 void adjoint_single_launch(lb_ctx* c, const double* f, const double* lam_next, double* lam_n, const Geo& geo,
-                           const CollParams<double>& cp, double* domega) {
-    {
-        Timed t(c, LB_K_ADJOINT);
-        k_adjoint<Pol, PEND, COLL><<<c->grid(), c->block(), 0, c->stream>>>(f, lam_next, lam_n, c->partial(), geo, cp);
-    }
-    k_sums_final<Pol, AdjointRates<COLL>::K><<<1, c->block(), 0, c->stream>>>(c->partial(), c->L.nblocks, domega,
-                                                                               0.0, 0.0, 1);
+                           const CollParams<double>& cp, double* partial, const double* prev, double* domega) {
+    Timed t(c, LB_K_ADJOINT);
+    k_adjoint<Pol, PEND, COLL><<<c->grid(), c->block(), 0, c->stream>>>(f, lam_next, lam_n, partial, geo, cp, prev,
+                                                                        c->L.nblocks, domega);
 }
 
-// One single-fluid adjoint step (kernel + the accumulation of its rate sums).
+template <int COLL>
+void adjoint_single_sums(lb_ctx* c, const double* partial, double* domega) {
+    k_sums_final<Pol, AdjointRates<COLL>::K><<<1, c->block(), 0, c->stream>>>(partial, c->L.nblocks, domega, 0.0,
+                                                                               0.0, 1);
+}
+
+// One single-fluid adjoint step for the context's collision.  sums_now: the
+// step's rate sums are reduced into domega by a separate launch right away;
+// otherwise they stay in `partial` for the next step (prev) or the caller.
 void adjoint_single_step(lb_ctx* c, const double* f, bool pending, const double* lam_next, double* lam_n,
-                         const Geo& geo, const CollParams<double>& cp, double* domega) {
-    switch (c->p.collision) {
-    case LB_TRT:
-        if (pending) adjoint_single_launch<true, COLL_TRT>(c, f, lam_next, lam_n, geo, cp, domega);
-        else adjoint_single_launch<false, COLL_TRT>(c, f, lam_next, lam_n, geo, cp, domega);
-        break;
-    case LB_MRT:
-        if (pending) adjoint_single_launch<true, COLL_MRT>(c, f, lam_next, lam_n, geo, cp, domega);
-        else adjoint_single_launch<false, COLL_MRT>(c, f, lam_next, lam_n, geo, cp, domega);
-        break;
-    default:
-        if (pending) adjoint_single_launch<true, COLL_BGK>(c, f, lam_next, lam_n, geo, cp, domega);
-        else adjoint_single_launch<false, COLL_BGK>(c, f, lam_next, lam_n, geo, cp, domega);
-    }
+                         const Geo& geo, const CollParams<double>& cp, double* partial, const double* prev,
+                         double* domega, bool sums_now) {
+    auto go = [&](auto coll) {
+        constexpr int COLL = decltype(coll)::value;
+        if (pending) adjoint_single_launch<true, COLL>(c, f, lam_next, lam_n, geo, cp, partial, prev, domega);
+        else adjoint_single_launch<false, COLL>(c, f, lam_next, lam_n, geo, cp, partial, prev, domega);
+        if (sums_now) adjoint_single_sums<COLL>(c, partial, domega);
+    };
+    if (c->p.collision == LB_TRT) go(std::integral_constant<int, COLL_TRT>{});
+    else if (c->p.collision == LB_MRT) go(std::integral_constant<int, COLL_MRT>{});
+    else go(std::integral_constant<int, COLL_BGK>{});
+}
+
+// The rate sums left in `partial` by the last step of a sweep.
+void adjoint_single_flush(lb_ctx* c, const double* partial, double* domega) {
+    if (c->p.collision == LB_TRT) adjoint_single_sums<COLL_TRT>(c, partial, domega);
+    else if (c->p.collision == LB_MRT) adjoint_single_sums<COLL_MRT>(c, partial, domega);
+    else adjoint_single_sums<COLL_BGK>(c, partial, domega);
 }
 
 }  // namespace
@@ -872,7 +884,8 @@ int lb_adjoint_step(lb_ctx* c, const double* f, int f_pending, const double* lam
     if (c->p.model != LB_SINGLE || c->p.storage != LB_F64) return LB_ENOTSUP;
     if (lam_n == lam_next || lam_n == f) return LB_EINVAL;
     c->launched = true;
-    adjoint_single_step(c, f, f_pending != 0, lam_next, lam_n, c->canonical_geo(), coll_params<double>(c), domega);
+    adjoint_single_step(c, f, f_pending != 0, lam_next, lam_n, c->canonical_geo(), coll_params<double>(c),
+                        c->partial(), nullptr, domega, true);
     return launch_status();
 }
 
@@ -893,11 +906,19 @@ int lb_adjoint_segment(lb_ctx* c, const double* f0, const double* post, int32_t 
     const auto cp = coll_params<double>(c);
     double* cur = lam;            // lambda^{n+1}
     double* nxt = work;
-    for (int32_t n = length - 1; n >= 0; --n) {
-        if (n > 0) adjoint_single_step(c, post + (size_t)(n - 1) * n19, true, cur, nxt, geo, cp, domega);
-        else adjoint_single_step(c, f0, false, cur, nxt, geo, cp, domega);
+    // two partial arrays in the context's partial buffer (16 doubles per
+    // block, each step using slots 8 b + k of one half): step k's block 0
+    // reduces step k-1's half while the other blocks fill its own
+    double* halves[2] = {c->partial(), c->partial() + 8 * (size_t)c->L.nblocks};
+    const double* prev = nullptr;
+    for (int32_t n = length - 1, k = 0; n >= 0; --n, ++k) {
+        double* part = halves[k & 1];
+        const double* fn = n > 0 ? post + (size_t)(n - 1) * n19 : f0;
+        adjoint_single_step(c, fn, n > 0, cur, nxt, geo, cp, part, prev, domega, false);
+        prev = part;
         std::swap(cur, nxt);
     }
+    adjoint_single_flush(c, prev, domega);
     if (cur != lam) {
         Timed t(c, LB_K_OTHER);
         if (hipMemcpyAsync(lam, cur, n19 * sizeof(double), hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
