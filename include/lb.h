@@ -86,6 +86,18 @@ extern "C" {
 #define LB_TRT      1
 #define LB_MRT      2
 
+/* The binary step's kernel.  LB_STEP_MARCH: one single-pass kernel that
+ * marches each tile column through a chunk of z planes, computing phi and its
+ * stencils on chip (608 B/site in FP64): fastest on large lattices.
+ * LB_STEP_TWO_PASS: a phi pass, then the fused collide (776 B/site), every
+ * site in parallel: fastest on small lattices, where the march has too few
+ * blocks to hide its per-plane latency.  LB_STEP_AUTO (0, the default): the
+ * march when its grid has at least 400 blocks (64 x 4 tiles, 16-plane chunks;
+ * 128^3 has 512), else the two-pass step. */
+#define LB_STEP_AUTO     0
+#define LB_STEP_MARCH    1
+#define LB_STEP_TWO_PASS 2
+
 /* Storage precision of the distributions.
  * LB_F64: f and g stored as IEEE double, FP64 arithmetic, stored directly.
  * LB_F32: stored as float deviations d_i = f_i - w_i*rho0 (g: g_i - w_i*phi0),
@@ -103,7 +115,8 @@ typedef struct lb_params {
                              kernels (the virtual vector length of the targetDP
                              execution model, Section III-C): 0 or 1 (default), 2, 4 */
     int32_t collision;    /* LB_BGK (default), LB_TRT or LB_MRT               */
-    int32_t reserved;     /* must be 0                                        */
+    int32_t binary_step;  /* LB_BINARY: which step kernel runs (LB_STEP_*); the
+                             two give the same bits; ignored for LB_SINGLE     */
     double  tau_f;        /* BGK relaxation time of f, > 0.5                  */
     double  A, B, kappa;  /* free energy (binary only); kappa >= 0            */
     double  mobility;     /* Cahn-Hilliard mobility M > 0 (binary only)       */

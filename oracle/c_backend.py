@@ -19,7 +19,7 @@ def _params_type():
     """The lb_params struct of include/lb.h (field order and types)."""
     class P(ctypes.Structure):
         _fields_ = [("nx", _i32), ("ny", _i32), ("nz", _i32), ("model", _i32), ("storage", _i32), ("vvl", _i32),
-                    ("collision", _i32), ("reserved", _i32), ("tau_f", ctypes.c_double), ("A", ctypes.c_double),
+                    ("collision", _i32), ("binary_step", _i32), ("tau_f", ctypes.c_double), ("A", ctypes.c_double),
                     ("B", ctypes.c_double), ("kappa", ctypes.c_double), ("mobility", ctypes.c_double),
                     ("gamma", ctypes.c_double), ("rho0", ctypes.c_double), ("phi0", ctypes.c_double),
                     ("tau_minus", ctypes.c_double), ("tau_bulk", ctypes.c_double),

@@ -73,7 +73,7 @@ static int check(const lb_params* p) {
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return LB_EINVAL;
     if ((int64_t)p->nx * p->ny * p->nz >= ((int64_t)1 << 29)) return LB_EINVAL;
     if (p->model != LB_SINGLE && p->model != LB_BINARY) return LB_EINVAL;
-    if (p->reserved != 0 || bad_tau(p->tau_f)) return LB_EINVAL;
+    if (p->binary_step < LB_STEP_AUTO || p->binary_step > LB_STEP_TWO_PASS || bad_tau(p->tau_f)) return LB_EINVAL;
     if (p->model == LB_BINARY &&
         (!isfinite(p->A) || !isfinite(p->B) || !(p->kappa >= 0.0) || !(p->mobility > 0.0) || !(p->gamma > 0.0)))
         return LB_EINVAL;

@@ -81,7 +81,7 @@ int check_params(const lb_params* p) {
     if (p->model != LB_SINGLE && p->model != LB_BINARY) return LB_EINVAL;
     if (p->storage != LB_F64 && p->storage != LB_F32 && p->storage != LB_F16) return LB_EINVAL;
     if (p->vvl != 0 && p->vvl != 1 && p->vvl != 2 && p->vvl != 4) return LB_EINVAL;
-    if (p->reserved != 0) return LB_EINVAL;
+    if (p->binary_step < LB_STEP_AUTO || p->binary_step > LB_STEP_TWO_PASS) return LB_EINVAL;
     if (p->collision != LB_BGK && p->collision != LB_TRT && p->collision != LB_MRT) return LB_EINVAL;
     auto valid_tau = [](double t) { return std::isfinite(t) && t > 0.5; };
     if (p->collision != LB_BGK && !valid_tau(p->tau_minus)) return LB_EINVAL;
@@ -298,11 +298,28 @@ int run_binary_march(lb_ctx* c) {
     return LB_OK;
 }
 
+// The single-pass march runs one block per tile column and chunk, each
+// marching its planes in sequence, so on small lattices it has too few blocks
+// to hide its per-plane latency: 64^3 FP64 (64 blocks) took 83 us a step
+// against 39 us for the two-pass step (phi pass + fused collide, every site in
+// parallel), 112^3 (392 blocks) the same 207 us for both, and 128^3 (512
+// blocks) 261 against 303 us; FP32 and FP16 cross over at the same grid size.
+// With LB_STEP_AUTO the march runs from kMarchMinBlocks blocks up.  The two
+// paths give the same bits.
+constexpr int kMarchMinBlocks = 400;
+
+template <class S>
+bool march_pays(const lb_ctx* c) {
+    if (c->p.binary_step == LB_STEP_MARCH) return true;
+    if (c->p.binary_step == LB_STEP_TWO_PASS) return false;
+    return c->template march_geo<typename March<S>::P, March<S>::bz>().nblocks >= kMarchMinBlocks;
+}
+
 template <class S>
 int run_collide(lb_ctx* c) {
     using T = typename Compute<S>::T;
     const bool bin = c->p.model == LB_BINARY;
-    if (bin && c->pending) return run_binary_march<S>(c);
+    if (bin && c->pending && march_pays<S>(c)) return run_binary_march<S>(c);
     if (bin) { int rc = run_phi<S>(c); if (rc) return rc; }
     const auto cp = coll_params<S>(c);
     const int src = c->cur, dst = c->pending ? 1 - c->cur : c->cur;
@@ -486,9 +503,27 @@ int run_step_record_binary(lb_ctx* c, int32_t n, S* post, typename Compute<S>::T
     constexpr int BZ = March<S>::bz;
     Geo g = c->template march_geo<MP, BZ>();
     g.dstride = N;
+    const bool march = march_pays<S>(c);
+    Geo cg = c->canonical_geo();
     for (int32_t k = 1; k < n; ++k) {
         const S* src = post + (size_t)(k - 1) * 2 * Q * N;
         S* dst = post + (size_t)k * 2 * Q * N;
+        if (!march) {
+            // two-pass: phi of the recorded state, then the fused collide, both on stride N
+            T* ph = phi ? phi + (size_t)k * N : (T*)c->phi();
+            {
+                Timed t(c, LB_K_PHI);
+                k_phi<Pol, S, true><<<c->grid(), c->block(), 0, c->stream>>>(src + Q * N, ph, cg, cp.phi0);
+            }
+            {
+                Timed t(c, LB_K_COLLIDE);
+                k_collide<Pol, MODEL_BINARY, S, true><<<c->grid(), c->block(), 0, c->stream>>>(
+                    src, src + Q * N, dst, dst + Q * N, ph, cg, cp);
+            }
+            rc = launch_status();
+            if (rc) return rc;
+            continue;
+        }
         {
             Timed t(c, LB_K_COLLIDE);
             const dim3 grid(g.nblocks), block(MP::TPB);
@@ -814,7 +849,8 @@ int lb_set_params(lb_ctx* c, const lb_params* p) {
     if (rc) return rc;
     const lb_params& q = c->p;
     if (p->nx != q.nx || p->ny != q.ny || p->nz != q.nz || p->model != q.model || p->storage != q.storage ||
-        p->vvl != q.vvl || p->collision != q.collision || p->rho0 != q.rho0 || p->phi0 != q.phi0)
+        p->vvl != q.vvl || p->collision != q.collision || p->binary_step != q.binary_step || p->rho0 != q.rho0 ||
+        p->phi0 != q.phi0)
         return LB_EINVAL;
     c->p = *p;
     return LB_OK;

@@ -17,6 +17,7 @@ LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_ENOTSUP = 0, -1, -2, -3, -4
 LB_SINGLE, LB_BINARY = 0, 1
 LB_F64, LB_F32, LB_F16 = 0, 1, 2
 LB_BGK, LB_TRT, LB_MRT = 0, 1, 2
+LB_STEP_AUTO, LB_STEP_MARCH, LB_STEP_TWO_PASS = 0, 1, 2
 LB_K_COLLIDE, LB_K_PHI, LB_K_STREAM, LB_K_ADJOINT, LB_K_OTHER = 0, 1, 2, 3, 4
 Q = 19
 
@@ -36,7 +37,7 @@ class lb_params(ctypes.Structure):
     _fields_ = [
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
         ("model", ctypes.c_int32), ("storage", ctypes.c_int32), ("vvl", ctypes.c_int32),
-        ("collision", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("collision", ctypes.c_int32), ("binary_step", ctypes.c_int32),
         ("tau_f", ctypes.c_double),
         ("A", ctypes.c_double), ("B", ctypes.c_double), ("kappa", ctypes.c_double),
         ("mobility", ctypes.c_double), ("gamma", ctypes.c_double),
@@ -48,7 +49,7 @@ class lb_params(ctypes.Structure):
 
 def make_params(nx, ny, nz, model=LB_SINGLE, storage=LB_F64, tau_f=1.0, A=-0.0625, B=0.0625,
                 kappa=0.04, mobility=0.45, gamma=1.0, rho0=1.0, phi0=0.0, vvl=1, collision=LB_BGK,
-                tau_minus=None, tau_bulk=None, tau_ghost_even=None, tau_ghost_odd=None):
+                tau_minus=None, tau_bulk=None, tau_ghost_even=None, tau_ghost_odd=None, binary_step=0):
     """lb_params with defaults; the relaxation times not given default to the
     ones that make each collision reduce to the simpler one (TRT to BGK, MRT
     to TRT)."""
@@ -56,7 +57,7 @@ def make_params(nx, ny, nz, model=LB_SINGLE, storage=LB_F64, tau_f=1.0, A=-0.062
     tb = tau_f if tau_bulk is None else tau_bulk
     tge = tau_f if tau_ghost_even is None else tau_ghost_even
     tgo = tm if tau_ghost_odd is None else tau_ghost_odd
-    return lb_params(nx, ny, nz, model, storage, vvl, collision, 0, tau_f, A, B, kappa, mobility, gamma,
+    return lb_params(nx, ny, nz, model, storage, vvl, collision, binary_step, tau_f, A, B, kappa, mobility, gamma,
                      rho0, phi0, tm, tb, tge, tgo)
 
 

@@ -47,7 +47,8 @@ def test_library_exports_every_declared_symbol(lib):
 def test_constants_match_header():
     text = open(HEADER).read()
     for name in ("LB_OK", "LB_EINVAL", "LB_ENOMEM", "LB_EDEVICE", "LB_ENOTSUP", "LB_SINGLE", "LB_BGK", "LB_TRT", "LB_MRT",
-                 "LB_BINARY", "LB_F64", "LB_F32", "LB_F16", "LB_K_COLLIDE", "LB_K_PHI",
+                 "LB_BINARY", "LB_F64", "LB_F32", "LB_F16", "LB_K_COLLIDE", "LB_K_PHI", "LB_STEP_AUTO",
+                 "LB_STEP_MARCH", "LB_STEP_TWO_PASS",
                  "LB_K_STREAM", "LB_K_ADJOINT", "LB_K_OTHER"):
         m = re.search(r"#define\s+%s\s+\(?(-?\d+)\)?" % name, text)
         assert m, name
@@ -119,8 +120,10 @@ def test_collision_values(lib):
     assert _ws(lb.make_params(4, 4, 4, model=lb.LB_BINARY, **mrt))[0] == lb.LB_OK
     assert _ws(lb.make_params(4, 4, 4, model=lb.LB_BINARY, collision=lb.LB_TRT, tau_minus=1.2))[0] == lb.LB_OK
     p = lb.make_params(4, 4, 4)
-    p.reserved = 3
+    p.binary_step = 3
     assert _ws(p)[0] == lb.LB_EINVAL
+    for step in (lb.LB_STEP_AUTO, lb.LB_STEP_MARCH, lb.LB_STEP_TWO_PASS):
+        assert _ws(lb.make_params(4, 4, 4, model=lb.LB_BINARY, binary_step=step))[0] == lb.LB_OK
 
 
 def test_vvl_values(lib):

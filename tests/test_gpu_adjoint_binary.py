@@ -85,15 +85,17 @@ def test_binary_adjoint_from_pending_fields(lbgpu):
         assert abs(got[k] - want[name]) <= 1e-12 * max(abs(want[name]), 1.0), name
 
 
+@pytest.mark.parametrize("step_kernel", [1, 2])          # LB_STEP_MARCH, LB_STEP_TWO_PASS
 @pytest.mark.parametrize("pending_start", [False, True])
 @pytest.mark.parametrize("n", [1, 4])
-def test_binary_step_record(lbgpu, pending_start, n):
+def test_binary_step_record(lbgpu, pending_start, n, step_kernel):
     """lb_step_record (binary) leaves the state of lb_step and records, per
-    step, the post-collision f and g whose propagation is the next state."""
+    step, the post-collision f and g whose propagation is the next state,
+    with either step kernel."""
     nx, ny, nz = 7, 5, 6
     prm = O.Params()
     f, g = _state(nx, ny, nz, seed=5)
-    lat = lbgpu.Lattice(nx, ny, nz, model=lbgpu.LB_BINARY)
+    lat = lbgpu.Lattice(nx, ny, nz, model=lbgpu.LB_BINARY, binary_step=step_kernel)
     lat.set_state(f, g)
     if pending_start:
         lat.step(1)

@@ -77,13 +77,17 @@ def test_single_fluid_steps(lbgpu, nx, ny, nz, nsteps):
     lat.close()
 
 
+STEP_KERNELS = {"march": 1, "two_pass": 2}       # LB_STEP_MARCH, LB_STEP_TWO_PASS: both forced at every size
+
+
+@pytest.mark.parametrize("path", sorted(STEP_KERNELS))
 @pytest.mark.parametrize("nx,ny,nz", SIZES)
 @pytest.mark.parametrize("nsteps", [1, 10])
-def test_binary_fluid_steps(lbgpu, nx, ny, nz, nsteps):
-    print("case binary", nx, ny, nz, nsteps, flush=True)
+def test_binary_fluid_steps(lbgpu, nx, ny, nz, nsteps, path):
+    print("case binary", nx, ny, nz, nsteps, path, flush=True)
     prm = O.Params()
     rho, u, phi = binary_case(nx, ny, nz, seed=2, phi_max=0.3, u_max=0.01)
-    lat = lbgpu.Lattice(nx, ny, nz, model=lbgpu.LB_BINARY, **params_of(prm))
+    lat = lbgpu.Lattice(nx, ny, nz, model=lbgpu.LB_BINARY, binary_step=STEP_KERNELS[path], **params_of(prm))
     lat.init_equilibrium(rho, u, phi)
     f0, g0 = lat.get_state()
     rf0, rg0 = O.init_binary(rho, u, phi, prm)
@@ -345,19 +349,21 @@ def test_mrt_reduced_precision(lbgpu, storage, tol):
     assert relerr(ug, uref) < tol
 
 
+@pytest.mark.parametrize("path", sorted(STEP_KERNELS))
 @pytest.mark.parametrize("coll", ["trt", "mrt"])
 @pytest.mark.parametrize("nx,ny,nz", [(16, 16, 16), (5, 6, 37), (70, 5, 17)])
-def test_binary_trt_mrt(lbgpu, coll, nx, ny, nz):
-    """Binary fluid with f relaxing by TRT or MRT: the two-pass collide of a
-    direct state and the single-pass march, against the oracle."""
-    print("case binary", coll, nx, ny, nz, flush=True)
+def test_binary_trt_mrt(lbgpu, coll, nx, ny, nz, path):
+    """Binary fluid with f relaxing by TRT or MRT: the collide of a direct
+    state, then steps by the single-pass march or the two-pass step, against
+    the oracle."""
+    print("case binary", coll, nx, ny, nz, path, flush=True)
     prm = O.Params(tau_f=0.8)
     taus = (0.8, 1.25, 1.4, 0.9, 1.2) if coll == "mrt" else (0.8, 1.25, 0.8, 0.8, 1.25)
     kw = dict(collision=lbgpu.LB_MRT if coll == "mrt" else lbgpu.LB_TRT, tau_minus=taus[1])
     if coll == "mrt":
         kw.update(tau_bulk=taus[2], tau_ghost_even=taus[3], tau_ghost_odd=taus[4])
     rho, u, phi = binary_case(nx, ny, nz, seed=21, phi_max=0.3, u_max=0.01)
-    lat = lbgpu.Lattice(nx, ny, nz, model=lbgpu.LB_BINARY, **params_of(prm), **kw)
+    lat = lbgpu.Lattice(nx, ny, nz, model=lbgpu.LB_BINARY, binary_step=STEP_KERNELS[path], **params_of(prm), **kw)
     f, g = O.step_binary(*O.init_binary(rho, u, phi, prm), prm, 1)      # off equilibrium
     lat.set_state(f, g)
     lat.collide()
@@ -386,3 +392,28 @@ def test_binary_mrt_reduced_precision(lbgpu, storage, tol):
     rf, rg = O.step_binary_mrt(*O.init_binary(rho, u, phi, prm), prm, taus, 10)
     uref, _rr = O.velocity(rf)
     assert relerr(ug, uref) < tol and relerr(pg, O.order_parameter(rg)) < tol
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("coll", ["bgk", "mrt"])
+@pytest.mark.parametrize("nx,ny,nz", [(5, 6, 7), (67, 9, 21), (64, 8, 33)])
+def test_binary_step_kernels_agree_bitwise(lbgpu, storage, coll, nx, ny, nz):
+    """The single-pass march and the two-pass step sum phi in the same order
+    and share the collision, so the states they produce are the same bits,
+    in every storage and collision; LB_STEP_AUTO is one of the two."""
+    code = {"f64": lbgpu.LB_F64, "f32": lbgpu.LB_F32, "f16": lbgpu.LB_F16}[storage]
+    kw = dict(collision=lbgpu.LB_MRT, tau_minus=1.25, tau_bulk=1.4, tau_ghost_even=0.9,
+              tau_ghost_odd=1.2) if coll == "mrt" else {}
+    rho, u, phi = binary_case(nx, ny, nz, seed=31, phi_max=0.3, u_max=0.01)
+    states = {}
+    for path, step in (("march", 1), ("two_pass", 2), ("auto", 0)):
+        lat = lbgpu.Lattice(nx, ny, nz, model=lbgpu.LB_BINARY, storage=code, phi0=float(phi.mean()),
+                            binary_step=step, **kw)
+        lat.init_equilibrium(rho, u, phi)
+        lat.step(7)
+        states[path] = lat.get_state()
+        lat.close()
+    for a, b in zip(states["march"], states["two_pass"]):
+        assert torch.equal(a, b)
+    for a, b in zip(states["march"], states["auto"]):
+        assert torch.equal(a, b)
