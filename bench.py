@@ -192,7 +192,8 @@ def bench_adjoint(args, n, desc, T=200, K=20):
         loss.backward()
         return f.grad, tau.grad
 
-    for _ in range(max(args.warmup // 10, 1)):
+    n_warm = max(args.warmup // 10, 1)          # whole rollouts: forward + backward
+    for _ in range(n_warm):
         once()
     torch.cuda.synchronize()
     iters = max(args.steps // 100, 1)
@@ -215,7 +216,7 @@ def bench_adjoint(args, n, desc, T=200, K=20):
     achieved = alg["adjoint"] * nsite / (avg * 1e-3) / 1e9
     out = {
         "metric": METRIC, "value": round(nsite * T * iters / wall / 1e6, 2), "unit": "MLUPS",
-        "n_gpus": 1, "steps": T * iters, "warmup": args.warmup,
+        "n_gpus": 1, "steps": T * iters, "warmup": T * n_warm,
         "ms_per_step": round(wall * 1e3 / (T * iters), 5), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": desc, "nx": n, "ny": n, "nz": n, "tau": taus, "rollout_steps": T,
@@ -251,7 +252,8 @@ def bench_adjoint_binary(args, n, desc, T=200, K=20):
         loss.backward()
         return p0.grad, torch.stack([kap.grad, mob.grad, tau.grad])
 
-    for _ in range(max(args.warmup // 10, 1)):
+    n_warm = max(args.warmup // 10, 1)          # whole rollouts: forward + backward
+    for _ in range(n_warm):
         once()
     torch.cuda.synchronize()
     iters = max(args.steps // 100, 1)
@@ -277,7 +279,7 @@ def bench_adjoint_binary(args, n, desc, T=200, K=20):
     achieved = alg["adjoint"] * nsite / (per_step_ms * 1e-3) / 1e9 if per_step_ms else 0.0
     out = {
         "metric": METRIC, "value": round(nsite * T * iters / wall / 1e6, 2), "unit": "MLUPS",
-        "n_gpus": 1, "steps": T * iters, "warmup": args.warmup,
+        "n_gpus": 1, "steps": T * iters, "warmup": T * n_warm,
         "ms_per_step": round(wall * 1e3 / (T * iters), 5), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": desc, "nx": n, "ny": n, "nz": n, "rollout_steps": T, "checkpoint_every": K,
