@@ -354,7 +354,10 @@ __global__ __launch_bounds__(P::TPB) void k_collide_single_strided(const S* fsrc
 // consecutive z planes.  phi(s) = phi0 + sum_i e_i(s - c_i) needs the pulled
 // g of s, which the collision of s needs anyway: each lane gathers g for
 // plane z+1, sums it into the plane's phi tile in LDS and keeps the 19 values
-// in registers for the next plane's collision.  The x/y halo ring of the
+// for the next plane's collision, in registers or (GLDS) in LDS.  On small
+// lattices the host picks the two-pass step instead, because a few blocks
+// walking their planes in sequence cannot hide the per-plane latency.
+// The x/y halo ring of the
 // tile (2 TX + 2 TY sites per plane) is summed by one lane each from its own
 // gather; the chunk's first and last plane need one extra plane of phi each.
 // Three phi planes (z-1, z, z+1) rotate in LDS.  Lanes outside the lattice
@@ -1098,9 +1101,9 @@ enum { LG_GATHER = 0, LG_GATHER_KEEP = 1, LG_PULLED_KEEP = 2 };
 // Writes lambda_f^n, P^n to p_out (LG != LG_GATHER) and the five
 // sensitivity fields afield[k*N + s] (a_phi, a_Gx, a_Gy, a_Gz, a_lap); block
 // partials of dL/domega_f, dL/domega_g and dL/dkappa go to
-// partial[8 b + 0..2].  Only lambda_f stays in registers: f is reduced to
-// its moments (and sum lambda_f f) as it loads, and g with lambda_g are
-// consumed in one pass once u is known.
+// partial[8 b + 0..2].  Only lambda_f is kept, in LDS: f is reduced to its
+// moments (and sum lambda_f f) as it loads, and g with lambda_g are consumed
+// in one pass once u is known.
 template <class P, bool F_PENDING, int LG>
 __global__ __launch_bounds__(P::TPB) void k_adjoint_binary(const double* __restrict__ fn,
                                                            const double* __restrict__ gn,
@@ -1240,9 +1243,10 @@ __global__ __launch_bounds__(P::TPB) void k_adjoint_binary_init(const double* __
 //                      + sum_a [a_lap(s + e_a) + a_lap(s - e_a)]   (= dL/dphi(s)).
 // B_ONLY (the reverse of the initialisation, and each step of a sweep in
 // the pair form): out[s] = b.  Otherwise out is lambda_g^n:
-// out_j(s) = (1 - omega_g) lambda_g^{n+1}_j(s + c_j) + b(s).  Block 0 also adds the K block partials
-// the local kernel left (partial[8 b + k], b < nblocks) into sums[0..K), in
-// block order, which saves the step a separate reduction launch.
+// out_j(s) = (1 - omega_g) lambda_g^{n+1}_j(s + c_j) + b(s).  Block 0 also
+// adds the K block partials the local kernel left (partial[8 b + k],
+// b < nblocks) into sums[0..K), in block order, which saves the step a
+// separate reduction launch.
 template <class P, bool B_ONLY, int K>
 __global__ __launch_bounds__(P::TPB) void k_adjoint_binary_stencil(const double* __restrict__ afield,
                                                                    const double* __restrict__ lg_next,
