@@ -106,17 +106,22 @@ def test_single_fluid_fp64_largest_lattice(lbgpu):
         assert np.abs(f[:, k] - want).max() <= 1e-12 * np.abs(want).max(), p
 
 
-def test_binary_fp64_largest_offsets(lbgpu):
+@pytest.mark.parametrize("step_kernel", [1, 2])          # LB_STEP_MARCH, LB_STEP_TWO_PASS
+def test_binary_fp64_largest_offsets(lbgpu, step_kernel):
+    """Two steps: the first collides the initial (direct) state in place, the
+    second pulls from the pending one through the chosen step kernel; the
+    oracle's 11^3 block around each sample is exact at its centre for two
+    steps after the initialisation."""
     n = (1024, 512, 511)                            # 267,911,168 sites: FP64 offsets up to 2^31
-    print("case binary FP64 max size", n, flush=True)
+    print("case binary FP64 max size", n, "step kernel", step_kernel, flush=True)
     prm = O.Params()
     _release()
     try:
-        lat = lbgpu.Lattice(*n, model=lbgpu.LB_BINARY)
+        lat = lbgpu.Lattice(*n, model=lbgpu.LB_BINARY, binary_step=step_kernel)
         rho, u, phi = _device_fields(n)
         lat.init_equilibrium(rho, u, phi)
         del rho, u, phi
-        lat.step(1)
+        lat.step(2)
         pts = _samples(n, 6, seed=2)
         f, g = _gathered(lat, pts, n)
         stats = lat.conserved_sums().cpu().numpy()
@@ -124,9 +129,9 @@ def test_binary_fp64_largest_offsets(lbgpu):
     finally:
         _release()
     for k, p in enumerate(pts):
-        rho, u, phi = _block(p, n, r=3)
-        wf, wg = O.step_binary(*O.init_binary(rho, u, phi, prm), prm, 1)
-        wf, wg = wf[:, 3, 3, 3], wg[:, 3, 3, 3]
+        rho, u, phi = _block(p, n, r=5)
+        wf, wg = O.step_binary(*O.init_binary(rho, u, phi, prm), prm, 2)
+        wf, wg = wf[:, 5, 5, 5], wg[:, 5, 5, 5]
         assert np.abs(f[:, k] - wf).max() <= 1e-12 * np.abs(wf).max(), p
         assert np.abs(g[:, k] - wg).max() <= 1e-12 * np.abs(wg).max(), p
     assert np.isfinite(stats).all()
