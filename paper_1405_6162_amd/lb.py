@@ -115,14 +115,22 @@ def _check(fn, rc):
         raise LBError(fn, rc)
 
 
-def _ptr(t):
+def _ptr(t, dtype=None):
+    """Device address of a contiguous CUDA tensor (None -> NULL); with dtype
+    given, the tensor must have it (the C side reads raw memory)."""
     if t is None:
         return None
     if not t.is_cuda:
         raise ValueError("liblb.so takes device tensors")
     if not t.is_contiguous():
         raise ValueError("tensor must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError("expected a %s tensor, got %s" % (dtype, t.dtype))
     return t.data_ptr()
+
+
+def _f64(t):
+    return _ptr(t, torch.float64)
 
 
 def _stream():
@@ -152,7 +160,7 @@ def lb_set_stream(ctx, stream):
 
 
 def lb_init_equilibrium(ctx, rho, u, phi=None):
-    _check("lb_init_equilibrium", _lib.lb_init_equilibrium(ctx, _ptr(rho), _ptr(u), _ptr(phi)))
+    _check("lb_init_equilibrium", _lib.lb_init_equilibrium(ctx, _f64(rho), _f64(u), _f64(phi)))
 
 
 def lb_collide(ctx):
@@ -168,15 +176,15 @@ def lb_step(ctx, nsteps):
 
 
 def lb_moments(ctx, rho, u, phi=None):
-    _check("lb_moments", _lib.lb_moments(ctx, _ptr(rho), _ptr(u), _ptr(phi)))
+    _check("lb_moments", _lib.lb_moments(ctx, _f64(rho), _f64(u), _f64(phi)))
 
 
 def lb_conserved_sums(ctx, out):
-    _check("lb_conserved_sums", _lib.lb_conserved_sums(ctx, _ptr(out)))
+    _check("lb_conserved_sums", _lib.lb_conserved_sums(ctx, _f64(out)))
 
 
 def lb_field_stats(ctx, out):
-    _check("lb_field_stats", _lib.lb_field_stats(ctx, _ptr(out)))
+    _check("lb_field_stats", _lib.lb_field_stats(ctx, _f64(out)))
 
 
 def lb_get_state(ctx, f, g=None):
@@ -196,8 +204,8 @@ def lb_step_record(ctx, nsteps, post, phi=None):
 
 
 def lb_adjoint_step(ctx, f, lam_next, lam_n, domega, f_pending=False):
-    _check("lb_adjoint_step", _lib.lb_adjoint_step(ctx, _ptr(f), 1 if f_pending else 0, _ptr(lam_next),
-                                                   _ptr(lam_n), _ptr(domega)))
+    _check("lb_adjoint_step", _lib.lb_adjoint_step(ctx, _f64(f), 1 if f_pending else 0, _f64(lam_next),
+                                                   _f64(lam_n), _f64(domega)))
 
 
 def lb_set_params(ctx, params):
@@ -206,36 +214,37 @@ def lb_set_params(ctx, params):
 
 def lb_adjoint_step_binary(ctx, f, g, lf_next, lg_next, lf_n, lg_n, grads, pending=False, phi=None):
     _check("lb_adjoint_step_binary", _lib.lb_adjoint_step_binary(
-        ctx, _ptr(f), _ptr(g), _ptr(phi), 1 if pending else 0, _ptr(lf_next), _ptr(lg_next), _ptr(lf_n),
-        _ptr(lg_n), _ptr(grads)))
+        ctx, _f64(f), _f64(g), _f64(phi), 1 if pending else 0, _f64(lf_next), _f64(lg_next), _f64(lf_n),
+        _f64(lg_n), _f64(grads)))
 
 
 def lb_adjoint_init_binary(ctx, rho, u, phi, lf0, lg0, dphi, drho, du, dkappa):
     _check("lb_adjoint_init_binary", _lib.lb_adjoint_init_binary(
-        ctx, _ptr(rho), _ptr(u), _ptr(phi), _ptr(lf0), _ptr(lg0), _ptr(dphi), _ptr(drho), _ptr(du),
-        _ptr(dkappa)))
+        ctx, _f64(rho), _f64(u), _f64(phi), _f64(lf0), _f64(lg0), _f64(dphi), _f64(drho), _f64(du),
+        _f64(dkappa)))
 
 
 def lb_adjoint_segment(ctx, f0, post, length, lam, work, domega):
-    _check("lb_adjoint_segment", _lib.lb_adjoint_segment(ctx, _ptr(f0), _ptr(post), int(length), _ptr(lam),
-                                                         _ptr(work), _ptr(domega)))
+    _check("lb_adjoint_segment", _lib.lb_adjoint_segment(ctx, _f64(f0), _f64(post), int(length), _f64(lam),
+                                                         _f64(work), _f64(domega)))
 
 
 def lb_adjoint_segment_binary(ctx, f0, g0, post, phi, length, lf, lg, work, grads):
     _check("lb_adjoint_segment_binary", _lib.lb_adjoint_segment_binary(
-        ctx, _ptr(f0), _ptr(g0), _ptr(post), _ptr(phi), int(length), _ptr(lf), _ptr(lg), _ptr(work), _ptr(grads)))
+        ctx, _f64(f0), _f64(g0), _f64(post), _f64(phi), int(length), _f64(lf), _f64(lg), _f64(work), _f64(grads)))
 
 
 def lb_mask_index(ctx, mask, index, count):
-    _check("lb_mask_index", _lib.lb_mask_index(ctx, _ptr(mask), _ptr(index), _ptr(count)))
+    _check("lb_mask_index", _lib.lb_mask_index(ctx, _ptr(mask, torch.uint8), _ptr(index, torch.int32),
+                                               _ptr(count, torch.int64)))
 
 
 def lb_get_sites(ctx, index, m, f_packed, g_packed=None):
-    _check("lb_get_sites", _lib.lb_get_sites(ctx, _ptr(index), int(m), _ptr(f_packed), _ptr(g_packed)))
+    _check("lb_get_sites", _lib.lb_get_sites(ctx, _ptr(index, torch.int32), int(m), _ptr(f_packed), _ptr(g_packed)))
 
 
 def lb_set_sites(ctx, index, m, f_packed, g_packed=None):
-    _check("lb_set_sites", _lib.lb_set_sites(ctx, _ptr(index), int(m), _ptr(f_packed), _ptr(g_packed)))
+    _check("lb_set_sites", _lib.lb_set_sites(ctx, _ptr(index, torch.int32), int(m), _ptr(f_packed), _ptr(g_packed)))
 
 
 def lb_profile(ctx, enable):

@@ -346,3 +346,17 @@ def test_mrt_shear_wave_32_adjoint_vs_finite_differences(lbgpu):
         gk = taut.grad[k].item()
         print("  dL/d%s adjoint %.9e fd %.9e" % (names[k], gk, fd), flush=True)
         assert abs(fd - gk) <= 1e-6 * abs(gk) + floor, names[k]
+
+
+def test_bindings_refuse_wrong_dtypes(lbgpu):
+    """The FP64-only calls check their tensors' dtype before passing raw
+    device addresses to the library."""
+    lat = lbgpu.Lattice(4, 4, 4)
+    f = torch.zeros((19, 4, 4, 4), dtype=torch.float32, device="cuda")
+    lam = torch.zeros((19, 4, 4, 4), dtype=torch.float64, device="cuda")
+    dw = torch.zeros(1, dtype=torch.float64, device="cuda")
+    with pytest.raises(TypeError):
+        lbgpu.lb_adjoint_step(lat.ctx, f, lam, torch.empty_like(lam), dw)
+    with pytest.raises(TypeError):
+        lbgpu.lb_moments(lat.ctx, torch.empty((4, 4, 4), dtype=torch.float32, device="cuda"), None)
+    lat.close()
