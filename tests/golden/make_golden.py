@@ -1,0 +1,57 @@
+"""Writes the stored expected values under tests/golden/ from the oracle
+alone (oracle/lb_oracle.py and the seeded inputs; nothing from the GPU
+library).  The paper prints no worked example, so these fixtures are the
+oracle's own results on two tiny seeded cases, kept so that a later change
+of the oracle's arithmetic shows up as a failing test.
+
+    python tests/golden/make_golden.py
+"""
+
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle import lb_oracle as O  # noqa: E402
+from paper_1405_6162_amd import inputs  # noqa: E402
+
+CASES = {
+    # name: (model, (nx, ny, nz), steps, seed)
+    "single_4x4x4_3steps": ("single", (4, 4, 4), 3, 7),
+    "binary_5x4x3_2steps": ("binary", (5, 4, 3), 2, 8),
+}
+
+
+def compute(model, shape, steps, seed):
+    """The case's state after `steps` steps, as one (k, 19, nz, ny, nx) array
+    (k = 1 single fluid: f; k = 2 binary: f, g)."""
+    nx, ny, nz = shape
+    if model == "single":
+        rho, u = inputs.single_fluid_random(nx, ny, nz, seed=seed)
+        f = O.step_single(O.init_single(rho, u), 1.0, steps)
+        return f[None]
+    prm = O.Params()
+    rho, u, phi = inputs.spinodal_quench(nx, ny, nz, seed=seed, phi_max=0.3)
+    f, g = O.step_binary(*O.init_binary(rho, u, phi, prm), prm, steps)
+    return np.stack([f, g])
+
+
+def path(name):
+    return os.path.join(HERE, name + ".txt")
+
+
+def main():
+    for name, (model, shape, steps, seed) in CASES.items():
+        a = compute(model, shape, steps, seed)
+        header = ("%s: %s fluid, lattice %s (nx, ny, nz), %d steps from the seeded initial state (seed %d), "
+                  "oracle FP64; array shape %s, C order, written by tests/golden/make_golden.py"
+                  % (name, model, shape, steps, seed, a.shape))
+        np.savetxt(path(name), a.reshape(-1), fmt="%.17e", header=header)
+        print(path(name))
+
+
+if __name__ == "__main__":
+    main()
