@@ -709,7 +709,7 @@ def stencil_transpose(a_phi, a_G, a_lap):
     return b
 
 
-def adjoint_step_binary(f_n, g_n, lf_next, lg_next, prm):
+def adjoint_step_binary(f_n, g_n, lf_next, lg_next, prm, taus=None):
     """Reverse of one binary step.  With lambda*_i(s) = lambda^{n+1}_i(s + c_i)
     for both distributions,
         lf^n_j = (1 - omega_f) lf*_j + omega_f Sf
@@ -720,7 +720,15 @@ def adjoint_step_binary(f_n, g_n, lf_next, lg_next, prm):
     transposed stencil of the sensitivities (stencil_transpose), the same for
     every j because phi = sum_j g_j.  Also returns the parameter sensitivities
     dL/domega_f = sum lf* (f^eq - f), dL/domega_g = sum lg* (g^eq - g) and
-    dL/dkappa (at fixed omega)."""
+    dL/dkappa (at fixed omega).
+
+    taus: None for the BGK step above, else the five times of f's
+    moment-space collision (collide_binary_mrt; TRT is the case of even
+    groups at one time and odd groups at another).  Omega is symmetric and
+    f^eq depends on f only through rho and u, so every omega_f lf* above
+    becomes mu = Omega lf* (and (1 - omega_f) lf* becomes lf* - mu); the rate
+    sensitivities are then dL/domega_k = sum (P_k lf*) (f^eq - f) for the
+    group projectors P_k, returned as grads["omega_<group>"]."""
     omega_f, omega_g = 1.0 / prm.tau_f, 1.0 / prm.tau_g
     lf = np.empty_like(lf_next)
     lg = np.empty_like(lg_next)
@@ -729,20 +737,30 @@ def adjoint_step_binary(f_n, g_n, lf_next, lg_next, prm):
         lg[i] = neighbour(lg_next[i], C[i])
     phi, G, lap, mu, P = binary_fields(g_n, prm)
     u, rho = velocity(f_n)
+    if taus is None:
+        mu_f = omega_f * lf
+    else:
+        mu_f = np.einsum("ij,j...->i...", relaxation_matrix(taus), lf)
     a_phi, a_G, a_lap, d_kappa, (Sf, Tf, Tg) = binary_stencil_sensitivities(
-        lf, lg, phi, G, lap, u, prm, omega_f, omega_g)
+        mu_f, lg, phi, G, lap, u, prm, 1.0, omega_g)
     b = stencil_transpose(a_phi, a_G, a_lap)
     lf_n = np.empty_like(lf)
     lg_n = np.empty_like(lg)
     for j in range(NQ):
-        acc = omega_f * Sf
+        acc = Sf
         for a in range(3):
-            acc = acc + (omega_f * Tf[a] + omega_g * phi / rho * Tg[a]) * (C[j, a] - u[a])
-        lf_n[j] = (1.0 - omega_f) * lf[j] + acc
+            acc = acc + (Tf[a] + omega_g * phi / rho * Tg[a]) * (C[j, a] - u[a])
+        lf_n[j] = lf[j] - mu_f[j] + acc
         lg_n[j] = (1.0 - omega_g) * lg[j] + b
     feq = equilibrium_f(rho, u, P)
     geq = equilibrium_g(phi, u, mu, prm)
-    grads = {"omega_f": (lf * (feq - f_n)).sum(), "omega_g": (lg * (geq - g_n)).sum(), "kappa": d_kappa}
+    grads = {"omega_g": (lg * (geq - g_n)).sum(), "kappa": d_kappa}
+    if taus is None:
+        grads["omega_f"] = (lf * (feq - f_n)).sum()
+    else:
+        proj = relaxation_projectors()
+        for k in MRT_RATES:
+            grads["omega_" + k] = np.einsum("i...,ij,j...->...", lf, proj[k], feq - f_n).sum()
     return lf_n, lg_n, grads
 
 
@@ -778,25 +796,32 @@ def binary_loss_seed(f, g, beta=1.0):
     return velocity_loss_seed(f), lg
 
 
-def rollout_gradient_binary(rho, u, phi, prm, nsteps, beta=1.0):
+def rollout_gradient_binary(rho, u, phi, prm, nsteps, beta=1.0, taus=None):
     """Gradient of binary_loss after nsteps binary steps from
     init_binary(rho, u, phi) by a plain reverse sweep over every stored
     state (small lattices only).  Returns (L, dL/dphi0, dL/drho0, dL/du0,
-    {tau_f, mobility, kappa})."""
+    {tau_f, mobility, kappa}); with taus (the five moment-space times of f,
+    step_binary_mrt) the f times are returned as tau_<group> instead of
+    tau_f."""
     f, g = init_binary(rho, u, phi, prm)
     states = [(f, g)]
     for _ in range(nsteps):
-        f, g = step_binary(f, g, prm)
+        f, g = step_binary(f, g, prm) if taus is None else step_binary_mrt(f, g, prm, taus)
         states.append((f, g))
     loss = binary_loss(f, g, beta)
     lf, lg = binary_loss_seed(f, g, beta)
-    dw_f = dw_g = dk = 0.0
+    fkeys = ["omega_f"] if taus is None else ["omega_" + k for k in MRT_RATES]
+    dw = {k: 0.0 for k in fkeys + ["omega_g", "kappa"]}
     for n in range(nsteps - 1, -1, -1):
-        lf, lg, gr = adjoint_step_binary(states[n][0], states[n][1], lf, lg, prm)
-        dw_f, dw_g, dk = dw_f + gr["omega_f"], dw_g + gr["omega_g"], dk + gr["kappa"]
+        lf, lg, gr = adjoint_step_binary(states[n][0], states[n][1], lf, lg, prm, taus)
+        for k in dw:
+            dw[k] = dw[k] + gr[k]
     dphi, drho, du, dk0 = adjoint_init_binary(rho, u, phi, lf, lg, prm)
     # omega = 1/tau; tau_g = M/Gamma + 1/2
-    grads = {"tau_f": -dw_f / prm.tau_f ** 2,
-             "mobility": -dw_g / prm.tau_g ** 2 / prm.gamma,
-             "kappa": dk + dk0}
+    grads = {"mobility": -dw["omega_g"] / prm.tau_g ** 2 / prm.gamma, "kappa": dw["kappa"] + dk0}
+    if taus is None:
+        grads["tau_f"] = -dw["omega_f"] / prm.tau_f ** 2
+    else:
+        for k, t in zip(MRT_RATES, taus):
+            grads["tau_" + k] = -dw["omega_" + k] / (t * t)
     return loss, dphi, drho, du, grads

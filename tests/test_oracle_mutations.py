@@ -152,6 +152,12 @@ def _mut_projectors_swapped():
     return P
 
 
+def _mut_relaxation_odd_times_swapped(taus):
+    t = list(taus)
+    t[1], t[4] = t[4], t[1]
+    return O.relaxation_matrix.__wrapped__(tuple(t))
+
+
 def _swap_weights():
     w = O.W.copy()
     c2 = (O.C * O.C).sum(1)
@@ -194,6 +200,9 @@ MUTATIONS = {
                                                      [pins.test_mrt_adjoint_step_matches_complex_step]),
     "MRT adjoint: bulk and even-ghost projectors swapped": ("relaxation_projectors", _mut_projectors_swapped,
                                                             [pins.test_mrt_adjoint_step_matches_complex_step]),
+    "binary MRT adjoint: flux and odd-ghost times swapped in Omega": (
+        "relaxation_matrix", _mut_relaxation_odd_times_swapped,
+        [pins.test_binary_mrt_adjoint_step_matches_complex_step]),
 }
 
 # non-callable attributes replaced by a value

@@ -764,3 +764,89 @@ def test_binary_mrt_reduces_and_conserves():
     np.testing.assert_allclose(O.momentum(fs), O.momentum(f), rtol=0, atol=1e-16)
     np.testing.assert_allclose(O.order_parameter(gs), O.order_parameter(g), rtol=0, atol=1e-15)
     np.testing.assert_array_equal(gs, b[1])
+
+
+# The binary adjoint with f relaxing in moment space (MRT, and TRT as its
+# two-time case): complex-step derivatives of step_binary_mrt pin mu = Omega
+# lambda* and the per-group rate sums.
+
+BIN_MRT_TAUS = (0.8, 1.15, 1.3, 0.9, 1.2)
+
+
+def _binary_mrt_rollout_loss(rho, u, phi, prm, taus, T, beta):
+    f, g = O.init_binary(rho, u, phi, prm)
+    return O.binary_loss(*O.step_binary_mrt(f, g, prm, taus, T), beta)
+
+
+def test_binary_mrt_adjoint_step_matches_complex_step():
+    rho, u, phi = _binary_adjoint_case()
+    prm, taus, h = O.Params(), BIN_MRT_TAUS, 1e-30
+    f, g = O.step_binary_mrt(*O.init_binary(rho, u, phi, prm), prm, taus, 1)
+    rng = np.random.default_rng(16)
+    lf1, lg1 = rng.standard_normal(f.shape), rng.standard_normal(g.shape)
+    lf0, lg0, grads = O.adjoint_step_binary(f, g, lf1, lg1, prm, taus)
+
+    def proj(fc, gc, t=taus, p=prm):
+        a, b = O.step_binary_mrt(fc, gc, p, t, 1)
+        return (lf1 * a).sum() + (lg1 * b).sum()
+    for which, lam in (("f", lf0), ("g", lg0)):
+        for (i, s) in inputs.sample_components(f[0].size, 10, seed=17):
+            fc, gc = f.astype(np.complex128), g.astype(np.complex128)
+            (fc if which == "f" else gc).reshape(19, -1)[i, s] += 1j * h
+            d = proj(fc, gc).imag / h
+            assert abs(d - lam.reshape(19, -1)[i, s]) <= 1e-12 * np.abs(lam).max()
+    cf, cg = f.astype(np.complex128), g.astype(np.complex128)
+    for k, name in enumerate(O.MRT_RATES):
+        t = list(taus)
+        t[k] = t[k] + 1j * h
+        d = proj(cf, cg, tuple(t)).imag / h                      # dL/dtau_k = -dL/domega_k / tau_k^2
+        assert abs(d + grads["omega_" + name] / taus[k] ** 2) <= 1e-12 * abs(d), name
+
+
+def test_binary_mrt_adjoint_rollout_matches_complex_step():
+    """Whole rollout: dL/dphi0 at every site, the five f times, M and kappa."""
+    import dataclasses
+    rho, u, phi = _binary_adjoint_case()
+    prm, taus, T, beta, h = O.Params(), BIN_MRT_TAUS, 3, 0.5, 1e-30
+    loss, dphi, _dr, du, grads = O.rollout_gradient_binary(rho, u, phi, prm, T, beta, taus=taus)
+    assert loss > 0 and "tau_f" not in grads
+    cx = lambda a: a.astype(np.complex128)
+    for s in np.ndindex(phi.shape):
+        p = cx(phi)
+        p[s] += 1j * h
+        d = _binary_mrt_rollout_loss(cx(rho), cx(u), p, prm, taus, T, beta).imag / h
+        assert abs(d - dphi[s]) <= 1e-12 * np.abs(dphi).max()
+    v = cx(u)
+    v[(1, 2, 1, 3)] += 1j * h
+    d = _binary_mrt_rollout_loss(cx(rho), v, cx(phi), prm, taus, T, beta).imag / h
+    assert abs(d - du[1, 2, 1, 3]) <= 1e-12 * np.abs(du).max()
+    for k, name in enumerate(O.MRT_RATES):
+        t = list(taus)
+        t[k] = t[k] + 1j * h
+        d = _binary_mrt_rollout_loss(cx(rho), cx(u), cx(phi), prm, tuple(t), T, beta).imag / h
+        assert abs(d - grads["tau_" + name]) <= 1e-11 * abs(d), name
+    for name in ("kappa", "mobility"):
+        p2 = dataclasses.replace(prm, **{name: getattr(prm, name) + 1j * h})
+        d = _binary_mrt_rollout_loss(cx(rho), cx(u), cx(phi), p2, taus, T, beta).imag / h
+        assert abs(d - grads[name]) <= 1e-11 * abs(d), name
+
+
+def test_binary_trt_adjoint_central_differences():
+    """Independent of complex arithmetic: central differences (eps 1e-6) on
+    the two TRT times (even groups tied to tau_plus, odd to tau_minus) and a
+    phi0 component."""
+    rho, u, phi = _binary_adjoint_case()
+    prm, T, eps, tp, tm = O.Params(), 2, 1e-6, 0.85, 1.2
+    trt = lambda a, b: (a, b, a, a, b)
+    _loss, dphi, _dr, _du, grads = O.rollout_gradient_binary(rho, u, phi, prm, T, taus=trt(tp, tm))
+    L = lambda p, t: _binary_mrt_rollout_loss(rho, u, p, prm, t, T, 1.0)
+    d_plus = (L(phi, trt(tp + eps, tm)) - L(phi, trt(tp - eps, tm))) / (2 * eps)
+    d_minus = (L(phi, trt(tp, tm + eps)) - L(phi, trt(tp, tm - eps))) / (2 * eps)
+    g_plus = grads["tau_shear"] + grads["tau_bulk"] + grads["tau_ghost_even"]
+    g_minus = grads["tau_flux"] + grads["tau_ghost_odd"]
+    assert abs(d_plus - g_plus) <= 1e-6 * abs(g_plus)
+    assert abs(d_minus - g_minus) <= 1e-6 * abs(g_minus)
+    pp, pm = phi.copy(), phi.copy()
+    pp[1, 2, 3] += eps
+    pm[1, 2, 3] -= eps
+    assert abs((L(pp, trt(tp, tm)) - L(pm, trt(tp, tm))) / (2 * eps) - dphi[1, 2, 3]) <= 1e-6 * np.abs(dphi).max()
