@@ -1094,6 +1094,12 @@ __device__ __forceinline__ void phi_stencil(const double* __restrict__ phi, cons
 // writing lambda_g (304), at the price of the local kernel storing P (152).
 enum { LG_GATHER = 0, LG_GATHER_KEEP = 1, LG_PULLED_KEEP = 2 };
 
+// Omega lambda at direction i under TRT, from lambda_i and lambda_opp(i):
+// omega_+ times the even part plus omega_- times the odd part.
+__device__ __forceinline__ double trt_mu(double l, double lo, const CollParams<double>& cp) {
+    return cp.omega_f * 0.5 * (l + lo) + cp.omega_m * 0.5 * (l - lo);
+}
+
 // Local part of the binary adjoint step.  fn, gn: f^n and g^n (canonical,
 // or the recorded post-collision fields of the previous step when
 // F_PENDING, pulled); phi: phi^n (canonical); lf_next: lambda_f^{n+1};
@@ -1104,7 +1110,14 @@ enum { LG_GATHER = 0, LG_GATHER_KEEP = 1, LG_PULLED_KEEP = 2 };
 // partial[8 b + 0..2].  Only lambda_f is kept, in LDS: f is reduced to its
 // moments (and sum lambda_f f) as it loads, and g with lambda_g are consumed
 // in one pass once u is known.
-template <class P, bool F_PENDING, int LG>
+// COLL_TRT: f relaxes by two times (even and odd parts of f - f^eq), so
+// mu = Omega lambda*_f = omega_+ (lambda*_i + lambda*_opp(i))/2
+//                      + omega_- (lambda*_i - lambda*_opp(i))/2
+// takes the place of omega_f lambda*_f and lambda*_f - mu that of
+// (1 - omega_f) lambda*_f.  lambda*_f is then loaded before f, so that both
+// directions of a pair are at hand, and the even and odd rate sums
+// sum (P_+- lambda*_f)(f^eq - f) go to partial[8 b + 0] and [8 b + 3].
+template <class P, bool F_PENDING, int LG, int COLL = COLL_BGK>
 __global__ __launch_bounds__(P::TPB) void k_adjoint_binary(const double* __restrict__ fn,
                                                            const double* __restrict__ gn,
                                                            const double* __restrict__ phi,
@@ -1115,22 +1128,37 @@ __global__ __launch_bounds__(P::TPB) void k_adjoint_binary(const double* __restr
                                                            double* __restrict__ afield,
                                                            double* __restrict__ partial, Geo geo,
                                                            CollParams<double> cp) {
-    __shared__ double sh[3][P::TPB];
+    static_assert(COLL == COLL_BGK || COLL == COLL_TRT, "binary adjoint: BGK or TRT");
+    constexpr bool TRT = COLL == COLL_TRT;
+    constexpr int K = TRT ? 4 : 3;
+    __shared__ double sh[K][P::TPB];
     __shared__ double lf[Q][P::TPB];         // this lane's lambda_f waits here (own slots only: no barrier)
     const int t = threadIdx.x;
     const Column col = column_of_thread<P>(geo);
-    double acc[3] = {0.0, 0.0, 0.0};
+    double acc[K] = {};
     for (int v = 0; v < P::TZ; ++v) {
         const Site st = site_at(col, v, geo);
         if (!st.active) continue;
         const uint32_t off = offset_at<0, 0, 0>(st, geo);
-        // f: moments and sum lambda_f f; lambda_f kept
-        double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0, lff = 0.0;
+        if constexpr (TRT) {
+            static_for<0, Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                lf[i][t] = *at(lf_next + i * geo.dstride, offset_at<cx(i), cy(i), cz(i)>(st, geo));
+            });
+        }
+        // f: moments and sum lambda_f f (TRT: also sum lambda_f,opp f); lambda_f kept
+        double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0, lff = 0.0, lof = 0.0;
         static_for<0, Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
             const double fi = *at(fn + i * geo.dstride, src_offset<i, F_PENDING>(st, geo));
-            const double li = *at(lf_next + i * geo.dstride, offset_at<cx(i), cy(i), cz(i)>(st, geo));
-            lf[i][t] = li;
+            double li;
+            if constexpr (TRT) {
+                li = lf[i][t];
+                lof = lof + lf[opp(i)][t] * fi;
+            } else {
+                li = *at(lf_next + i * geo.dstride, offset_at<cx(i), cy(i), cz(i)>(st, geo));
+                lf[i][t] = li;
+            }
             rho = rho + fi;
             if constexpr (cx(i) > 0) jx = jx + fi;
             if constexpr (cx(i) < 0) jx = jx - fi;
@@ -1160,37 +1188,58 @@ __global__ __launch_bounds__(P::TPB) void k_adjoint_binary(const double* __restr
             gs.template add<i>(l, cu, E, 0.0);
             dwg = dwg + l * (weight<double>(i) * (p * E + fe.template mobility_term<i>(cp)) - gi);
         });
-        // lambda_f pass
+        // lambda_f pass (TRT: the sums take mu, and omega_f is folded in)
         BinSums<true> fs;
-        double lfeq = 0.0;
+        double lfeq = 0.0, lofeq = 0.0;
         static_for<0, Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
             const double cu = cdot<i>(ux, uy, uz);
             const double E = 1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq;
             const double li = lf[i][t];
-            fs.template add<i>(li, cu, E, cdot<i>(Gx, Gy, Gz));
-            lfeq = lfeq + li * weight<double>(i) * (rho * E + fe.template stress_term<i>(cp));
+            if constexpr (TRT) {
+                // mu_i = omega_+ (l_i + l_opp)/2 + omega_- (l_i - l_opp)/2
+                const double lo = lf[opp(i)][t];
+                const double feq = weight<double>(i) * (rho * E + fe.template stress_term<i>(cp));
+                fs.template add<i>(trt_mu(li, lo, cp), cu, E, cdot<i>(Gx, Gy, Gz));
+                lfeq = lfeq + li * feq;
+                lofeq = lofeq + lo * feq;
+            } else {
+                fs.template add<i>(li, cu, E, cdot<i>(Gx, Gy, Gz));
+                lfeq = lfeq + li * weight<double>(i) * (rho * E + fe.template stress_term<i>(cp));
+            }
         });
-        const BinAdj r = binary_adjoint_finish(fs, gs, ux, uy, uz, p, Gx, Gy, Gz, lap, cp, cp.omega_f, cp.omega_g);
+        const double wf = TRT ? 1.0 : cp.omega_f;
+        const BinAdj r = binary_adjoint_finish(fs, gs, ux, uy, uz, p, Gx, Gy, Gz, lap, cp, wf, cp.omega_g);
         const double wg = cp.omega_g * p / rho;
-        const double V[3] = {cp.omega_f * r.Tf[0] + wg * r.Tg[0], cp.omega_f * r.Tf[1] + wg * r.Tg[1],
-                             cp.omega_f * r.Tf[2] + wg * r.Tg[2]};
-        const double base = cp.omega_f * r.Sf - (V[0] * ux + V[1] * uy + V[2] * uz);
+        const double V[3] = {wf * r.Tf[0] + wg * r.Tg[0], wf * r.Tf[1] + wg * r.Tg[1], wf * r.Tf[2] + wg * r.Tg[2]};
+        const double base = wf * r.Sf - (V[0] * ux + V[1] * uy + V[2] * uz);
         static_for<0, Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            *at(lf_n + i * geo.dstride, off) = (1.0 - cp.omega_f) * lf[i][t] + base + cdot<i>(V[0], V[1], V[2]);
+            if constexpr (TRT) {
+                const double li = lf[i][t];
+                *at(lf_n + i * geo.dstride, off) = li - trt_mu(li, lf[opp(i)][t], cp) + base + cdot<i>(V[0], V[1], V[2]);
+            } else {
+                *at(lf_n + i * geo.dstride, off) = (1.0 - cp.omega_f) * lf[i][t] + base + cdot<i>(V[0], V[1], V[2]);
+            }
         });
         afield[off] = r.a_phi;
         afield[(size_t)geo.nsite + off] = r.a_G[0];
         afield[2 * (size_t)geo.nsite + off] = r.a_G[1];
         afield[3 * (size_t)geo.nsite + off] = r.a_G[2];
         afield[4 * (size_t)geo.nsite + off] = r.a_lap;
-        acc[0] = acc[0] + (lfeq - lff);
+        if constexpr (TRT) {
+            // sum (P_+- lambda*)(f^eq - f) = [sum lambda* (f^eq - f) +- sum lambda*_opp (f^eq - f)] / 2
+            const double all = lfeq - lff, cross = lofeq - lof;
+            acc[0] = acc[0] + 0.5 * (all + cross);
+            acc[K - 1] = acc[K - 1] + 0.5 * (all - cross);
+        } else {
+            acc[0] = acc[0] + (lfeq - lff);
+        }
         acc[1] = acc[1] + dwg;
         acc[2] = acc[2] + r.dkappa;
     }
-    block_tree_sum<P::TPB, 3>(acc, sh);
-    if ((int)threadIdx.x < 3) partial[8 * (size_t)blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
+    block_tree_sum<P::TPB, K>(acc, sh);
+    if ((int)threadIdx.x < K) partial[8 * (size_t)blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
 }
 
 // Local part of the reverse of the equilibrium initialisation

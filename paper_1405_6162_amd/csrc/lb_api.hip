@@ -517,8 +517,12 @@ int run_step_record_binary(lb_ctx* c, int32_t n, S* post, typename Compute<S>::T
             }
             {
                 Timed t(c, LB_K_COLLIDE);
-                k_collide<Pol, MODEL_BINARY, S, true><<<c->grid(), c->block(), 0, c->stream>>>(
-                    src, src + Q * N, dst, dst + Q * N, ph, cg, cp);
+                if (c->p.collision == LB_TRT)
+                    k_collide<Pol, MODEL_BINARY, S, true, COLL_TRT><<<c->grid(), c->block(), 0, c->stream>>>(
+                        src, src + Q * N, dst, dst + Q * N, ph, cg, cp);
+                else
+                    k_collide<Pol, MODEL_BINARY, S, true><<<c->grid(), c->block(), 0, c->stream>>>(
+                        src, src + Q * N, dst, dst + Q * N, ph, cg, cp);
             }
             rc = launch_status();
             if (rc) return rc;
@@ -527,12 +531,17 @@ int run_step_record_binary(lb_ctx* c, int32_t n, S* post, typename Compute<S>::T
         {
             Timed t(c, LB_K_COLLIDE);
             const dim3 grid(g.nblocks), block(MP::TPB);
-            if (phi)
-                k_binary_march<MP, BZ, S, March<S>::glds, 3, true><<<grid, block, 0, c->stream>>>(
-                    src, src + Q * N, dst, dst + Q * N, g, cp, phi + (size_t)k * N);
-            else
-                k_binary_march<MP, BZ, S, March<S>::glds><<<grid, block, 0, c->stream>>>(
-                    src, src + Q * N, dst, dst + Q * N, g, cp);
+            auto go = [&](auto coll) {
+                constexpr int COLL = decltype(coll)::value;
+                if (phi)
+                    k_binary_march<MP, BZ, S, March<S>::glds, 3, true, COLL><<<grid, block, 0, c->stream>>>(
+                        src, src + Q * N, dst, dst + Q * N, g, cp, phi + (size_t)k * N);
+                else
+                    k_binary_march<MP, BZ, S, March<S>::glds, 3, false, COLL><<<grid, block, 0, c->stream>>>(
+                        src, src + Q * N, dst, dst + Q * N, g, cp);
+            };
+            if (c->p.collision == LB_TRT) go(std::integral_constant<int, COLL_TRT>{});
+            else go(std::integral_constant<int, COLL_BGK>{});
         }
         rc = launch_status();
         if (rc) return rc;
@@ -635,12 +644,34 @@ template <int LG>
 void launch_adjoint_binary_local(lb_ctx* c, bool pending, const double* f, const double* g, const double* phi,
                                  const double* lf_next, const double* lg_next, const double* b_next, double* lf_n,
                                  double* p_out, double* afield, const Geo& geo, const CollParams<double>& cp) {
-    if (pending)
-        k_adjoint_binary<Pol, true, LG><<<c->grid(), c->block(), 0, c->stream>>>(
-            f, g, phi, lf_next, lg_next, b_next, lf_n, p_out, afield, c->partial(), geo, cp);
+    auto go = [&](auto coll) {
+        constexpr int COLL = decltype(coll)::value;
+        if (pending)
+            k_adjoint_binary<Pol, true, LG, COLL><<<c->grid(), c->block(), 0, c->stream>>>(
+                f, g, phi, lf_next, lg_next, b_next, lf_n, p_out, afield, c->partial(), geo, cp);
+        else
+            k_adjoint_binary<Pol, false, LG, COLL><<<c->grid(), c->block(), 0, c->stream>>>(
+                f, g, phi, lf_next, lg_next, b_next, lf_n, p_out, afield, c->partial(), geo, cp);
+    };
+    if (c->p.collision == LB_TRT) go(std::integral_constant<int, COLL_TRT>{});
+    else go(std::integral_constant<int, COLL_BGK>{});
+}
+
+// Gradient sums of a binary adjoint step: dL/domega_f, dL/domega_g,
+// dL/dkappa, and for TRT dL/domega_minus (omega_f being the even rate).
+int binary_adjoint_grad_count(const lb_ctx* c) { return c->p.collision == LB_TRT ? 4 : 3; }
+
+// The stencil kernel of a binary adjoint step, with block 0 adding the
+// local kernel's partials (one per gradient sum) into grads.
+template <bool B_ONLY>
+void launch_adjoint_binary_stencil(lb_ctx* c, const double* afield, const double* lg_next, double* out,
+                                   const Geo& geo, double omega_g, double* grads) {
+    if (binary_adjoint_grad_count(c) == 4)
+        k_adjoint_binary_stencil<Pol, B_ONLY, 4><<<c->grid(), c->block(), 0, c->stream>>>(
+            afield, lg_next, out, geo, omega_g, c->partial(), c->L.nblocks, grads);
     else
-        k_adjoint_binary<Pol, false, LG><<<c->grid(), c->block(), 0, c->stream>>>(
-            f, g, phi, lf_next, lg_next, b_next, lf_n, p_out, afield, c->partial(), geo, cp);
+        k_adjoint_binary_stencil<Pol, B_ONLY, 3><<<c->grid(), c->block(), 0, c->stream>>>(
+            afield, lg_next, out, geo, omega_g, c->partial(), c->L.nblocks, grads);
 }
 
 // Rate sums an adjoint step of the single fluid accumulates: 1 (BGK), 2
@@ -836,7 +867,7 @@ int lb_step_record(lb_ctx* c, int32_t nsteps, void* post, void* phi) {
     if (phi && c->p.model != LB_BINARY) return LB_EINVAL;
     if (nsteps == 0) return LB_OK;
     if (!post) return LB_EINVAL;
-    if (c->p.model == LB_BINARY && c->p.collision != LB_BGK) return LB_ENOTSUP;
+    if (c->p.model == LB_BINARY && c->p.collision == LB_MRT) return LB_ENOTSUP;
     return by_storage(c, [&](auto tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
         return run_step_record<S>(c, nsteps, (S*)post, (typename Compute<S>::T*)phi);
@@ -860,7 +891,7 @@ int lb_adjoint_step_binary(lb_ctx* c, const double* f, const double* g, const do
                            const double* lf_next, const double* lg_next, double* lf_n, double* lg_n,
                            double* grads) {
     if (!c || !f || !g || !lf_next || !lg_next || !lf_n || !lg_n || !grads) return LB_EINVAL;
-    if (c->p.model != LB_BINARY || c->p.storage != LB_F64 || c->p.collision != LB_BGK) return LB_ENOTSUP;
+    if (c->p.model != LB_BINARY || c->p.storage != LB_F64 || c->p.collision == LB_MRT) return LB_ENOTSUP;
     const double* outs[2] = {lf_n, lg_n};
     const double* ins[5] = {f, g, lf_next, lg_next, phi_n};
     for (const double* o : outs)
@@ -881,17 +912,12 @@ int lb_adjoint_step_binary(lb_ctx* c, const double* f, const double* g, const do
     }
     {
         Timed t(c, LB_K_ADJOINT);
-        if (pending)
-            k_adjoint_binary<Pol, true, LG_GATHER><<<c->grid(), c->block(), 0, c->stream>>>(
-                f, g, phi, lf_next, lg_next, nullptr, lf_n, nullptr, afield, c->partial(), geo, cp);
-        else
-            k_adjoint_binary<Pol, false, LG_GATHER><<<c->grid(), c->block(), 0, c->stream>>>(
-                f, g, phi, lf_next, lg_next, nullptr, lf_n, nullptr, afield, c->partial(), geo, cp);
+        launch_adjoint_binary_local<LG_GATHER>(c, pending != 0, f, g, phi, lf_next, lg_next, nullptr, lf_n, nullptr,
+                                               afield, geo, cp);
     }
     {
         Timed t(c, LB_K_ADJOINT);
-        k_adjoint_binary_stencil<Pol, false, 3><<<c->grid(), c->block(), 0, c->stream>>>(
-            afield, lg_next, lg_n, geo, cp.omega_g, c->partial(), c->L.nblocks, grads);
+        launch_adjoint_binary_stencil<false>(c, afield, lg_next, lg_n, geo, cp.omega_g, grads);
     }
     return launch_status();
 }
@@ -899,7 +925,7 @@ int lb_adjoint_step_binary(lb_ctx* c, const double* f, const double* g, const do
 int lb_adjoint_init_binary(lb_ctx* c, const double* rho, const double* u, const double* phi, const double* lf0,
                            const double* lg0, double* dphi, double* drho, double* du, double* dkappa) {
     if (!c || !rho || !u || !phi || !lf0 || !lg0 || !dphi || !drho || !du || !dkappa) return LB_EINVAL;
-    if (c->p.model != LB_BINARY || c->p.storage != LB_F64 || c->p.collision != LB_BGK) return LB_ENOTSUP;
+    if (c->p.model != LB_BINARY || c->p.storage != LB_F64) return LB_ENOTSUP;
     c->launched = true;
     const Geo geo = c->canonical_geo();
     const auto cp = coll_params<double>(c);
@@ -967,18 +993,19 @@ int lb_adjoint_segment_binary(lb_ctx* c, const double* f0, const double* g0, con
                               int32_t length, double* lf, double* lg, double* work, double* grads) {
     if (!c || !f0 || !g0 || !lf || !lg || !work || !grads || length < 1) return LB_EINVAL;
     if (length > 1 && !post) return LB_EINVAL;
-    if (c->p.model != LB_BINARY || c->p.storage != LB_F64 || c->p.collision != LB_BGK) return LB_ENOTSUP;
+    if (c->p.model != LB_BINARY || c->p.storage != LB_F64 || c->p.collision == LB_MRT) return LB_ENOTSUP;
     const size_t N = c->L.nsite, n19 = (size_t)Q * N;
+    const size_t ng = (size_t)binary_adjoint_grad_count(c);
     const size_t npost = length > 1 ? (size_t)(length - 1) * 2 * n19 : 0;
     const size_t nphi = phi && length > 1 ? (size_t)(length - 1) * N : 0;
     struct R { const double* p; size_t n; };
     const R outs[3] = {{lf, n19}, {lg, n19}, {work, 2 * n19}};
     const R all[8] = {{lf, n19}, {lg, n19}, {work, 2 * n19}, {f0, n19}, {g0, n19}, {post, npost}, {phi, nphi},
-                      {grads, 3}};
+                      {grads, ng}};
     for (int o = 0; o < 3; ++o)                      // all[o] is outs[o]
         for (int a = 0; a < 8; ++a)
             if (a != o && overlaps(outs[o].p, outs[o].n, all[a].p, all[a].n)) return LB_EINVAL;
-    if (overlaps(grads, 3, f0, n19) || overlaps(grads, 3, g0, n19) || overlaps(grads, 3, post, npost))
+    if (overlaps(grads, ng, f0, n19) || overlaps(grads, ng, g0, n19) || overlaps(grads, ng, post, npost))
         return LB_EINVAL;
     c->launched = true;
     const Geo geo = c->canonical_geo();
@@ -1007,8 +1034,7 @@ int lb_adjoint_segment_binary(lb_ctx* c, const double* f0, const double* g0, con
         else
             launch_adjoint_binary_local<LG_PULLED_KEEP>(c, pending, fn, gn, ph, lf_cur, p_cur, bfield, lf_nxt,
                                                         p_nxt, afield, geo, cp);
-        k_adjoint_binary_stencil<Pol, true, 3><<<c->grid(), c->block(), 0, c->stream>>>(
-            afield, nullptr, bfield, geo, 1.0, c->partial(), c->L.nblocks, grads);
+        launch_adjoint_binary_stencil<true>(c, afield, nullptr, bfield, geo, 1.0, grads);
         std::swap(lf_cur, lf_nxt);
         std::swap(p_cur, p_nxt);
     }

@@ -225,10 +225,11 @@ def test_single_model_rejects_phi(lib):
 
 @no_device
 def test_collision_support_of_the_adjoint_calls(lib):
-    """The binary adjoint and the binary record are BGK only (LB_ENOTSUP before
-    any launch); the single-fluid adjoint takes every collision."""
+    """The binary adjoint and the binary record take BGK and TRT, not MRT
+    (LB_ENOTSUP before any launch); the single-fluid adjoint takes every
+    collision."""
     fake = [ctypes.c_void_p((k + 2) << 20) for k in range(8)]
-    p = lb.make_params(6, 5, 4, model=lb.LB_BINARY, collision=lb.LB_TRT, tau_minus=1.2)
+    p = lb.make_params(6, 5, 4, model=lb.LB_BINARY, collision=lb.LB_MRT, tau_minus=1.2)
     _, need = _ws(p)
     ctx = ctypes.c_void_p()
     assert lib.lb_create(ctypes.byref(p), ctypes.c_void_p(1 << 20), need, None, ctypes.byref(ctx)) == lb.LB_OK

@@ -37,6 +37,8 @@ class _Lattice:
 
     def mrt_taus(self):
         p = self.params
+        if p.collision == lb.LB_TRT:
+            return (p.tau_f, p.tau_minus, p.tau_f, p.tau_f, p.tau_minus)
         return (p.tau_f, p.tau_minus, p.tau_bulk, p.tau_ghost_even, p.tau_ghost_odd)
 
     def set_tau(self, tau):
@@ -50,7 +52,9 @@ class _Lattice:
             self.f = O.init_single(*a)
 
     def _step(self):
-        if self.model == lb.LB_BINARY:
+        if self.model == lb.LB_BINARY and self.params.collision == lb.LB_TRT:
+            self.f, self.g = O.step_binary_mrt(self.f, self.g, self.prm, self.mrt_taus(), 1)
+        elif self.model == lb.LB_BINARY:
             self.f, self.g = O.step_binary(self.f, self.g, self.prm, 1)
         elif self.params.collision == lb.LB_MRT:
             self.f = O.step_single_mrt(self.f, self.mrt_taus(), 1)
@@ -76,7 +80,10 @@ def _record(ctx, n, post, phi=None):
         if ctx.model == lb.LB_BINARY:
             if phi is not None:
                 phi[k] = torch.from_numpy(O.order_parameter(ctx.g))
-            pf, pg = O.collide_binary(ctx.f, ctx.g, ctx.prm)
+            if ctx.params.collision == lb.LB_TRT:
+                pf, pg = O.collide_binary_mrt(ctx.f, ctx.g, ctx.prm, ctx.mrt_taus())
+            else:
+                pf, pg = O.collide_binary(ctx.f, ctx.g, ctx.prm)
             post[k, :19] = torch.from_numpy(pf)
             post[k, 19:] = torch.from_numpy(pg)
             ctx.f, ctx.g = O.propagate(pf), O.propagate(pg)
@@ -97,10 +104,18 @@ def _adjoint_binary(ctx, f, g, lf, lg, lf_n, lg_n, grads, pending=False, phi=Non
     if phi is not None:                    # a recorded phi must be that of this step's state
         ctx.calls["phi_given"] += 1
         np.testing.assert_allclose(phi.numpy(), O.order_parameter(gn), rtol=0, atol=1e-15)
-    a, b, gr = O.adjoint_step_binary(fn, gn, lf.numpy(), lg.numpy(), ctx.prm)
+    if ctx.params.collision == lb.LB_TRT:           # (omega_f, omega_g, kappa, omega_minus)
+        assert grads.shape == (4,)
+        a, b, gr = O.adjoint_step_binary(fn, gn, lf.numpy(), lg.numpy(), ctx.prm, ctx.mrt_taus())
+        even = gr["omega_shear"] + gr["omega_bulk"] + gr["omega_ghost_even"]
+        add = [even, gr["omega_g"], gr["kappa"], gr["omega_flux"] + gr["omega_ghost_odd"]]
+    else:
+        assert grads.shape == (3,)
+        a, b, gr = O.adjoint_step_binary(fn, gn, lf.numpy(), lg.numpy(), ctx.prm)
+        add = [gr["omega_f"], gr["omega_g"], gr["kappa"]]
     lf_n.copy_(torch.from_numpy(a))
     lg_n.copy_(torch.from_numpy(b))
-    grads += torch.tensor([gr["omega_f"], gr["omega_g"], gr["kappa"]], dtype=torch.float64)
+    grads += torch.tensor(add, dtype=torch.float64)
 
 
 def _adjoint_init_binary(ctx, rho, u, phi, lf, lg, dphi, drho, du, dkappa):
@@ -195,6 +210,34 @@ def test_binary_rollout_checkpoint_logic(fake_lib, T, K):
             assert abs(t.grad.item()) <= 1e-15 and abs(g_o[name]) <= 1e-15
             continue
         assert abs(t.grad.item() - g_o[name]) <= 1e-12 * abs(g_o[name]), name
+
+
+@pytest.mark.parametrize("T,K", [(1, 1), (5, 2), (4, 4)])
+def test_binary_trt_rollout_checkpoint_logic(fake_lib, T, K):
+    """A binary TRT lattice: tau_f is the pair (tau_f, tau_minus), the sweep
+    sums four gradients, and the pair's gradient is the oracle's even and odd
+    group sums."""
+    nx, ny, nz = 4, 3, 5
+    rho, u, phi = inputs.spinodal_quench(nx, ny, nz, seed=3, phi_max=0.3)
+    _r, u = inputs.single_fluid_random(nx, ny, nz, seed=4, u_max=0.02)
+    tp, tm = 0.9, 1.25
+    prm = O.Params(tau_f=tp, kappa=0.05, mobility=0.4)
+    loss_o, dphi_o, _dr, _du, g_o = O.rollout_gradient_binary(rho, u, phi, O.Params(**vars(prm)), T, 0.5,
+                                                              taus=(tp, tm, tp, tp, tm))
+    lat = _Lattice(lb.LB_BINARY, O.Params())
+    lat.params.collision = lb.LB_TRT
+    r0, u0, p0 = (torch.from_numpy(a.copy()).requires_grad_(True) for a in (rho, u, phi))
+    tau = torch.tensor([tp, tm], dtype=torch.float64, requires_grad=True)
+    with pytest.raises(ValueError):
+        adjoint.rollout_binary(r0, u0, p0, lat, T, K, tau_f=torch.tensor(tp, dtype=torch.float64))
+    fT, gT = adjoint.rollout_binary(r0, u0, p0, lat, T, K, prm.kappa, prm.mobility, tau)
+    loss = adjoint.binary_loss(fT, gT, 0.5)
+    assert abs(loss.item() - loss_o) <= 1e-14 * abs(loss_o)
+    loss.backward()
+    np.testing.assert_allclose(p0.grad.numpy(), dphi_o, rtol=0, atol=1e-13 * np.abs(dphi_o).max())
+    want = [g_o["tau_shear"] + g_o["tau_bulk"] + g_o["tau_ghost_even"], g_o["tau_flux"] + g_o["tau_ghost_odd"]]
+    for k in range(2):
+        assert abs(tau.grad[k].item() - want[k]) <= 1e-12 * abs(want[k]), k
 
 
 @pytest.mark.parametrize("T,K", [(0, 2), (1, 1), (6, 1), (6, 6), (6, 9), (7, 3)])
