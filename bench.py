@@ -59,6 +59,10 @@ WORKLOADS = {
     "adjoint_binary128_trt_f64": ("adjoint_binary", "f64", 128, "D3Q19 binary fluid 128^3 spinodal quench, FP64, "
                                   "f by TRT (tau+ = 1, tau- = 1.25), 200-step rollout + adjoint (gradients "
                                   "w.r.t. phi0, rho0, u0, kappa, M, tau+, tau-) with checkpoints every 20 steps"),
+    "adjoint_binary128_mrt_f64": ("adjoint_binary", "f64", 128, "D3Q19 binary fluid 128^3 spinodal quench, FP64, "
+                                  "f by MRT (tau_shear = 1, tau_flux = 1.25, tau_bulk = 1.4, tau_ghost_even = 0.9, "
+                                  "tau_ghost_odd = 1.2), 200-step rollout + adjoint (gradients w.r.t. phi0, rho0, "
+                                  "u0, kappa, M and the five times) with checkpoints every 20 steps"),
     "precision256_f32": ("precision", "f32", 256, "D3Q19 binary fluid 256^3 spinodal quench, 500 steps: FP32 "
                                                   "deviation storage against FP64"),
     "precision384_f16": ("precision", "f16", 384, "D3Q19 binary fluid 384^3 spinodal quench, 1000 steps: FP16 "
@@ -245,13 +249,19 @@ def bench_adjoint_binary(args, n, desc, T=200, K=20):
     from paper_1405_6162_amd.adjoint import binary_loss, rollout_binary
     log("bench: %s" % desc)
     rho, u, phi = (torch.as_tensor(a, device="cuda") for a in inputs.spinodal_quench(n, n, n, seed=0))
-    trt = "_trt_" in args.workload
-    lat = lb.Lattice(n, n, n, model=lb.LB_BINARY, **(dict(collision=lb.LB_TRT, tau_minus=1.25) if trt else {}))
+    trt, mrt = "_trt_" in args.workload, "_mrt_" in args.workload
+    times = [1.0, 1.25, 1.4, 0.9, 1.2] if mrt else ([1.0, 1.25] if trt else 1.0)
+    kw = {}
+    if trt:
+        kw = dict(collision=lb.LB_TRT, tau_minus=1.25)
+    elif mrt:
+        kw = dict(collision=lb.LB_MRT, tau_minus=1.25, tau_bulk=1.4, tau_ghost_even=0.9, tau_ghost_odd=1.2)
+    lat = lb.Lattice(n, n, n, model=lb.LB_BINARY, **kw)
     par = lambda v: torch.tensor(v, dtype=torch.float64, device="cuda", requires_grad=True)
 
     def once():
         p0 = phi.clone().requires_grad_(True)
-        kap, mob, tau = par(0.04), par(0.45), par([1.0, 1.25] if trt else 1.0)
+        kap, mob, tau = par(0.04), par(0.45), par(times)
         loss = binary_loss(*rollout_binary(rho, u, p0, lat, T, K, kap, mob, tau), 1.0)
         loss.backward()
         return p0.grad, torch.cat([kap.grad.reshape(1), mob.grad.reshape(1), tau.grad.reshape(-1)])
@@ -290,7 +300,7 @@ def bench_adjoint_binary(args, n, desc, T=200, K=20):
                    "seed": 0},
         "roofline": {"bound": "hbm",
                      "kernel": "adjoint step: k_adjoint_binary%s + k_adjoint_binary_stencil" % (
-                         " (TRT)" if trt else ""),
+                         " (TRT)" if trt else (" (MRT)" if mrt else "")),
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(args.workload),
                      "traffic_unit": "bytes per adjoint step (local + stencil kernel)",
@@ -298,7 +308,8 @@ def bench_adjoint_binary(args, n, desc, T=200, K=20):
                      "avg_step_ms": round(per_step_ms, 5), "launches": adj_n},
         "gradients": dict({"kappa": float(gpar[0]), "mobility": float(gpar[1]), "tau_f": float(gpar[2]),
                            "max_abs_dphi0": float(gphi.abs().max())},
-                          **({"tau_minus": float(gpar[3])} if trt else {})),
+                          **{k: float(v) for k, v in zip(("tau_minus", "tau_bulk", "tau_ghost_even",
+                                                          "tau_ghost_odd"), gpar[3:])}),
     }
     if not args.no_copy:
         out["copy_probe"] = copy_probe(torch)

@@ -191,7 +191,7 @@ int lb_set_state(lb_ctx* ctx, const void* f, const void* g);
 int lb_set_tau(lb_ctx* ctx, double tau_f);
 
 /* nsteps x (collide; propagate) like lb_step (LB_SINGLE: any collision;
- * LB_BINARY: LB_BGK or LB_TRT, else LB_ENOTSUP), recording each step's
+ * LB_BINARY: any collision), recording each step's
  * post-collision field (before its propagation) in caller memory, canonical
  * layout, storage dtype.  LB_SINGLE: step k (0-based) writes
  * post[k*19*N + i*N + s] (nsteps*19*N elements).  LB_BINARY: step k writes f*
@@ -228,8 +228,7 @@ int lb_adjoint_step(lb_ctx* ctx, const double* f, int f_pending, const double* l
 int lb_set_params(lb_ctx* ctx, const lb_params* p);
 
 /* Adjoint (reverse) of one binary-fluid step, LB_BINARY + LB_F64 only, for
- * f relaxing by LB_BGK or LB_TRT (LB_MRT: LB_ENOTSUP; g always relaxes by
- * BGK).  The step is the one of lb_step: f and g relax to their equilibria, whose
+ * f relaxing by any collision (g always relaxes by BGK).  The step is the one of lb_step: f and g relax to their equilibria, whose
  * pressure tensor and chemical potential read phi = sum g at the site and
  * its six neighbours (central-difference gradient and 7-point Laplacian,
  * Section II-A's finite-difference order-parameter model), then both
@@ -241,11 +240,12 @@ int lb_set_params(lb_ctx* ctx, const lb_params* p);
  * lf_next, lg_next = dL/df^{n+1}, dL/dg^{n+1}; lf_n, lg_n receive dL/df^n and
  * dL/dg^n (must not alias the inputs or each other).  grads (device
  * doubles) is INCREMENTED by dL/d(1/tau_f), dL/d(1/tau_g) and dL/dkappa of
- * this step (tau_g = mobility/gamma + 1/2), and for LB_TRT by
- * dL/d(1/tau_minus) in a fourth double (tau_f being then the time of the
- * even part of f - f^eq): 3 doubles for LB_BGK, 4 for LB_TRT.  With TRT the
- * symmetric relaxation Omega takes the place of 1/tau_f as in
- * lb_adjoint_step.  Uses the context's parameters;
+ * this step (tau_g = mobility/gamma + 1/2); then, for LB_TRT, by
+ * dL/d(1/tau_minus) (tau_f being the time of the even part of f - f^eq),
+ * and for LB_MRT by dL/d(1/tau) of tau_minus, tau_bulk, tau_ghost_even and
+ * tau_ghost_odd (tau_f being the shear time): 3 doubles for LB_BGK, 4 for
+ * LB_TRT, 7 for LB_MRT.  With TRT or MRT the symmetric relaxation Omega
+ * takes the place of 1/tau_f as in lb_adjoint_step.  Uses the context's parameters;
  * uses the context's spare state buffer and phi buffer as scratch, so calls
  * on one context must not overlap; the lattice state itself is unchanged. */
 int lb_adjoint_step_binary(lb_ctx* ctx, const double* f, const double* g, const double* phi_n,
@@ -283,7 +283,7 @@ int lb_adjoint_init_binary(lb_ctx* ctx, const double* rho, const double* u, cons
  * length == 1); phi = the length-1 phi fields recorded with them (N each), or
  * NULL to have every step's phi computed.  lf, lg (19*N each) hold
  * dL/df, dL/dg at step s0+length on entry and at s0 on return; work[38*N]
- * is scratch.  grads (3 device doubles, 4 for LB_TRT) is INCREMENTED as by
+ * is scratch.  grads (3, 4 or 7 device doubles) is INCREMENTED as by
  * lb_adjoint_step_binary.  Between steps lambda_g is kept as a pair
  * (P, b), P_j(x) = lambda_g^{n+1}_j(x + c_j) and b = dL/dphi^n, from which
  * lambda_g^n = (1 - 1/tau_g) P + b; this moves 136 fewer bytes a site per

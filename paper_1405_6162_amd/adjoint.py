@@ -106,6 +106,11 @@ class LBRollout(torch.autograd.Function):
         return lam, grad_tau, None, None, None
 
 
+# relaxation times of f that a binary rollout differentiates, per collision
+_BINARY_TIMES = {lb.LB_BGK: ("tau_f",), lb.LB_TRT: ("tau_f", "tau_minus"),
+                 lb.LB_MRT: ("tau_f", "tau_minus", "tau_bulk", "tau_ghost_even", "tau_ghost_odd")}
+
+
 class LBBinaryRollout(torch.autograd.Function):
     """(f_T, g_T) = LBBinaryRollout.apply(rho0, u0, phi0, kappa, mobility,
     tau_f, lattice, nsteps, every).
@@ -113,9 +118,10 @@ class LBBinaryRollout(torch.autograd.Function):
     Binary-fluid rollout from the equilibrium built on (rho0, u0, phi0)
     (float64 device tensors of shapes (nz, ny, nx), (3, nz, ny, nx),
     (nz, ny, nx)), with kappa and mobility as 0-d float64 tensors and tau_f
-    0-d (BGK) or, on a TRT lattice, the pair (tau_f, tau_minus) of the even
-    and odd relaxation times.  lattice: an lb.Lattice with model LB_BINARY,
-    storage LB_F64 and collision LB_BGK or LB_TRT, whose state and
+    0-d (BGK) or the tensor of the lattice's relaxation times of f: on a TRT
+    lattice (tau_f, tau_minus), the even and odd times; on an MRT lattice
+    (tau_f, tau_minus, tau_bulk, tau_ghost_even, tau_ghost_odd).  lattice:
+    an lb.Lattice with model LB_BINARY and storage LB_F64, whose state and
     parameters this call overwrites.  Gradients flow to rho0, u0,
     phi0, kappa, mobility and tau_f.  The backward recomputes each segment of
     at most `every` steps from its checkpoint, recording every step's
@@ -128,15 +134,13 @@ class LBBinaryRollout(torch.autograd.Function):
     def forward(ctx, rho0, u0, phi0, kappa, mobility, tau_f, lattice, nsteps, every):
         if lattice.model != lb.LB_BINARY or lattice.storage != lb.LB_F64:
             raise ValueError("the binary adjoint is implemented for the binary fluid in FP64")
-        if lattice.params.collision not in (lb.LB_BGK, lb.LB_TRT):
-            raise ValueError("the binary adjoint is implemented for BGK and TRT collisions of f")
         if nsteps < 0 or every < 1:
             raise ValueError("nsteps must be >= 0 and every >= 1")
-        trt = lattice.params.collision == lb.LB_TRT
-        if tuple(tau_f.shape) != ((2,) if trt else ()):
-            raise ValueError("tau_f must be %s on this lattice" % ("(tau_f, tau_minus)" if trt else "0-d"))
-        taus = [float(t) for t in tau_f.reshape(-1)]
-        times = dict(tau_f=taus[0], tau_minus=taus[1]) if trt else dict(tau_f=taus[0])
+        names = _BINARY_TIMES[lattice.params.collision]
+        if tuple(tau_f.shape) != ((len(names),) if len(names) > 1 else ()):
+            raise ValueError("tau_f must be %s on this lattice" % ("(%s)" % ", ".join(names) if len(names) > 1
+                                                                   else "0-d"))
+        times = dict(zip(names, (float(t) for t in tau_f.reshape(-1))))
         lattice.set_params(kappa=float(kappa), mobility=float(mobility), **times)
         fields = tuple(t.detach().to(torch.float64).contiguous() for t in (rho0, u0, phi0))
         lattice.init_equilibrium(*fields)
@@ -166,8 +170,8 @@ class LBBinaryRollout(torch.autograd.Function):
         lf = grad_f.detach().to(torch.float64).contiguous().clone() if grad_f is not None else zero()
         lg = grad_g.detach().to(torch.float64).contiguous().clone() if grad_g is not None else zero()
         work = torch.empty((2 * lb.Q,) + tuple(shape[1:]), dtype=torch.float64, device=dev)
-        # dL/domega_f, dL/domega_g, dL/dkappa (and dL/domega_minus for TRT)
-        grads = torch.zeros(4 if "tau_minus" in times else 3, dtype=torch.float64, device=dev)
+        # dL/domega_f, dL/domega_g, dL/dkappa, then the other times of f (lb.h)
+        grads = torch.zeros(3 + len(times) - 1, dtype=torch.float64, device=dev)
         for seg in range(len(ctx.ckpts) - 1, -1, -1):
             start = seg * K
             length = min(K, T - start)
@@ -193,25 +197,25 @@ class LBBinaryRollout(torch.autograd.Function):
         tau_g = mobility / lat.params.gamma + 0.5
         g_kappa = (grads[2] + dkappa0[0]).reshape(())
         g_mob = (-grads[1] / (tau_g * tau_g) / lat.params.gamma).reshape(())
-        tf = times["tau_f"]
-        g_tau = (-grads[0] / (tf * tf)).reshape(())
-        if "tau_minus" in times:
-            tm = times["tau_minus"]
-            g_tau = torch.stack([g_tau, -grads[3] / (tm * tm)])
+        # tau_f's sum is grads[0], the further times' are grads[3:]
+        rate_sums = torch.cat([grads[:1], grads[3:]])
+        tv = torch.tensor(list(times.values()), dtype=torch.float64, device=dev)
+        g_tau = (-rate_sums / (tv * tv)).reshape(() if len(times) == 1 else (len(times),))
         ctx.ckpts = ctx.fields = None
         return drho, du, dphi, g_kappa, g_mob, g_tau, None, None, None
 
 
 def rollout_binary(rho0, u0, phi0, lattice, nsteps, every=20, kappa=None, mobility=None, tau_f=None):
     """Convenience wrapper: LBBinaryRollout.apply with tensor parameters
-    (defaults: the lattice's current values; on a TRT lattice tau_f is the
-    pair (tau_f, tau_minus))."""
+    (defaults: the lattice's current values; on a TRT or MRT lattice tau_f
+    is the tensor of its relaxation times of f)."""
     dev = phi0.device
     as_t = lambda v, d: v if torch.is_tensor(v) else torch.tensor(float(d if v is None else v),
                                                                    dtype=torch.float64, device=dev)
-    if lattice.params.collision == lb.LB_TRT and not torch.is_tensor(tau_f):
-        pair = (lattice.params.tau_f, lattice.params.tau_minus) if tau_f is None else tau_f
-        tau_f = torch.tensor([float(t) for t in pair], dtype=torch.float64, device=dev)
+    names = _BINARY_TIMES[lattice.params.collision]
+    if len(names) > 1 and not torch.is_tensor(tau_f):
+        vals = [getattr(lattice.params, k) for k in names] if tau_f is None else tau_f
+        tau_f = torch.tensor([float(t) for t in vals], dtype=torch.float64, device=dev)
     return LBBinaryRollout.apply(rho0, u0, phi0, as_t(kappa, lattice.params.kappa),
                                  as_t(mobility, lattice.params.mobility), as_t(tau_f, lattice.params.tau_f),
                                  lattice, int(nsteps), int(every))

@@ -1117,6 +1117,11 @@ __device__ __forceinline__ double trt_mu(double l, double lo, const CollParams<d
 // (1 - omega_f) lambda*_f.  lambda*_f is then loaded before f, so that both
 // directions of a pair are at hand, and the even and odd rate sums
 // sum (P_+- lambda*_f)(f^eq - f) go to partial[8 b + 0] and [8 b + 3].
+// COLL_MRT: mu adds, for each of the seven moments m with a rate of its own
+// (the energy, three even and three odd ghosts), (omega_m - omega_+-) times
+// the projection of lambda*_f on m; the moments of lambda*_f, f and f^eq on
+// them give the bulk and ghost rate sums (partial[8 b + 4..6]), and the
+// shear and flux sums are the even and odd sums less those.
 template <class P, bool F_PENDING, int LG, int COLL = COLL_BGK>
 __global__ __launch_bounds__(P::TPB) void k_adjoint_binary(const double* __restrict__ fn,
                                                            const double* __restrict__ gn,
@@ -1128,9 +1133,9 @@ __global__ __launch_bounds__(P::TPB) void k_adjoint_binary(const double* __restr
                                                            double* __restrict__ afield,
                                                            double* __restrict__ partial, Geo geo,
                                                            CollParams<double> cp) {
-    static_assert(COLL == COLL_BGK || COLL == COLL_TRT, "binary adjoint: BGK or TRT");
-    constexpr bool TRT = COLL == COLL_TRT;
-    constexpr int K = TRT ? 4 : 3;
+    constexpr bool MRT = COLL == COLL_MRT;
+    constexpr bool TRT = COLL == COLL_TRT || MRT;          // MRT includes the even/odd (TRT) part
+    constexpr int K = MRT ? 7 : (TRT ? 4 : 3);
     __shared__ double sh[K][P::TPB];
     __shared__ double lf[Q][P::TPB];         // this lane's lambda_f waits here (own slots only: no barrier)
     const int t = threadIdx.x;
@@ -1148,10 +1153,17 @@ __global__ __launch_bounds__(P::TPB) void k_adjoint_binary(const double* __restr
         }
         // f: moments and sum lambda_f f (TRT: also sum lambda_f,opp f); lambda_f kept
         double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0, lff = 0.0, lof = 0.0;
+        double mf[MRT ? 7 : 1] = {};                    // MRT: f on the seven extra moments
         static_for<0, Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
             const double fi = *at(fn + i * geo.dstride, src_offset<i, F_PENDING>(st, geo));
             double li;
+            if constexpr (MRT) {
+                static_for<0, 7>([&](auto Kx) {
+                    constexpr int c = mrt_poly(mrt_extra(decltype(Kx)::value), i);
+                    if constexpr (c != 0) mf[decltype(Kx)::value] = mf[decltype(Kx)::value] + double(c) * fi;
+                });
+            }
             if constexpr (TRT) {
                 li = lf[i][t];
                 lof = lof + lf[opp(i)][t] * fi;
@@ -1188,6 +1200,34 @@ __global__ __launch_bounds__(P::TPB) void k_adjoint_binary(const double* __restr
             gs.template add<i>(l, cu, E, 0.0);
             dwg = dwg + l * (weight<double>(i) * (p * E + fe.template mobility_term<i>(cp)) - gi);
         });
+        // MRT: lambda*_f on the seven extra moments, and the coefficients
+        // a_k = (omega_k - omega_+-) (lambda*.m_k) / |m_k|^2 of its correction
+        double ml[MRT ? 7 : 1] = {}, a[MRT ? 7 : 1] = {}, mfeq[MRT ? 7 : 1] = {};
+        if constexpr (MRT) {
+            static_for<0, 7>([&](auto Kx) {
+                constexpr int k = decltype(Kx)::value;
+                constexpr int m = mrt_extra(k);
+                static_for<0, Q>([&](auto I) {
+                    constexpr int c = mrt_poly(m, decltype(I)::value);
+                    if constexpr (c != 0) ml[k] = ml[k] + double(c) * lf[decltype(I)::value][t];
+                });
+                const double dom = k == 0 ? cp.omega_b - cp.omega_f
+                                          : (k < 4 ? cp.omega_ge - cp.omega_f : cp.omega_go - cp.omega_m);
+                a[k] = dom * ml[k] / double(mrt_norm(m));
+            });
+        }
+        // mu_i = omega_+ (l_i + l_opp)/2 + omega_- (l_i - l_opp)/2 (+ the MRT correction)
+        auto mu_at = [&](auto I) {
+            constexpr int i = decltype(I)::value;
+            double mu = trt_mu(lf[i][t], lf[opp(i)][t], cp);
+            if constexpr (MRT) {
+                static_for<0, 7>([&](auto Kx) {
+                    constexpr int c = mrt_poly(mrt_extra(decltype(Kx)::value), i);
+                    if constexpr (c != 0) mu = mu + double(c) * a[decltype(Kx)::value];
+                });
+            }
+            return mu;
+        };
         // lambda_f pass (TRT: the sums take mu, and omega_f is folded in)
         BinSums<true> fs;
         double lfeq = 0.0, lofeq = 0.0;
@@ -1197,12 +1237,17 @@ __global__ __launch_bounds__(P::TPB) void k_adjoint_binary(const double* __restr
             const double E = 1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq;
             const double li = lf[i][t];
             if constexpr (TRT) {
-                // mu_i = omega_+ (l_i + l_opp)/2 + omega_- (l_i - l_opp)/2
                 const double lo = lf[opp(i)][t];
                 const double feq = weight<double>(i) * (rho * E + fe.template stress_term<i>(cp));
-                fs.template add<i>(trt_mu(li, lo, cp), cu, E, cdot<i>(Gx, Gy, Gz));
+                fs.template add<i>(mu_at(I), cu, E, cdot<i>(Gx, Gy, Gz));
                 lfeq = lfeq + li * feq;
                 lofeq = lofeq + lo * feq;
+                if constexpr (MRT) {
+                    static_for<0, 7>([&](auto Kx) {
+                        constexpr int c = mrt_poly(mrt_extra(decltype(Kx)::value), i);
+                        if constexpr (c != 0) mfeq[decltype(Kx)::value] = mfeq[decltype(Kx)::value] + double(c) * feq;
+                    });
+                }
             } else {
                 fs.template add<i>(li, cu, E, cdot<i>(Gx, Gy, Gz));
                 lfeq = lfeq + li * weight<double>(i) * (rho * E + fe.template stress_term<i>(cp));
@@ -1216,8 +1261,7 @@ __global__ __launch_bounds__(P::TPB) void k_adjoint_binary(const double* __restr
         static_for<0, Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
             if constexpr (TRT) {
-                const double li = lf[i][t];
-                *at(lf_n + i * geo.dstride, off) = li - trt_mu(li, lf[opp(i)][t], cp) + base + cdot<i>(V[0], V[1], V[2]);
+                *at(lf_n + i * geo.dstride, off) = lf[i][t] - mu_at(I) + base + cdot<i>(V[0], V[1], V[2]);
             } else {
                 *at(lf_n + i * geo.dstride, off) = (1.0 - cp.omega_f) * lf[i][t] + base + cdot<i>(V[0], V[1], V[2]);
             }
@@ -1230,8 +1274,22 @@ __global__ __launch_bounds__(P::TPB) void k_adjoint_binary(const double* __restr
         if constexpr (TRT) {
             // sum (P_+- lambda*)(f^eq - f) = [sum lambda* (f^eq - f) +- sum lambda*_opp (f^eq - f)] / 2
             const double all = lfeq - lff, cross = lofeq - lof;
-            acc[0] = acc[0] + 0.5 * (all + cross);
-            acc[K - 1] = acc[K - 1] + 0.5 * (all - cross);
+            double even = 0.5 * (all + cross), odd = 0.5 * (all - cross);
+            if constexpr (MRT) {
+                // rate sum of moment k: (lambda*.m_k)((f^eq - f).m_k) / |m_k|^2;
+                // k = 0 energy (bulk), 1-3 even ghosts, 4-6 odd ghosts
+                static_for<0, 7>([&](auto Kx) {
+                    constexpr int k = decltype(Kx)::value;
+                    const double d = ml[k] * (mfeq[k] - mf[k]) / double(mrt_norm(mrt_extra(k)));
+                    if constexpr (k == 0) acc[4] = acc[4] + d;
+                    else if constexpr (k < 4) acc[5] = acc[5] + d;
+                    else acc[6] = acc[6] + d;
+                    if constexpr (k < 4) even = even - d;      // shear = even - bulk - even ghosts
+                    else odd = odd - d;                         // flux = odd - odd ghosts
+                });
+            }
+            acc[0] = acc[0] + even;
+            acc[3] = acc[3] + odd;
         } else {
             acc[0] = acc[0] + (lfeq - lff);
         }

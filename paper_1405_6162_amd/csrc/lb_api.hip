@@ -520,6 +520,9 @@ int run_step_record_binary(lb_ctx* c, int32_t n, S* post, typename Compute<S>::T
                 if (c->p.collision == LB_TRT)
                     k_collide<Pol, MODEL_BINARY, S, true, COLL_TRT><<<c->grid(), c->block(), 0, c->stream>>>(
                         src, src + Q * N, dst, dst + Q * N, ph, cg, cp);
+                else if (c->p.collision == LB_MRT)
+                    k_collide<Pol, MODEL_BINARY, S, true, COLL_MRT><<<c->grid(), c->block(), 0, c->stream>>>(
+                        src, src + Q * N, dst, dst + Q * N, ph, cg, cp);
                 else
                     k_collide<Pol, MODEL_BINARY, S, true><<<c->grid(), c->block(), 0, c->stream>>>(
                         src, src + Q * N, dst, dst + Q * N, ph, cg, cp);
@@ -541,6 +544,7 @@ int run_step_record_binary(lb_ctx* c, int32_t n, S* post, typename Compute<S>::T
                         src, src + Q * N, dst, dst + Q * N, g, cp);
             };
             if (c->p.collision == LB_TRT) go(std::integral_constant<int, COLL_TRT>{});
+            else if (c->p.collision == LB_MRT) go(std::integral_constant<int, COLL_MRT>{});
             else go(std::integral_constant<int, COLL_BGK>{});
         }
         rc = launch_status();
@@ -654,19 +658,28 @@ void launch_adjoint_binary_local(lb_ctx* c, bool pending, const double* f, const
                 f, g, phi, lf_next, lg_next, b_next, lf_n, p_out, afield, c->partial(), geo, cp);
     };
     if (c->p.collision == LB_TRT) go(std::integral_constant<int, COLL_TRT>{});
+    else if (c->p.collision == LB_MRT) go(std::integral_constant<int, COLL_MRT>{});
     else go(std::integral_constant<int, COLL_BGK>{});
 }
 
 // Gradient sums of a binary adjoint step: dL/domega_f, dL/domega_g,
-// dL/dkappa, and for TRT dL/domega_minus (omega_f being the even rate).
-int binary_adjoint_grad_count(const lb_ctx* c) { return c->p.collision == LB_TRT ? 4 : 3; }
+// dL/dkappa; for TRT and MRT then dL/domega_minus (omega_f being the even,
+// or shear, rate and omega_minus the odd, or flux, one); for MRT then the
+// bulk, even-ghost and odd-ghost rates.
+int binary_adjoint_grad_count(const lb_ctx* c) {
+    return c->p.collision == LB_MRT ? 7 : (c->p.collision == LB_TRT ? 4 : 3);
+}
 
 // The stencil kernel of a binary adjoint step, with block 0 adding the
 // local kernel's partials (one per gradient sum) into grads.
 template <bool B_ONLY>
 void launch_adjoint_binary_stencil(lb_ctx* c, const double* afield, const double* lg_next, double* out,
                                    const Geo& geo, double omega_g, double* grads) {
-    if (binary_adjoint_grad_count(c) == 4)
+    const int ng = binary_adjoint_grad_count(c);
+    if (ng == 7)
+        k_adjoint_binary_stencil<Pol, B_ONLY, 7><<<c->grid(), c->block(), 0, c->stream>>>(
+            afield, lg_next, out, geo, omega_g, c->partial(), c->L.nblocks, grads);
+    else if (ng == 4)
         k_adjoint_binary_stencil<Pol, B_ONLY, 4><<<c->grid(), c->block(), 0, c->stream>>>(
             afield, lg_next, out, geo, omega_g, c->partial(), c->L.nblocks, grads);
     else
@@ -867,7 +880,6 @@ int lb_step_record(lb_ctx* c, int32_t nsteps, void* post, void* phi) {
     if (phi && c->p.model != LB_BINARY) return LB_EINVAL;
     if (nsteps == 0) return LB_OK;
     if (!post) return LB_EINVAL;
-    if (c->p.model == LB_BINARY && c->p.collision == LB_MRT) return LB_ENOTSUP;
     return by_storage(c, [&](auto tag) {
         using S = std::remove_pointer_t<decltype(tag)>;
         return run_step_record<S>(c, nsteps, (S*)post, (typename Compute<S>::T*)phi);
@@ -891,7 +903,7 @@ int lb_adjoint_step_binary(lb_ctx* c, const double* f, const double* g, const do
                            const double* lf_next, const double* lg_next, double* lf_n, double* lg_n,
                            double* grads) {
     if (!c || !f || !g || !lf_next || !lg_next || !lf_n || !lg_n || !grads) return LB_EINVAL;
-    if (c->p.model != LB_BINARY || c->p.storage != LB_F64 || c->p.collision == LB_MRT) return LB_ENOTSUP;
+    if (c->p.model != LB_BINARY || c->p.storage != LB_F64) return LB_ENOTSUP;
     const double* outs[2] = {lf_n, lg_n};
     const double* ins[5] = {f, g, lf_next, lg_next, phi_n};
     for (const double* o : outs)
@@ -993,7 +1005,7 @@ int lb_adjoint_segment_binary(lb_ctx* c, const double* f0, const double* g0, con
                               int32_t length, double* lf, double* lg, double* work, double* grads) {
     if (!c || !f0 || !g0 || !lf || !lg || !work || !grads || length < 1) return LB_EINVAL;
     if (length > 1 && !post) return LB_EINVAL;
-    if (c->p.model != LB_BINARY || c->p.storage != LB_F64 || c->p.collision == LB_MRT) return LB_ENOTSUP;
+    if (c->p.model != LB_BINARY || c->p.storage != LB_F64) return LB_ENOTSUP;
     const size_t N = c->L.nsite, n19 = (size_t)Q * N;
     const size_t ng = (size_t)binary_adjoint_grad_count(c);
     const size_t npost = length > 1 ? (size_t)(length - 1) * 2 * n19 : 0;

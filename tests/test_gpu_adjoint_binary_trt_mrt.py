@@ -1,9 +1,10 @@
-"""Adjoint of the binary-fluid FP64 step with f relaxing by two times (TRT):
-the local adjoint kernel with mu = Omega lambda*_f, the recorded TRT
-recompute, the segment sweep and the checkpointed rollout against the
-oracle's moment-space reverse sweep (TRT as the MRT case with the even
-groups at tau_plus and the odd at tau_minus; pinned by complex-step
-derivatives), and central differences of the GPU forward in the two times."""
+"""Adjoint of the binary-fluid FP64 step with f relaxing by two times (TRT)
+or in moment space (MRT): the local adjoint kernel with mu = Omega
+lambda*_f, the recorded recompute, the segment sweep and the checkpointed
+rollout against the oracle's moment-space reverse sweep (TRT as the MRT
+case with the even groups at tau_plus and the odd at tau_minus; pinned by
+complex-step derivatives), and central differences of the GPU forward in the
+two TRT times."""
 
 import numpy as np
 import pytest
@@ -16,6 +17,8 @@ pytestmark = pytest.mark.gpu
 
 TP, TM = 0.9, 1.3
 EVEN, ODD = ("shear", "bulk", "ghost_even"), ("flux", "ghost_odd")
+MRT_TAUS = (0.9, 1.3, 1.4, 0.85, 1.15)          # shear (tau_f), flux (tau_minus), bulk, ghost even, ghost odd
+COLLS = ["trt", "mrt"]
 
 
 def relerr(a, ref):
@@ -26,8 +29,8 @@ def dev(a):
     return torch.as_tensor(np.ascontiguousarray(a), device="cuda")
 
 
-def _taus(tp=TP, tm=TM):
-    return (tp, tm, tp, tp, tm)
+def _taus(tp=TP, tm=TM, coll="trt"):
+    return (tp, tm, tp, tp, tm) if coll == "trt" else MRT_TAUS
 
 
 def _fields(nx, ny, nz, seed, phi_max=0.3):
@@ -37,42 +40,53 @@ def _fields(nx, ny, nz, seed, phi_max=0.3):
     return rho, u, phi
 
 
-def _state(nx, ny, nz, seed, prm):
+def _state(nx, ny, nz, seed, prm, coll="trt"):
     f, g = O.init_binary(*_fields(nx, ny, nz, seed), prm)
-    return O.step_binary_mrt(f, g, prm, _taus(), 1)
+    return O.step_binary_mrt(f, g, prm, _taus(coll=coll), 1)
 
 
-def _lattice(lbgpu, nx, ny, nz, prm, **kw):
-    return lbgpu.Lattice(nx, ny, nz, model=lbgpu.LB_BINARY, collision=lbgpu.LB_TRT, tau_f=TP, tau_minus=TM,
-                         A=prm.A, B=prm.B, kappa=prm.kappa, mobility=prm.mobility, gamma=prm.gamma, **kw)
+def _lattice(lbgpu, nx, ny, nz, prm, coll="trt", **kw):
+    t = _taus(coll=coll)
+    times = dict(tau_f=t[0], tau_minus=t[1])
+    if coll == "mrt":
+        times.update(tau_bulk=t[2], tau_ghost_even=t[3], tau_ghost_odd=t[4])
+    return lbgpu.Lattice(nx, ny, nz, model=lbgpu.LB_BINARY, collision=lbgpu.LB_TRT if coll == "trt" else lbgpu.LB_MRT,
+                         A=prm.A, B=prm.B, kappa=prm.kappa, mobility=prm.mobility, gamma=prm.gamma, **times, **kw)
 
 
-def _lib_grads(want):
-    """The oracle's group sums as the library's (omega_f, omega_g, kappa, omega_minus)."""
+def _lib_grads(want, coll="trt"):
+    """The oracle's group sums as the library's: (omega_f, omega_g, kappa,
+    omega_minus) for TRT, (omega_shear, omega_g, kappa, omega_flux,
+    omega_bulk, omega_ghost_even, omega_ghost_odd) for MRT."""
+    if coll == "mrt":
+        return [want["omega_shear"], want["omega_g"], want["kappa"]] + [want["omega_" + k] for k in O.MRT_RATES[1:]]
     return [sum(want["omega_" + k] for k in EVEN), want["omega_g"], want["kappa"],
             sum(want["omega_" + k] for k in ODD)]
 
 
+@pytest.mark.parametrize("coll", COLLS)
 @pytest.mark.parametrize("given_phi", [False, True])
 @pytest.mark.parametrize("pending", [False, True])
 @pytest.mark.parametrize("nx,ny,nz", [(5, 6, 7), (67, 9, 5)])
-def test_binary_trt_adjoint_step_kernels(lbgpu, nx, ny, nz, pending, given_phi):
-    print("case binary trt adjoint step", nx, ny, nz, pending, given_phi, flush=True)
-    prm = O.Params(tau_f=TP, kappa=0.05, mobility=0.3)
-    f, g = _state(nx, ny, nz, 1, prm)
+def test_binary_adjoint_step_kernels_trt_mrt(lbgpu, nx, ny, nz, pending, given_phi, coll):
+    print("case binary adjoint step", coll, nx, ny, nz, pending, given_phi, flush=True)
+    taus = _taus(coll=coll)
+    prm = O.Params(tau_f=taus[0], kappa=0.05, mobility=0.3)
+    f, g = _state(nx, ny, nz, 1, prm, coll)
     rng = np.random.default_rng(2)
     lf1, lg1 = rng.standard_normal(f.shape), rng.standard_normal(g.shape)
     if pending:                    # the kernel pulls f^n, g^n from the previous post-collision fields
-        pf, pg = O.collide_binary_mrt(f, g, prm, _taus())
+        pf, pg = O.collide_binary_mrt(f, g, prm, taus)
         fn, gn = O.propagate(pf), O.propagate(pg)
         given_f, given_g = pf, pg
     else:
         fn, gn = f, g
         given_f, given_g = f, g
-    want_f, want_g, want = O.adjoint_step_binary(fn, gn, lf1, lg1, prm, _taus())
-    lat = _lattice(lbgpu, nx, ny, nz, prm)
+    want_f, want_g, want = O.adjoint_step_binary(fn, gn, lf1, lg1, prm, taus)
+    lat = _lattice(lbgpu, nx, ny, nz, prm, coll)
     lf, lg = torch.empty_like(dev(lf1)), torch.empty_like(dev(lg1))
-    grads = torch.full((4,), 0.5, dtype=torch.float64, device="cuda")     # the call increments it
+    ng = 7 if coll == "mrt" else 4
+    grads = torch.full((ng,), 0.5, dtype=torch.float64, device="cuda")     # the call increments it
     lbgpu.lb_set_stream(lat.ctx, lbgpu._stream())
     phi = dev(O.order_parameter(gn)) if given_phi else None
     lbgpu.lb_adjoint_step_binary(lat.ctx, dev(given_f), dev(given_g), dev(lf1), dev(lg1), lf, lg, grads,
@@ -80,16 +94,18 @@ def test_binary_trt_adjoint_step_kernels(lbgpu, nx, ny, nz, pending, given_phi):
     assert relerr(lf.cpu().numpy(), want_f) < 1e-12
     assert relerr(lg.cpu().numpy(), want_g) < 1e-12
     got = grads.cpu().numpy() - 0.5
-    for k, w in enumerate(_lib_grads(want)):
+    for k, w in enumerate(_lib_grads(want, coll)):
         assert abs(got[k] - w) <= 1e-12 * max(abs(w), 1.0), k
 
 
+@pytest.mark.parametrize("coll", COLLS)
 @pytest.mark.parametrize("step_kernel", [1, 2])          # LB_STEP_MARCH, LB_STEP_TWO_PASS
-def test_binary_trt_step_record(lbgpu, step_kernel):
+def test_binary_step_record_trt_mrt(lbgpu, step_kernel, coll):
     nx, ny, nz, n = 7, 5, 6, 3
-    prm = O.Params(tau_f=TP)
-    f, g = _state(nx, ny, nz, 5, prm)
-    lat = _lattice(lbgpu, nx, ny, nz, prm, binary_step=step_kernel)
+    taus = _taus(coll=coll)
+    prm = O.Params(tau_f=taus[0])
+    f, g = _state(nx, ny, nz, 5, prm, coll)
+    lat = _lattice(lbgpu, nx, ny, nz, prm, coll, binary_step=step_kernel)
     lat.set_state(f, g)
     post = torch.empty((n, 38, nz, ny, nx), dtype=torch.float64, device="cuda")
     phi = torch.empty((n, nz, ny, nx), dtype=torch.float64, device="cuda")
@@ -98,22 +114,25 @@ def test_binary_trt_step_record(lbgpu, step_kernel):
     p, ph = post.cpu().numpy(), phi.cpu().numpy()
     for k in range(n):
         assert relerr(ph[k], O.order_parameter(g)) < 1e-13
-        pf, pg = O.collide_binary_mrt(f, g, prm, _taus())
+        pf, pg = O.collide_binary_mrt(f, g, prm, taus)
         assert relerr(p[k, :19], pf) < 1e-12 and relerr(p[k, 19:], pg) < 1e-12
         f, g = O.propagate(pf), O.propagate(pg)
     sf, sg = (a.cpu().numpy() for a in lat.get_state())
     assert relerr(sf, f) < 1e-12 and relerr(sg, g) < 1e-12
 
 
-def test_binary_trt_segment(lbgpu):
-    """lb_adjoint_segment_binary on a recorded TRT segment against the
+@pytest.mark.parametrize("coll", COLLS)
+def test_binary_segment_trt_mrt(lbgpu, coll):
+    """lb_adjoint_segment_binary on a recorded TRT / MRT segment against the
     oracle's reverse sweep over the same states."""
     nx, ny, nz, length = 67, 9, 5, 4
-    prm = O.Params(tau_f=TP, kappa=0.05, mobility=0.3)
-    f0, g0 = _state(nx, ny, nz, 23, prm)
+    taus = _taus(coll=coll)
+    ng = 7 if coll == "mrt" else 4
+    prm = O.Params(tau_f=taus[0], kappa=0.05, mobility=0.3)
+    f0, g0 = _state(nx, ny, nz, 23, prm, coll)
     rng = np.random.default_rng(24)
     lf_T, lg_T = rng.standard_normal(f0.shape), rng.standard_normal(g0.shape)
-    lat = _lattice(lbgpu, nx, ny, nz, prm)
+    lat = _lattice(lbgpu, nx, ny, nz, prm, coll)
     lat.set_state(f0, g0)
     lbgpu.lb_set_stream(lat.ctx, lbgpu._stream())
     post = torch.empty((length - 1, 38, nz, ny, nx), dtype=torch.float64, device="cuda")
@@ -121,40 +140,43 @@ def test_binary_trt_segment(lbgpu):
     lbgpu.lb_step_record(lat.ctx, length - 1, post, phi)
     lf, lg = dev(lf_T), dev(lg_T)
     work = torch.empty((38, nz, ny, nx), dtype=torch.float64, device="cuda")
-    grads = torch.full((4,), 0.25, dtype=torch.float64, device="cuda")
+    grads = torch.full((ng,), 0.25, dtype=torch.float64, device="cuda")
     lbgpu.lb_adjoint_segment_binary(lat.ctx, dev(f0), dev(g0), post, phi, length, lf, lg, work, grads)
     states = [(f0, g0)]
     for _ in range(length - 1):
-        states.append(O.step_binary_mrt(*states[-1], prm, _taus(), 1))
+        states.append(O.step_binary_mrt(*states[-1], prm, taus, 1))
     a, b = lf_T, lg_T
-    tot = np.zeros(4)
+    tot = np.zeros(ng)
     for n in range(length - 1, -1, -1):
-        a, b, gr = O.adjoint_step_binary(states[n][0], states[n][1], a, b, prm, _taus())
-        tot = tot + np.array(_lib_grads(gr))
+        a, b, gr = O.adjoint_step_binary(states[n][0], states[n][1], a, b, prm, taus)
+        tot = tot + np.array(_lib_grads(gr, coll))
     assert relerr(lf.cpu().numpy(), a) < 1e-12
     assert relerr(lg.cpu().numpy(), b) < 1e-12
     got = grads.cpu().numpy() - 0.25
-    for k in range(4):
+    for k in range(ng):
         assert abs(got[k] - tot[k]) <= 1e-12 * max(abs(tot[k]), 1.0), k
 
 
+@pytest.mark.parametrize("coll", COLLS)
 @pytest.mark.parametrize("T,K", [(5, 2), (4, 4)])
-def test_binary_trt_rollout_matches_oracle(lbgpu, T, K):
-    """The checkpointed rollout with tau_f = (tau_plus, tau_minus) against
-    the oracle's full reverse sweep: dL/dphi0, dL/drho0, dL/du0, kappa, M
-    and the two times."""
+def test_binary_rollout_trt_mrt_matches_oracle(lbgpu, T, K, coll):
+    """The checkpointed rollout with tau_f the lattice's times of f
+    ((tau_plus, tau_minus) for TRT, five for MRT) against the oracle's full
+    reverse sweep: dL/dphi0, dL/drho0, dL/du0, kappa, M and the times."""
     from paper_1405_6162_amd.adjoint import binary_loss, rollout_binary
-    print("case binary trt rollout T=%d K=%d" % (T, K), flush=True)
+    print("case binary %s rollout T=%d K=%d" % (coll, T, K), flush=True)
     nx, ny, nz = 12, 10, 8
-    prm = O.Params(tau_f=TP, kappa=0.04, mobility=0.45)
+    taus = _taus(coll=coll)
+    prm = O.Params(tau_f=taus[0], kappa=0.04, mobility=0.45)
     rho, u, phi = _fields(nx, ny, nz, seed=8)
     beta = 0.5
-    loss_o, dphi_o, drho_o, du_o, g_o = O.rollout_gradient_binary(rho, u, phi, prm, T, beta, taus=_taus())
-    lat = _lattice(lbgpu, nx, ny, nz, prm)
+    loss_o, dphi_o, drho_o, du_o, g_o = O.rollout_gradient_binary(rho, u, phi, prm, T, beta, taus=taus)
+    lat = _lattice(lbgpu, nx, ny, nz, prm, coll)
     r0, u0, p0 = (dev(a).requires_grad_(True) for a in (rho, u, phi))
     kap, mob = (torch.tensor(v, dtype=torch.float64, device="cuda", requires_grad=True)
                 for v in (prm.kappa, prm.mobility))
-    tau = torch.tensor([TP, TM], dtype=torch.float64, device="cuda", requires_grad=True)
+    tau = torch.tensor([TP, TM] if coll == "trt" else list(taus), dtype=torch.float64, device="cuda",
+                       requires_grad=True)
     fT, gT = rollout_binary(r0, u0, p0, lat, T, K, kap, mob, tau)
     loss = binary_loss(fT, gT, beta)
     assert abs(loss.item() - loss_o) <= 1e-12 * abs(loss_o)
@@ -164,9 +186,12 @@ def test_binary_trt_rollout_matches_oracle(lbgpu, T, K):
     assert relerr(u0.grad.cpu().numpy(), du_o) < 1e-11
     assert abs(kap.grad.item() - g_o["kappa"]) <= 1e-11 * abs(g_o["kappa"])
     assert abs(mob.grad.item() - g_o["mobility"]) <= 1e-11 * abs(g_o["mobility"])
-    want = [sum(g_o["tau_" + k] for k in EVEN), sum(g_o["tau_" + k] for k in ODD)]
+    if coll == "trt":
+        want = [sum(g_o["tau_" + k] for k in EVEN), sum(g_o["tau_" + k] for k in ODD)]
+    else:
+        want = [g_o["tau_" + k] for k in O.MRT_RATES]
     got = tau.grad.cpu().numpy()
-    for k in range(2):
+    for k in range(len(want)):
         assert abs(got[k] - want[k]) <= 1e-11 * abs(want[k]), k
 
 

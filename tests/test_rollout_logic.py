@@ -52,7 +52,7 @@ class _Lattice:
             self.f = O.init_single(*a)
 
     def _step(self):
-        if self.model == lb.LB_BINARY and self.params.collision == lb.LB_TRT:
+        if self.model == lb.LB_BINARY and self.params.collision != lb.LB_BGK:
             self.f, self.g = O.step_binary_mrt(self.f, self.g, self.prm, self.mrt_taus(), 1)
         elif self.model == lb.LB_BINARY:
             self.f, self.g = O.step_binary(self.f, self.g, self.prm, 1)
@@ -80,7 +80,7 @@ def _record(ctx, n, post, phi=None):
         if ctx.model == lb.LB_BINARY:
             if phi is not None:
                 phi[k] = torch.from_numpy(O.order_parameter(ctx.g))
-            if ctx.params.collision == lb.LB_TRT:
+            if ctx.params.collision != lb.LB_BGK:
                 pf, pg = O.collide_binary_mrt(ctx.f, ctx.g, ctx.prm, ctx.mrt_taus())
             else:
                 pf, pg = O.collide_binary(ctx.f, ctx.g, ctx.prm)
@@ -109,6 +109,10 @@ def _adjoint_binary(ctx, f, g, lf, lg, lf_n, lg_n, grads, pending=False, phi=Non
         a, b, gr = O.adjoint_step_binary(fn, gn, lf.numpy(), lg.numpy(), ctx.prm, ctx.mrt_taus())
         even = gr["omega_shear"] + gr["omega_bulk"] + gr["omega_ghost_even"]
         add = [even, gr["omega_g"], gr["kappa"], gr["omega_flux"] + gr["omega_ghost_odd"]]
+    elif ctx.params.collision == lb.LB_MRT:         # (omega_f, omega_g, kappa, then the other four times)
+        assert grads.shape == (7,)
+        a, b, gr = O.adjoint_step_binary(fn, gn, lf.numpy(), lg.numpy(), ctx.prm, ctx.mrt_taus())
+        add = [gr["omega_shear"], gr["omega_g"], gr["kappa"]] + [gr["omega_" + k] for k in O.MRT_RATES[1:]]
     else:
         assert grads.shape == (3,)
         a, b, gr = O.adjoint_step_binary(fn, gn, lf.numpy(), lg.numpy(), ctx.prm)
@@ -238,6 +242,31 @@ def test_binary_trt_rollout_checkpoint_logic(fake_lib, T, K):
     want = [g_o["tau_shear"] + g_o["tau_bulk"] + g_o["tau_ghost_even"], g_o["tau_flux"] + g_o["tau_ghost_odd"]]
     for k in range(2):
         assert abs(tau.grad[k].item() - want[k]) <= 1e-12 * abs(want[k]), k
+
+
+@pytest.mark.parametrize("T,K", [(1, 1), (5, 2)])
+def test_binary_mrt_rollout_checkpoint_logic(fake_lib, T, K):
+    """A binary MRT lattice: tau_f is the five times and each gets the
+    oracle's group gradient."""
+    nx, ny, nz = 4, 3, 5
+    rho, u, phi = inputs.spinodal_quench(nx, ny, nz, seed=3, phi_max=0.3)
+    _r, u = inputs.single_fluid_random(nx, ny, nz, seed=4, u_max=0.02)
+    taus = (0.9, 1.2, 1.35, 0.85, 1.1)
+    prm = O.Params(tau_f=taus[0], kappa=0.05, mobility=0.4)
+    loss_o, dphi_o, _dr, _du, g_o = O.rollout_gradient_binary(rho, u, phi, O.Params(**vars(prm)), T, 0.5,
+                                                              taus=taus)
+    lat = _Lattice(lb.LB_BINARY, O.Params())
+    lat.params.collision = lb.LB_MRT
+    r0, u0, p0 = (torch.from_numpy(a.copy()).requires_grad_(True) for a in (rho, u, phi))
+    tau = torch.tensor(taus, dtype=torch.float64, requires_grad=True)
+    fT, gT = adjoint.rollout_binary(r0, u0, p0, lat, T, K, prm.kappa, prm.mobility, tau)
+    loss = adjoint.binary_loss(fT, gT, 0.5)
+    assert abs(loss.item() - loss_o) <= 1e-14 * abs(loss_o)
+    loss.backward()
+    np.testing.assert_allclose(p0.grad.numpy(), dphi_o, rtol=0, atol=1e-13 * np.abs(dphi_o).max())
+    for k, name in enumerate(O.MRT_RATES):
+        want = g_o["tau_" + name]
+        assert abs(tau.grad[k].item() - want) <= 1e-12 * abs(want), name
 
 
 @pytest.mark.parametrize("T,K", [(0, 2), (1, 1), (6, 1), (6, 6), (6, 9), (7, 3)])
