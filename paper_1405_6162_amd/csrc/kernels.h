@@ -1134,8 +1134,8 @@ __global__ __launch_bounds__(P::TPB) void k_adjoint_binary(const double* __restr
                                                            double* __restrict__ partial, Geo geo,
                                                            CollParams<double> cp) {
     constexpr bool MRT = COLL == COLL_MRT;
-    constexpr bool TRT = COLL == COLL_TRT || MRT;          // MRT includes the even/odd (TRT) part
-    constexpr int K = MRT ? 7 : (TRT ? 4 : 3);
+    constexpr bool SPLIT = COLL != COLL_BGK;     // even and odd parts relax apart (TRT; MRT on top)
+    constexpr int K = MRT ? 7 : (SPLIT ? 4 : 3);
     __shared__ double sh[K][P::TPB];
     __shared__ double lf[Q][P::TPB];         // this lane's lambda_f waits here (own slots only: no barrier)
     const int t = threadIdx.x;
@@ -1145,13 +1145,13 @@ __global__ __launch_bounds__(P::TPB) void k_adjoint_binary(const double* __restr
         const Site st = site_at(col, v, geo);
         if (!st.active) continue;
         const uint32_t off = offset_at<0, 0, 0>(st, geo);
-        if constexpr (TRT) {
+        if constexpr (SPLIT) {
             static_for<0, Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
                 lf[i][t] = *at(lf_next + i * geo.dstride, offset_at<cx(i), cy(i), cz(i)>(st, geo));
             });
         }
-        // f: moments and sum lambda_f f (TRT: also sum lambda_f,opp f); lambda_f kept
+        // f: moments and sum lambda_f f (TRT, MRT: also sum lambda_f,opp f); lambda_f kept
         double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0, lff = 0.0, lof = 0.0;
         double mf[MRT ? 7 : 1] = {};                    // MRT: f on the seven extra moments
         static_for<0, Q>([&](auto I) {
@@ -1164,7 +1164,7 @@ __global__ __launch_bounds__(P::TPB) void k_adjoint_binary(const double* __restr
                     if constexpr (c != 0) mf[decltype(Kx)::value] = mf[decltype(Kx)::value] + double(c) * fi;
                 });
             }
-            if constexpr (TRT) {
+            if constexpr (SPLIT) {
                 li = lf[i][t];
                 lof = lof + lf[opp(i)][t] * fi;
             } else {
@@ -1228,7 +1228,7 @@ __global__ __launch_bounds__(P::TPB) void k_adjoint_binary(const double* __restr
             }
             return mu;
         };
-        // lambda_f pass (TRT: the sums take mu, and omega_f is folded in)
+        // lambda_f pass (TRT, MRT: the sums take mu, and omega_f is folded in)
         BinSums<true> fs;
         double lfeq = 0.0, lofeq = 0.0;
         static_for<0, Q>([&](auto I) {
@@ -1236,7 +1236,7 @@ __global__ __launch_bounds__(P::TPB) void k_adjoint_binary(const double* __restr
             const double cu = cdot<i>(ux, uy, uz);
             const double E = 1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq;
             const double li = lf[i][t];
-            if constexpr (TRT) {
+            if constexpr (SPLIT) {
                 const double lo = lf[opp(i)][t];
                 const double feq = weight<double>(i) * (rho * E + fe.template stress_term<i>(cp));
                 fs.template add<i>(mu_at(I), cu, E, cdot<i>(Gx, Gy, Gz));
@@ -1253,14 +1253,14 @@ __global__ __launch_bounds__(P::TPB) void k_adjoint_binary(const double* __restr
                 lfeq = lfeq + li * weight<double>(i) * (rho * E + fe.template stress_term<i>(cp));
             }
         });
-        const double wf = TRT ? 1.0 : cp.omega_f;
+        const double wf = SPLIT ? 1.0 : cp.omega_f;
         const BinAdj r = binary_adjoint_finish(fs, gs, ux, uy, uz, p, Gx, Gy, Gz, lap, cp, wf, cp.omega_g);
         const double wg = cp.omega_g * p / rho;
         const double V[3] = {wf * r.Tf[0] + wg * r.Tg[0], wf * r.Tf[1] + wg * r.Tg[1], wf * r.Tf[2] + wg * r.Tg[2]};
         const double base = wf * r.Sf - (V[0] * ux + V[1] * uy + V[2] * uz);
         static_for<0, Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            if constexpr (TRT) {
+            if constexpr (SPLIT) {
                 *at(lf_n + i * geo.dstride, off) = lf[i][t] - mu_at(I) + base + cdot<i>(V[0], V[1], V[2]);
             } else {
                 *at(lf_n + i * geo.dstride, off) = (1.0 - cp.omega_f) * lf[i][t] + base + cdot<i>(V[0], V[1], V[2]);
@@ -1271,7 +1271,7 @@ __global__ __launch_bounds__(P::TPB) void k_adjoint_binary(const double* __restr
         afield[2 * (size_t)geo.nsite + off] = r.a_G[1];
         afield[3 * (size_t)geo.nsite + off] = r.a_G[2];
         afield[4 * (size_t)geo.nsite + off] = r.a_lap;
-        if constexpr (TRT) {
+        if constexpr (SPLIT) {
             // sum (P_+- lambda*)(f^eq - f) = [sum lambda* (f^eq - f) +- sum lambda*_opp (f^eq - f)] / 2
             const double all = lfeq - lff, cross = lofeq - lof;
             double even = 0.5 * (all + cross), odd = 0.5 * (all - cross);
