@@ -21,8 +21,9 @@ import torch
 from . import lb
 
 
-# Relaxation times of the single fluid per collision, in the order of the
-# rate sums lb_adjoint_step accumulates.
+# Relaxation times of f per collision, in the order of the rate sums
+# lb_adjoint_step accumulates (and lb_adjoint_step_binary after its omega_g
+# and kappa sums).
 RATE_NAMES = {lb.LB_BGK: ("tau_f",), lb.LB_TRT: ("tau_f", "tau_minus"),
               lb.LB_MRT: ("tau_f", "tau_minus", "tau_bulk", "tau_ghost_even", "tau_ghost_odd")}
 
@@ -106,11 +107,6 @@ class LBRollout(torch.autograd.Function):
         return lam, grad_tau, None, None, None
 
 
-# relaxation times of f that a binary rollout differentiates, per collision
-_BINARY_TIMES = {lb.LB_BGK: ("tau_f",), lb.LB_TRT: ("tau_f", "tau_minus"),
-                 lb.LB_MRT: ("tau_f", "tau_minus", "tau_bulk", "tau_ghost_even", "tau_ghost_odd")}
-
-
 class LBBinaryRollout(torch.autograd.Function):
     """(f_T, g_T) = LBBinaryRollout.apply(rho0, u0, phi0, kappa, mobility,
     tau_f, lattice, nsteps, every).
@@ -136,7 +132,7 @@ class LBBinaryRollout(torch.autograd.Function):
             raise ValueError("the binary adjoint is implemented for the binary fluid in FP64")
         if nsteps < 0 or every < 1:
             raise ValueError("nsteps must be >= 0 and every >= 1")
-        names = _BINARY_TIMES[lattice.params.collision]
+        names = RATE_NAMES[lattice.params.collision]
         if tuple(tau_f.shape) != ((len(names),) if len(names) > 1 else ()):
             raise ValueError("tau_f must be %s on this lattice" % ("(%s)" % ", ".join(names) if len(names) > 1
                                                                    else "0-d"))
@@ -212,7 +208,7 @@ def rollout_binary(rho0, u0, phi0, lattice, nsteps, every=20, kappa=None, mobili
     dev = phi0.device
     as_t = lambda v, d: v if torch.is_tensor(v) else torch.tensor(float(d if v is None else v),
                                                                    dtype=torch.float64, device=dev)
-    names = _BINARY_TIMES[lattice.params.collision]
+    names = RATE_NAMES[lattice.params.collision]
     if len(names) > 1 and not torch.is_tensor(tau_f):
         vals = [getattr(lattice.params, k) for k in names] if tau_f is None else tau_f
         tau_f = torch.tensor([float(t) for t in vals], dtype=torch.float64, device=dev)
