@@ -227,3 +227,33 @@ def test_binary_trt_rollout_central_differences_24(lbgpu):
     fd_m = (L(phi, tm=TM + eps) - L(phi, tm=TM - eps)) / (2 * eps)
     assert abs(fd_p - gt[0]) <= 1e-6 * abs(gt[0]), (fd_p, gt[0])
     assert abs(fd_m - gt[1]) <= 1e-6 * abs(gt[1]), (fd_m, gt[1])
+
+
+def test_binary_mrt_rollout_central_differences_24(lbgpu):
+    """24^3, 12 steps, checkpoints every 5, f by MRT: the gradients in the
+    bulk, flux and odd-ghost times against central differences (eps 1e-6) of
+    the GPU forward."""
+    from paper_1405_6162_amd.adjoint import binary_loss, rollout_binary
+    n, T, K, eps = 24, 12, 5, 1e-6
+    prm = O.Params(tau_f=MRT_TAUS[0])
+    rho, u, phi = inputs.spinodal_quench(n, n, n, seed=12, phi_max=0.1)
+    _r, u = inputs.single_fluid_random(n, n, n, seed=13, u_max=0.02)
+    lat = _lattice(lbgpu, n, n, n, prm, "mrt")
+    tau = torch.tensor(MRT_TAUS, dtype=torch.float64, device="cuda", requires_grad=True)
+    loss = binary_loss(*rollout_binary(dev(rho), dev(u), dev(phi), lat, T, K, tau_f=tau), 1.0)
+    loss.backward()
+    gt = tau.grad.cpu().numpy()
+
+    def L(t):
+        with torch.no_grad():
+            tt = torch.tensor(t, dtype=torch.float64, device="cuda")
+            return binary_loss(*rollout_binary(dev(rho), dev(u), dev(phi), lat, T, K, tau_f=tt), 1.0).item()
+    # FP64 rounding of the two losses bounds what a central difference resolves
+    floor = 4.0 * np.finfo(np.float64).eps * abs(loss.item()) / eps
+    for k in (1, 2, 4):                              # flux, bulk, odd ghosts
+        tp, tm = list(MRT_TAUS), list(MRT_TAUS)
+        tp[k] += eps
+        tm[k] -= eps
+        fd = (L(tp) - L(tm)) / (2 * eps)
+        print("tau", k, "fd", fd, "adjoint", gt[k], flush=True)
+        assert abs(fd - gt[k]) <= 1e-6 * abs(gt[k]) + floor, (k, fd, gt[k])
