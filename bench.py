@@ -3,10 +3,16 @@
 
 A step is one full update of every site: one launch of the fused
 pull-stream + collision kernel (for the binary fluid the single-pass kernel
-that also computes phi and its stencils).  The
-default workload is the binary fluid on a 128^3 periodic lattice in FP64
-(spinodal quench, rho = 1, u = 0, phi ~ U(-0.05, 0.05), seed 0), whose
-100-step run is the benchmark configuration.
+that also computes phi and its stencils).  The default workload is the
+binary fluid on a 256^3 periodic lattice in FP64 (spinodal quench, rho = 1,
+u = 0, phi ~ U(-0.05, 0.05), seed 0): the largest FP64 configuration on one
+GPU, the one the FP64-against-FP32 comparison is quoted on.
+
+The timed region runs the steps as plain launches (no per-launch events);
+`value` and `ms_per_step` come from it.  A second, separate pass of the same
+number of steps brackets every launch with HIP events on the library's
+stream to give the kernel's own average duration, from which `roofline` is
+computed.
 
 Prints one JSON line on stdout.  Progress goes to stderr.
 
@@ -105,52 +111,71 @@ def traffic_from_profile(workload):
     return int(float(info["traffic_bytes_per_launch"]))
 
 
-def cpu_baseline(model, n, seconds_target=12.0):
-    """The FP64 oracle on the host, on the same workload's initial state, for
-    as many whole steps as fit in about `seconds_target` (at least one)."""
+def cpu_baseline(model, n, slab_div=8):
+    """The FP64 oracle timed on the host: the C reference (oracle/lb_oracle.c,
+    plain loops, OpenMP over sites; its results do not depend on the thread
+    count) from the workload's initial state.  All cores: one step of the
+    whole n^3 lattice.  One thread: one step of an n x n x n/slab_div slab of
+    the same workload (periodic, the same per-site work), so the sample stays
+    bounded.  MLUPS = sites / wall time of the step (initialisation not
+    timed)."""
     import numpy as np
-    from oracle import lb_oracle as O
+    from oracle import c_backend as C
     from paper_1405_6162_amd import inputs
-    prm = O.Params()
-    if model == "binary":
-        rho, u, phi = inputs.spinodal_quench(n, n, n, seed=0)
-        f, g = O.init_binary(rho, u, phi, prm)
-    else:
-        rho, u = inputs.single_fluid_random(n, n, n, seed=0)
-        f, g = O.init_single(rho, u), None
-    steps, t_total = 0, 0.0
-    while steps == 0 or (t_total < seconds_target and steps < 50):
-        t0 = time.perf_counter()
+
+    def one_step(nz, threads):
+        used = C.set_threads(threads)
         if model == "binary":
-            f, g = O.step_binary(f, g, prm, 1)
+            rho, u, phi = inputs.spinodal_quench(n, n, nz, seed=0)
+            lat = C.CLattice(n, n, nz, model=1)
+            lat.init_equilibrium(rho, u, phi)
         else:
-            f = O.step_single(f, prm.tau_f, 1)
-        t_total += time.perf_counter() - t0
-        steps += 1
-    assert np.isfinite(f).all()
-    mlups = n ** 3 * steps / t_total / 1e6
-    return {"value": round(mlups, 4), "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": "%d step(s) of the same %d^3 %s-fluid workload from its initial state, %.1f s wall; "
-                      "numpy elementwise kernels, one thread" % (steps, n, model, t_total)}
+            rho, u = inputs.single_fluid_random(n, n, nz, seed=0)
+            lat = C.CLattice(n, n, nz, model=0)
+            lat.init_equilibrium(rho, u)
+        del rho, u
+        t0 = time.perf_counter()
+        lat.step(1)
+        dt = time.perf_counter() - t0
+        ok = bool(np.isfinite(lat.sums()).all())
+        lat.close()
+        assert ok
+        return n * n * nz / dt / 1e6, dt, used
+
+    v_all, t_all, cores = one_step(n, 0)
+    nz1 = max(n // slab_div, 1)
+    v_one, t_one, _ = one_step(nz1, 1)
+    return {"value": round(v_all, 4), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "value_1_thread": round(v_one, 4),
+            "sample": "C reference (plain FP64 loops, OpenMP over sites): 1 step of the %d^3 %s-fluid workload "
+                      "on %d threads, %.1f s wall; 1 step of a %dx%dx%d slab of it on 1 thread, %.1f s wall"
+                      % (n, model, cores, t_all, n, n, nz1, t_one)}
 
 
 def copy_probe(torch, nbytes=2 << 30, reps=10):
-    """Plain device-to-device copy of `nbytes`: the achievable HBM rate, and
+    """The library's streaming copy (lb_stream_copy: 16-byte loads, nontemporal
+    16-byte stores) of `nbytes` device bytes, timed with events on the
+    current stream: the HBM rate of a plain read-once / write-once copy, and
     the reference kernel for scaling the FETCH_SIZE / WRITE_SIZE counters."""
-    n = nbytes // 8
-    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    from paper_1405_6162_amd import lb
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
-    b.copy_(a)
+    lb.lb_stream_copy(b, a)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
-        b.copy_(a)
+        lb.lb_stream_copy(b, a)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
+    ok = bool(torch.equal(a, b))
     del a, b
-    return {"bytes_per_launch": 2 * nbytes, "GB/s": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
+    if not ok:
+        raise RuntimeError("lb_stream_copy produced a wrong copy")
+    return {"kernel": "k_stream_copy (lb_stream_copy)", "bytes_per_launch": 2 * nbytes,
+            "GB/s": round(2 * nbytes / (ms * 1e-3) / 1e9, 1), "frac_of_peak": round(
+                2 * nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
 def pull_copy_ceiling(lb, lat, bytes_per_launch, launches=10):
@@ -494,7 +519,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="binary128_f64", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="binary256_f64", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-copy", action="store_true", help="skip the copy-bandwidth probe")
     ap.add_argument("--vvl", type=int, default=1, choices=(1, 2, 4),
@@ -544,7 +569,7 @@ def main():
     torch.cuda.synchronize()
     log("bench: warmup done")
 
-    lb.lb_profile(lat.ctx, True)
+    # timed region: plain launches only
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -553,10 +578,16 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    lb.lb_profile(lat.ctx, False)
     gpu_ms = e0.elapsed_time(e1)
-    col_ms, col_n = lb.lb_kernel_times(lat.ctx, lb.LB_K_COLLIDE)
     log("bench: timed region %.3f ms (events), %.3f s wall" % (gpu_ms, wall))
+    # kernel timing pass: the same number of steps, every launch between two
+    # HIP events on the library's stream
+    lb.lb_profile(lat.ctx, True)
+    lat.step(args.steps)
+    torch.cuda.synchronize()
+    lb.lb_profile(lat.ctx, False)
+    col_ms, col_n = lb.lb_kernel_times(lat.ctx, lb.LB_K_COLLIDE)
+    log("bench: kernel pass %.3f ms in %d launches" % (col_ms, col_n))
 
     nsite = n ** 3
     sums = lat.conserved_sums().cpu()
@@ -602,6 +633,7 @@ def main():
             "bytes_per_site": alg["collide"],
             "avg_launch_ms": round(col_avg_ms, 5),
             "launches": col_n,
+            "timing": "HIP events around each launch, in a pass of its own after the timed region",
             "frac_of_pull_copy": round(achieved / ceiling["GB/s"], 4) if ceiling["GB/s"] else None,
         },
         "pull_copy_ceiling": ceiling,
@@ -610,10 +642,12 @@ def main():
             "GB/s": round(step_bytes * nsite * args.steps / seconds / 1e9, 1),
             "frac": round(step_bytes * nsite * args.steps / seconds / 1e9 / HBM_PEAK_GBS, 4),
             "timing": "wall clock of the whole timed region",
+            "event_ms_per_step": round(gpu_ms / args.steps, 5),
         },
     }
     if not args.no_copy:
         out["copy_probe"] = copy_probe(torch)
+        out["roofline"]["frac_of_copy_probe"] = round(achieved / out["copy_probe"]["GB/s"], 4)
         log("bench: copy probe %s GB/s" % out["copy_probe"]["GB/s"])
     if not args.no_cpu:
         log("bench: timing the CPU oracle on a bounded sample")

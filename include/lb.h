@@ -132,45 +132,74 @@ typedef struct lb_params {
 typedef struct lb_ctx lb_ctx;   /* opaque; created by lb_create */
 
 /* Bytes of device workspace a context with these parameters needs.
- * Host-only (touches no device).  LB_EINVAL on bad parameters. */
+ * Host-only (touches no device).  LB_EINVAL on bad parameters.
+ * Paper: Section III-B (targetMalloc: target lattice data is allocated with
+ * error checking); here the caller allocates and the library only sizes. */
 int lb_workspace_bytes(const lb_params* p, size_t* bytes);
 
 /* Create a context.  `workspace` is a device allocation of at least
  * lb_workspace_bytes() bytes, 256-byte aligned, owned by the caller and
  * borrowed until lb_destroy; `stream` is a hipStream_t (NULL = the null
- * stream).  Queues no device work.  *out receives the context. */
+ * stream).  Queues no device work.  *out receives the context.
+ * Paper: Section III-A (the target holds the master copy of the lattice
+ * data) and Section III-B (lattice fields on the target, structure of
+ * arrays).  LB_EINVAL on bad parameters or a NULL workspace, LB_ENOMEM if
+ * workspace_bytes is too small; nothing is created then. */
 int lb_create(const lb_params* p, void* workspace, size_t workspace_bytes,
               void* stream, lb_ctx** out);
 
-/* Change the stream subsequent calls are queued on. */
+/* Change the stream subsequent calls are queued on.  Not in the paper
+ * (its CUDA layer synchronises after every launch, Section III-C's
+ * syncTarget; here ordering is the caller's stream). */
 int lb_set_stream(lb_ctx* ctx, void* stream);
 
 /* Set the state to equilibrium: f = f^eq(rho, u[, P(phi)]) and, for the
  * binary model, g = g^eq(phi, u, mu(phi)), the stencils applied to the given
  * phi.  rho[N], u[3*N] component-major, phi[N] (NULL for LB_SINGLE), all
  * FP64 device arrays in site order.  The state becomes the pre-collision
- * state at t = 0. */
+ * state at t = 0.  Paper: Section III-B (copyToTarget: lattice data enters
+ * the target once, as whole-lattice fields) and Section IV (the benchmark's
+ * two-fluid lattice-Boltzmann model; the equilibria are the readings in the
+ * file header).  LB_EINVAL if rho or u is NULL, or phi is NULL for
+ * LB_BINARY / not NULL for LB_SINGLE. */
 int lb_init_equilibrium(lb_ctx* ctx, const double* rho, const double* u, const double* phi);
 
 /* One collision of every site of the current state (binary: computes phi,
- * its stencils, mu and P from the current g first). */
+ * its stencils, mu and P from the current g first).  Paper: Section IV (the
+ * benchmarked operation: a lattice-Boltzmann collision of a two-fluid
+ * mixture, loops over 19 momenta and 3 dimensions) and Section II-A (the
+ * order parameter's gradients by finite differences).  LB_EINVAL on NULL. */
 int lb_collide(lb_ctx* ctx);
 
-/* One periodic propagation f_i(s + c_i) <- f_i(s) of every population. */
+/* One periodic propagation f_i(s + c_i) <- f_i(s) of every population.
+ * Paper: Section II-A (lattice-Boltzmann hydrodynamics on a regular
+ * lattice); the paper benchmarks the collision alone, propagation is the
+ * other half of the standard step.  On a state that is not pending this
+ * only marks it pending (no kernel).  LB_EINVAL on NULL. */
 int lb_propagate(lb_ctx* ctx);
 
 /* nsteps x (collide; propagate).  nsteps == 0 is a no-op, < 0 is LB_EINVAL.
- * Each step is one fused pull-stream + collide kernel (binary: preceded by
- * the phi kernel). */
+ * Each step is one launch of a fused pull-stream + collide kernel: for
+ * LB_BINARY on large lattices the single-pass march, which sums phi from
+ * the pulled g and takes its stencils on chip; on small lattices (or with
+ * LB_STEP_TWO_PASS) a phi kernel, then the fused collide (see
+ * binary_step).  Paper: Section IV (collision) and Section II-A
+ * (propagation, finite-difference gradients of phi). */
 int lb_step(lb_ctx* ctx, int32_t nsteps);
 
 /* Moments of the current state, FP64: rho[N], u[3*N] component-major, and
- * phi[N] (binary only; NULL to skip).  rho or u may be NULL to skip them. */
+ * phi[N] (binary only; NULL to skip).  rho or u may be NULL to skip them.
+ * Paper: Section III-A (the host copy is refreshed from the target master
+ * copy when needed) and Section III-B (copyFromTarget, structure-of-arrays
+ * fields, a vector field as three components).  LB_EINVAL if phi is given
+ * for LB_SINGLE. */
 int lb_moments(lb_ctx* ctx, double* rho, double* u, double* phi);
 
 /* out[5] (device, FP64) = (sum rho, sum j_x, sum j_y, sum j_z, sum phi) of
  * the current state, summed in a fixed order (bitwise reproducible for a
- * given lattice and state).  sum phi is 0 for LB_SINGLE. */
+ * given lattice and state).  sum phi is 0 for LB_SINGLE.  Paper: Section V
+ * (reductions over the lattice, which the paper leaves outside its layer);
+ * uses the context's partial-sum area.  LB_EINVAL on NULL. */
 int lb_conserved_sums(lb_ctx* ctx, double* out);
 
 /* out[10] (device, FP64) = statistics of the current state, reduced in a
@@ -183,11 +212,16 @@ int lb_field_stats(lb_ctx* ctx, double* out);
 
 /* Copy the current state out / in, canonical layout, storage dtype (double,
  * float or binary16), deviations for LB_F32/LB_F16.  f has 19*N elements; g
- * likewise (binary only; NULL otherwise). */
+ * likewise (binary only; NULL otherwise).  Paper: Section III-B
+ * (copyFromTarget / copyToTarget of whole lattice fields; structure of
+ * arrays, element (i, s) at i*N + s).  Device-to-device copies on the
+ * stream.  LB_EINVAL if f is NULL or g does not match the model. */
 int lb_get_state(lb_ctx* ctx, void* f, void* g);
 int lb_set_state(lb_ctx* ctx, const void* f, const void* g);
 
-/* Change tau_f (> 0.5) for subsequent collisions. */
+/* Change tau_f (> 0.5) for subsequent collisions.  Not in the paper (a
+ * kernel parameter, the role Section III-B gives to copyConstant...ToTarget).
+ * LB_EINVAL if tau_f <= 0.5 or not finite. */
 int lb_set_tau(lb_ctx* ctx, double tau_f);
 
 /* nsteps x (collide; propagate) like lb_step (LB_SINGLE: any collision;
@@ -201,7 +235,9 @@ int lb_set_tau(lb_ctx* ctx, double tau_f);
  * LB_F64, float otherwise).  phi must be NULL for LB_SINGLE.  The state
  * afterwards equals that after lb_step(nsteps).  Used by the adjoints'
  * segment recompute: post[k] holds the state of step k+1 in pending (pull)
- * form.  nsteps == 0 is a no-op. */
+ * form.  nsteps == 0 is a no-op.  Not in the paper (the forward half of the
+ * checkpoint-and-recompute adjoint, which the paper does not have).
+ * LB_EINVAL if post is NULL with nsteps > 0 or phi is given for LB_SINGLE. */
 int lb_step_record(lb_ctx* ctx, int32_t nsteps, void* post, void* phi);
 
 /* Adjoint (reverse) of one single-fluid step f^{n+1} = propagate(collide(f^n)),
@@ -217,14 +253,19 @@ int lb_step_record(lb_ctx* ctx, int32_t nsteps, void* post, void* phi);
  * this step's dL/d(1/tau) for each relaxation time: 1 value for LB_BGK
  * (tau_f), 2 for LB_TRT (tau_f, tau_minus), 5 for LB_MRT (tau_f, tau_minus,
  * tau_bulk, tau_ghost_even, tau_ghost_odd); the caller zeroes them first and
- * converts with dL/dtau = -dL/domega / tau^2.  Uses the context's times. */
+ * converts with dL/dtau = -dL/domega / tau^2.  Uses the context's times.
+ * Not in the paper (it has no adjoint); the transpose of the step of
+ * lb_step.  LB_ENOTSUP for LB_BINARY or reduced storage; LB_EINVAL on NULL
+ * or aliasing arrays. */
 int lb_adjoint_step(lb_ctx* ctx, const double* f, int f_pending, const double* lam_next,
                     double* lam_n, double* domega);
 
 /* Replace the physical parameters (tau_f, A, B, kappa, mobility, gamma,
- * tau_minus, tau_bulk, tau_ghost_even, tau_ghost_odd) for subsequent calls.  Every other field (sizes, model,
- * storage, vvl, collision, rho0, phi0) must equal the context's, else
- * LB_EINVAL; values are validated as by lb_create.  The state is kept. */
+ * tau_minus, tau_bulk, tau_ghost_even, tau_ghost_odd) for subsequent calls.
+ * Every other field (sizes, model, storage, vvl, collision, binary_step,
+ * rho0, phi0) must equal the context's, else LB_EINVAL; values are
+ * validated as by lb_create.  The state is kept.  Not in the paper (the
+ * operation's constant parameters, Section III-B's copyConstant family). */
 int lb_set_params(lb_ctx* ctx, const lb_params* p);
 
 /* Adjoint (reverse) of one binary-fluid step, LB_BINARY + LB_F64 only, for
@@ -247,7 +288,10 @@ int lb_set_params(lb_ctx* ctx, const lb_params* p);
  * LB_TRT, 7 for LB_MRT.  With TRT or MRT the symmetric relaxation Omega
  * takes the place of 1/tau_f as in lb_adjoint_step.  Uses the context's parameters;
  * uses the context's spare state buffer and phi buffer as scratch, so calls
- * on one context must not overlap; the lattice state itself is unchanged. */
+ * on one context must not overlap; the lattice state itself is unchanged.
+ * Not in the paper (it has no adjoint); the transpose of Section IV's
+ * binary step as this library computes it.  LB_ENOTSUP for LB_SINGLE or
+ * reduced storage; LB_EINVAL on NULL or aliasing arrays. */
 int lb_adjoint_step_binary(lb_ctx* ctx, const double* f, const double* g, const double* phi_n,
                            int pending, const double* lf_next, const double* lg_next,
                            double* lf_n, double* lg_n, double* grads);
@@ -258,7 +302,8 @@ int lb_adjoint_step_binary(lb_ctx* ctx, const double* f, const double* g, const 
  * drho[N] = dL/drho, du[3*N] = dL/du and INCREMENTS *dkappa (one device
  * double) by the dependence of the initial state on kappa.  Any collision
  * (the initial state does not relax).  Same scratch rule as
- * lb_adjoint_step_binary. */
+ * lb_adjoint_step_binary.  Not in the paper (transpose of lb_init_equilibrium).
+ * LB_ENOTSUP for LB_SINGLE or reduced storage; LB_EINVAL on NULL. */
 int lb_adjoint_init_binary(lb_ctx* ctx, const double* rho, const double* u, const double* phi,
                            const double* lf0, const double* lg0, double* dphi, double* drho,
                            double* du, double* dkappa);
@@ -293,7 +338,8 @@ int lb_adjoint_init_binary(lb_ctx* ctx, const double* rho, const double* u, cons
  * the context's spare state buffer and phi buffer as scratch (calls on one
  * context must not overlap; the lattice state is unchanged).  With
  * lb_profile on, every kernel of the sweep is timed as LB_K_ADJOINT, one
- * record per step's local kernel (single: the k_adjoint launch). */
+ * record per step's local kernel (single: the k_adjoint launch).
+ * Not in the paper (it has no adjoint). */
 int lb_adjoint_segment(lb_ctx* ctx, const double* f0, const double* post, int32_t length, double* lam,
                        double* work, double* domega);
 int lb_adjoint_segment_binary(lb_ctx* ctx, const double* f0, const double* g0, const double* post,
@@ -310,7 +356,11 @@ int lb_adjoint_segment_binary(lb_ctx* ctx, const double* f0, const double* g0, c
  * i*m + t; g_packed only for LB_BINARY, else NULL); lb_set_sites writes them
  * back into the state (sites outside [0, N) are skipped; listing a site twice
  * leaves one of the two values).  m = 0 is a no-op; m < 0 or m > N is
- * LB_EINVAL. */
+ * LB_EINVAL.  Paper: Section III-B (copyFromTargetMasked /
+ * copyToTargetMasked: a boolean structure of size N selects the sites, a
+ * kernel packs them into a scratch structure on the target; the host-side
+ * unpack loop is the caller's).  lb_mask_index keeps its block counts in the
+ * context's partial-sum area. */
 int lb_mask_index(lb_ctx* ctx, const uint8_t* mask, int32_t* index, int64_t* count);
 int lb_get_sites(lb_ctx* ctx, const int32_t* index, int64_t m, void* f_packed, void* g_packed);
 int lb_set_sites(lb_ctx* ctx, const int32_t* index, int64_t m, const void* f_packed, const void* g_packed);
@@ -321,7 +371,8 @@ int lb_set_sites(lb_ctx* ctx, const int32_t* index, int64_t m, const void* f_pac
  * are created without the system-scope fence (hipEventDisableSystemFence):
  * they time the work between them but do not publish its memory to the host.
  * lb_kernel_times waits for the recorded events and returns, for kernel
- * class `kind`, the summed duration in milliseconds and the launch count. */
+ * class `kind`, the summed duration in milliseconds and the launch count.
+ * Not in the paper (measurement; its Section IV reports whole-run times). */
 #define LB_K_COLLIDE  0   /* collide / fused pull-stream + collide */
 #define LB_K_PHI      1   /* order-parameter kernel (binary) */
 #define LB_K_STREAM   2   /* stand-alone propagation */
@@ -336,10 +387,22 @@ int lb_profile_mask(lb_ctx* ctx, unsigned kinds);
 int lb_kernel_times(lb_ctx* ctx, int kind, double* total_ms, int64_t* launches);
 
 /* Destroy a context (waits for its stream).  NULL is allowed (LB_OK).
- * The workspace is not freed: it belongs to the caller. */
+ * The workspace is not freed: it belongs to the caller.  Paper: Section
+ * III-B (targetFree), except that the memory is the caller's. */
 int lb_destroy(lb_ctx* ctx);
 
-/* Static description of a status code. */
+/* Streaming copy: dst[0 .. bytes) = src[0 .. bytes), device pointers, both
+ * 16-byte aligned, bytes a multiple of 16, the two ranges disjoint; queued
+ * on `stream` (a hipStream_t, NULL = the null stream).  Every byte is read
+ * once and written once with 16-byte accesses (nontemporal stores, as in the
+ * step kernels): the HBM rate of a plain copy on this memory system, which
+ * bounds the step kernels in practice, and the reference kernel that turns
+ * the HBM byte counters of a profiler into bytes.  Needs no context.
+ * bytes == 0 is a no-op; LB_EINVAL on NULL, misalignment, overlap or a
+ * grid beyond 2^31 - 1 blocks.  Not in the paper (measurement). */
+int lb_stream_copy(void* dst, const void* src, size_t bytes, void* stream);
+
+/* Static description of a status code.  Not in the paper. */
 const char* lb_strerror(int status);
 
 #ifdef __cplusplus

@@ -24,8 +24,9 @@ def build(verbose=False):
     os.makedirs(os.path.dirname(LIB), exist_ok=True)
     tmp = LIB + ".tmp%d" % os.getpid()
     # plain IEEE double arithmetic: no fast-math, no FMA contraction
-    cmd = [cc, "-O2", "-std=c99", "-Wall", "-fPIC", "-shared", "-ffp-contract=off", "-I", os.path.join(ROOT, "include"),
-           SRC, "-lm", "-o", tmp]
+    # OpenMP over sites: per-site arithmetic is the same on any thread
+    cmd = [cc, "-O2", "-std=c99", "-Wall", "-fPIC", "-shared", "-ffp-contract=off", "-fopenmp", "-I",
+           os.path.join(ROOT, "include"), SRC, "-lm", "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

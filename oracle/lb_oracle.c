@@ -26,7 +26,13 @@
  * Only LB_F64 storage and LB_BGK collision (other settings: LB_ENOTSUP), and
  * only the core calls (create, init, collide, propagate, step, moments,
  * conserved sums, get/set state, destroy).  Layout: canonical, distribution
- * i of site s = x + nx (y + ny z) at [i*N + s]. */
+ * i of site s = x + nx (y + ny z) at [i*N + s].
+ *
+ * Threads: built with OpenMP, the loops over sites (and over z planes in the
+ * stencils and the propagation) are shared among threads.  Every value is
+ * computed by the same expression whatever thread computes it, and the
+ * conserved sums are taken serially in site order, so results do not depend
+ * on the thread count (bitwise).  lb_oracle_set_threads chooses the count. */
 
 #include <math.h>
 #include <stddef.h>
@@ -36,7 +42,24 @@
 
 #include "lb.h"
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
 #define NQ 19
+
+/* Number of threads for the loops below (n <= 0: all the host offers);
+ * returns the count that will be used.  Not part of lb.h. */
+int lb_oracle_set_threads(int n) {
+#ifdef _OPENMP
+    if (n <= 0) n = omp_get_num_procs();
+    omp_set_num_threads(n);
+    return n;
+#else
+    (void)n;
+    return 1;
+#endif
+}
 
 static int CV[NQ][3];
 static double WT[NQ];
@@ -138,17 +161,24 @@ const char* lb_strerror(int status) {
     return "unknown status";
 }
 
-/* index of (x + dx, y + dy, z + dz), periodic */
+/* a + d wrapped into [0, n), for a in [0, n) and d in {-1, 0, 1} */
+static int wrap(int a, int d, int n) {
+    a += d;
+    return a < 0 ? a + n : (a >= n ? a - n : a);
+}
+
+/* index of (x + dx, y + dy, z + dz), periodic; dx, dy, dz in {-1, 0, 1} */
 static size_t nb(const lb_params* p, int x, int y, int z, int dx, int dy, int dz) {
-    x = (x + dx + p->nx) % p->nx;
-    y = (y + dy + p->ny) % p->ny;
-    z = (z + dz + p->nz) % p->nz;
+    x = wrap(x, dx, p->nx);
+    y = wrap(y, dy, p->ny);
+    z = wrap(z, dz, p->nz);
     return (size_t)x + (size_t)p->nx * ((size_t)y + (size_t)p->ny * z);
 }
 
 /* central-difference gradient and 7-point Laplacian of c->phi */
 static void stencils(lb_ctx* c) {
     const lb_params* p = &c->p;
+#pragma omp parallel for schedule(static)
     for (int z = 0; z < p->nz; ++z)
         for (int y = 0; y < p->ny; ++y)
             for (int x = 0; x < p->nx; ++x) {
@@ -165,6 +195,7 @@ static void stencils(lb_ctx* c) {
 
 /* phi = sum g, then its stencils */
 static void phi_fields(lb_ctx* c, const double* g) {
+#pragma omp parallel for schedule(static)
     for (size_t s = 0; s < c->n; ++s) {
         double a = 0.0;
         for (int i = 0; i < NQ; ++i) a += g[i * c->n + s];
@@ -226,6 +257,7 @@ int lb_init_equilibrium(lb_ctx* c, const double* rho, const double* u, const dou
         memcpy(c->phi, phi, c->n * sizeof(double));
         stencils(c);
     }
+#pragma omp parallel for schedule(static)
     for (size_t s = 0; s < c->n; ++s) {
         const double us[3] = {u[s], u[c->n + s], u[2 * c->n + s]};
         double feq[NQ], geq[NQ], P[3][3], mu = 0.0;
@@ -245,6 +277,7 @@ int lb_collide(lb_ctx* c) {
     const double of = 1.0 / c->p.tau_f;
     const double og = 1.0 / (c->p.mobility / c->p.gamma + 0.5);
     if (bin) phi_fields(c, c->g);
+#pragma omp parallel for schedule(static)
     for (size_t s = 0; s < c->n; ++s) {
         double rho, u[3], feq[NQ], geq[NQ], P[3][3], mu = 0.0;
         moments_of(c->f, c->n, s, &rho, u);
@@ -265,6 +298,7 @@ int lb_collide(lb_ctx* c) {
 static void stream_one(lb_ctx* c, double* a) {
     const lb_params* p = &c->p;
     for (int i = 0; i < NQ; ++i)
+#pragma omp parallel for schedule(static)
         for (int z = 0; z < p->nz; ++z)
             for (int y = 0; y < p->ny; ++y)
                 for (int x = 0; x < p->nx; ++x)
@@ -292,6 +326,7 @@ int lb_step(lb_ctx* c, int32_t nsteps) {
 int lb_moments(lb_ctx* c, double* rho, double* u, double* phi) {
     if (!c) return LB_EINVAL;
     if (phi && c->p.model != LB_BINARY) return LB_EINVAL;
+#pragma omp parallel for schedule(static)
     for (size_t s = 0; s < c->n; ++s) {
         double r, us[3];
         moments_of(c->f, c->n, s, &r, us);

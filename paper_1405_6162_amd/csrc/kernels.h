@@ -1518,4 +1518,33 @@ __global__ __launch_bounds__(CB) void k_set_sites(S* __restrict__ buf, const int
     });
 }
 
+// ---------------------------------------------------------------------------
+// Streaming copy: every byte read once and written once, 16 bytes per access
+// and COPY_U accesses in flight per lane (the loads of a lane are issued
+// before its first store), nontemporal stores as in the step kernels.  The
+// plain copy is what the memory system sustains with no gather and no
+// arithmetic: the practical ceiling of the update kernels, and the kernel
+// whose known byte count calibrates the profiler's HBM byte counters.
+// ---------------------------------------------------------------------------
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int COPY_TPB = 256;
+constexpr int COPY_U = 4;
+
+__global__ __launch_bounds__(COPY_TPB) void k_stream_copy(const u32x4* __restrict__ src, u32x4* __restrict__ dst,
+                                                          uint64_t nwords) {
+    const uint64_t base = (uint64_t)blockIdx.x * (COPY_TPB * COPY_U) + threadIdx.x;
+    u32x4 v[COPY_U];
+#pragma unroll
+    for (int u = 0; u < COPY_U; ++u) {
+        const uint64_t k = base + (uint64_t)u * COPY_TPB;
+        if (k < nwords) v[u] = src[k];
+    }
+#pragma unroll
+    for (int u = 0; u < COPY_U; ++u) {
+        const uint64_t k = base + (uint64_t)u * COPY_TPB;
+        if (k < nwords) __builtin_nontemporal_store(v[u], dst + k);
+    }
+}
+
 }  // namespace lbk

@@ -1139,6 +1139,21 @@ int lb_destroy(lb_ctx* c) {
     return rc;
 }
 
+int lb_stream_copy(void* dst, const void* src, size_t bytes, void* stream) {
+    if (bytes == 0) return LB_OK;
+    if (!dst || !src) return LB_EINVAL;
+    const uintptr_t d = reinterpret_cast<uintptr_t>(dst), s = reinterpret_cast<uintptr_t>(src);
+    if (d % 16 != 0 || s % 16 != 0 || bytes % 16 != 0) return LB_EINVAL;
+    if (d < s + bytes && s < d + bytes) return LB_EINVAL;
+    const uint64_t nwords = bytes / 16;
+    const uint64_t per_block = (uint64_t)COPY_TPB * COPY_U;
+    const uint64_t nblocks = (nwords + per_block - 1) / per_block;
+    if (nblocks > 0x7fffffffull) return LB_EINVAL;
+    k_stream_copy<<<(unsigned)nblocks, COPY_TPB, 0, (hipStream_t)stream>>>(
+        static_cast<const u32x4*>(src), static_cast<u32x4*>(dst), nwords);
+    return launch_status();
+}
+
 const char* lb_strerror(int status) {
     switch (status) {
         case LB_OK: return "ok";

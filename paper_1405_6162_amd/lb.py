@@ -91,6 +91,7 @@ _SIGNATURES = {
     "lb_profile_mask": (_int, [_vp, ctypes.c_uint]),
     "lb_kernel_times": (_int, [_vp, _int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     "lb_destroy": (_int, [_vp]),
+    "lb_stream_copy": (_int, [_vp, _vp, ctypes.c_size_t, _vp]),
     "lb_strerror": (ctypes.c_char_p, [_int]),
 }
 
@@ -274,6 +275,17 @@ def lb_destroy(ctx):
 def lb_strerror(status):
     load()
     return _lib.lb_strerror(status).decode()
+
+
+def lb_stream_copy(dst, src, nbytes=None, stream=None):
+    """Streaming copy of the first `nbytes` bytes (default: all of src) of
+    device tensor src into dst, on `stream` (default: the current one)."""
+    load()
+    nbytes = src.numel() * src.element_size() if nbytes is None else int(nbytes)
+    if nbytes > src.numel() * src.element_size() or nbytes > dst.numel() * dst.element_size():
+        raise ValueError("copy larger than its tensors")
+    _check("lb_stream_copy", _lib.lb_stream_copy(_ptr(dst), _ptr(src), nbytes,
+                                                 _stream() if stream is None else stream))
 
 
 # ---- a small owner object ---------------------------------------------------

@@ -9,8 +9,9 @@ from a `rocprofv3 --kernel-trace --stats --output-format csv` run.
 
 `pmc` prints FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the kernels
 whose name contains SUBSTRING, and scales each by what the same counter
-reads for the largest plain copy kernel in the run (`__amd_rocclr_copyBuffer`,
-which moves `copy-bytes` in each direction), giving HBM bytes per launch.
+reads for the largest dispatch of the library's streaming copy
+(`k_stream_copy`, which moves `copy-bytes` in each direction), giving HBM
+bytes per launch.
 The last lines are `key: value` pairs that bench.py reads.
 """
 
@@ -60,12 +61,13 @@ def _per_kernel(path):
 
 
 def _copy_reference(vals, grid):
-    """Counter value of the probe copy: the largest `__amd_rocclr_copyBuffer`
-    dispatches (the 2 GiB device copy is far larger than any other copy in a
-    bench run); dispatches within 1% of the largest are averaged."""
-    v = vals.get("__amd_rocclr_copyBuffer", [])
+    """Counter value of the probe copy: the largest dispatches of the
+    library's streaming copy `k_stream_copy` (the bench's 2 GiB probe is far
+    larger than any other copy in a run); dispatches within 1% of the
+    largest are averaged."""
+    v = [x for name, xs in vals.items() if "k_stream_copy" in name for x in xs]
     if not v:
-        raise SystemExit("no copy kernel found for scaling")
+        raise SystemExit("no k_stream_copy dispatch found for scaling")
     top = max(v)
     best = [x for x in v if x >= 0.99 * top]
     return sum(best) / len(best)

@@ -20,6 +20,9 @@ from paper_1405_6162_amd import profsummary  # noqa: E402
 COUNTER_FIELDS = ["Correlation_Id", "Dispatch_Id", "Grid_Size", "Kernel_Name", "Counter_Name", "Counter_Value"]
 
 
+COPY = "lbk::k_stream_copy(unsigned int const*, unsigned int*, unsigned long)"
+
+
 def _counter_csv(path, name, rows):
     with open(path, "w", newline="") as fh:
         w = csv.DictWriter(fh, fieldnames=COUNTER_FIELDS)
@@ -30,11 +33,11 @@ def _counter_csv(path, name, rows):
 
 
 def test_pmc_scaling_and_multi_kernel_step(tmp_path, capsys):
-    """FETCH_SIZE of the 2 GiB copy reads half its bytes (scale 2), WRITE_SIZE
-    all of them (scale 1); a step of two kernels sums their per-dispatch
+    """a copy whose FETCH_SIZE reads half its bytes gets scale 2, one whose
+    WRITE_SIZE reads all of them scale 1; a step of two kernels sums their per-dispatch
     traffic, taking the most-dispatched match of each substring."""
     kib = 1024.0
-    copy = "__amd_rocclr_copyBuffer"
+    copy = COPY
     fetch = [(copy, 1048576.0), (copy, 10.0), ("void k_a<1, true>(x)", 100.0), ("void k_a<1, true>(x)", 102.0),
              ("void k_a<1, false>(x)", 500.0), ("void k_b<2>(y)", 40.0)]
     write = [(copy, 2097152.0), (copy, 10.0), ("void k_a<1, true>(x)", 200.0), ("void k_a<1, true>(x)", 200.0),
@@ -56,8 +59,8 @@ def test_pmc_scaling_and_multi_kernel_step(tmp_path, capsys):
 
 def test_pmc_missing_kernel_and_missing_copy(tmp_path):
     fp, wp = tmp_path / "f.csv", tmp_path / "w.csv"
-    _counter_csv(fp, "FETCH_SIZE", [("__amd_rocclr_copyBuffer", 1.0), ("k_a", 1.0)])
-    _counter_csv(wp, "WRITE_SIZE", [("__amd_rocclr_copyBuffer", 1.0), ("k_a", 1.0)])
+    _counter_csv(fp, "FETCH_SIZE", [(COPY, 1.0), ("k_a", 1.0)])
+    _counter_csv(wp, "WRITE_SIZE", [(COPY, 1.0), ("k_a", 1.0)])
     with pytest.raises(SystemExit):
         profsummary.main(["pmc", str(fp), str(wp), "--kernel", "k_missing"])
     _counter_csv(fp, "FETCH_SIZE", [("k_a", 1.0)])

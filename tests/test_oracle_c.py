@@ -83,3 +83,29 @@ def test_refusals():
         C.CLattice(4, 4, 4, tau_f=0.5)
     with pytest.raises(ValueError):
         C.CLattice(0, 4, 4)
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_thread_count_does_not_change_a_bit(model):
+    """The site loops are shared among OpenMP threads; every value is the same
+    expression on any thread and the conserved sums are serial, so 1, 3 and
+    8 threads give identical states, moments and sums."""
+    nx, ny, nz = 9, 7, 11
+    out = []
+    for threads in (1, 3, 8):
+        C.set_threads(threads)
+        lat = C.CLattice(nx, ny, nz, model=model, tau_f=0.9)
+        if model:
+            lat.init_equilibrium(*inputs.spinodal_quench(nx, ny, nz, seed=3, phi_max=0.2))
+        else:
+            lat.init_equilibrium(*inputs.single_fluid_random(nx, ny, nz, seed=3))
+        lat.step(4)
+        f, g = lat.state()
+        rho, u, phi = lat.moments()
+        out.append((f, g, rho, u, phi, lat.sums()))
+        lat.close()
+    C.set_threads(0)
+    for other in out[1:]:
+        for a, b in zip(out[0], other):
+            if a is not None:
+                assert np.array_equal(a, b)
