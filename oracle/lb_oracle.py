@@ -825,3 +825,107 @@ def rollout_gradient_binary(rho, u, phi, prm, nsteps, beta=1.0, taus=None):
         for k, t in zip(MRT_RATES, taus):
             grads["tau_" + k] = -dw["omega_" + k] / (t * t)
     return loss, dphi, drho, du, grads
+
+
+# ---------------------------------------------------------------------------
+# The binary adjoint by its definition
+# ---------------------------------------------------------------------------
+#
+# The reverse of one step is, by definition, lambda^n = J^T lambda^{n+1} with
+# J the Jacobian of the whole step (collide, then propagate) with respect to
+# the state (f^n, g^n).  The functions below build J one column at a time
+# from the plain forward above by complex-step differentiation: column k is
+# Im step(x + i h e_k) / h.  Every operation of the forward (+, -, *, /,
+# integer powers, periodic shifts) is analytic and nothing is subtracted to
+# form the derivative, so each column is exact to rounding (Squire & Trapp
+# 1998).  Parameters are differentiated the same way.  This uses none of
+# the hand-derived sums above (binary_adjoint_sums and what builds on it):
+# one forward step per state component, so small lattices only.
+
+CSTEP = 1e-30          # complex step; far below any rounding of the real part
+
+
+def _binary_step_once(f, g, prm, taus):
+    if taus is None:
+        return step_binary(f, g, prm, 1)
+    return step_binary_mrt(f, g, prm, taus, 1)
+
+
+def _flat_state(f, g):
+    return np.concatenate([f.ravel(), g.ravel()])
+
+
+def binary_step_jacobian(f, g, prm, taus=None):
+    """J[m, k] = d x'_m / d x_k for one binary step x' = step(x), x the state
+    (f, g) flattened as concatenate(f.ravel(), g.ravel()) (f first, each in
+    the (19, nz, ny, nx) layout).  taus: None for BGK, else f's five
+    moment-space times (step_binary_mrt).  Returns a (2*19*N, 2*19*N) array."""
+    x = _flat_state(f, g).astype(np.complex128)
+    n = x.size
+    half = n // 2
+    J = np.empty((n, n))
+    for k in range(n):
+        xk = x.copy()
+        xk[k] += 1j * CSTEP
+        fo, go = _binary_step_once(xk[:half].reshape(f.shape), xk[half:].reshape(g.shape), prm, taus)
+        J[:, k] = _flat_state(fo, go).imag / CSTEP
+    return J
+
+
+def _parameter_derivative(fun, prm, name, taus=None, k=None):
+    """d fun / d parameter by one complex step: `name` is a field of Params,
+    or "taus" with k the index of f's moment-space time."""
+    import dataclasses
+    if name == "taus":
+        t = [complex(v) for v in taus]
+        t[k] += 1j * CSTEP
+        return fun(prm, tuple(t)).imag / CSTEP
+    p = dataclasses.replace(prm, **{name: getattr(prm, name) + 1j * CSTEP})
+    return fun(p, taus).imag / CSTEP
+
+
+def adjoint_step_binary_plain(f_n, g_n, lf_next, lg_next, prm, taus=None):
+    """Reverse of one binary step from its definition: (lf^n, lg^n) =
+    J^T (lf^{n+1}, lg^{n+1}) with J = binary_step_jacobian, and the
+    parameter gradients d/dp <lambda^{n+1}, step(f^n, g^n; p)> for
+    p = kappa, mobility and tau_f (BGK), or kappa, mobility and
+    tau_<group> for the five groups of MRT_RATES (taus given).  Returns
+    (lf^n, lg^n, grads)."""
+    J = binary_step_jacobian(f_n, g_n, prm, taus)
+    lam = J.T @ _flat_state(lf_next, lg_next)
+    half = lam.size // 2
+    lf_n, lg_n = lam[:half].reshape(f_n.shape), lam[half:].reshape(g_n.shape)
+    fc, gc = f_n.astype(np.complex128), g_n.astype(np.complex128)
+
+    def projected(p, t):
+        a, b = _binary_step_once(fc, gc, p, t)
+        return (lf_next * a).sum() + (lg_next * b).sum()
+    grads = {"kappa": _parameter_derivative(projected, prm, "kappa", taus),
+             "mobility": _parameter_derivative(projected, prm, "mobility", taus)}
+    if taus is None:
+        grads["tau_f"] = _parameter_derivative(projected, prm, "tau_f")
+    else:
+        for k, name in enumerate(MRT_RATES):
+            grads["tau_" + name] = _parameter_derivative(projected, prm, "taus", taus, k)
+    return lf_n, lg_n, grads
+
+
+def adjoint_init_binary_plain(rho, u, phi, lf0, lg0, prm):
+    """Reverse of init_binary from its definition: for every component of
+    phi, rho and u, the complex-step derivative of <(lf0, lg0), init_binary>,
+    and d/dkappa of the same.  Returns (dL/dphi, dL/drho, dL/du, dL/dkappa)."""
+    cx = lambda a: np.asarray(a).astype(np.complex128)
+
+    def projected(r, v, p, q=prm):
+        a, b = init_binary(r, v, p, q)
+        return (lf0 * a).sum() + (lg0 * b).sum()
+    out = []
+    for which, arr in (("phi", phi), ("rho", rho), ("u", u)):
+        d = np.empty(arr.shape)
+        for idx in np.ndindex(arr.shape):
+            args = {"rho": cx(rho), "u": cx(u), "phi": cx(phi)}
+            args[which][idx] += 1j * CSTEP
+            d[idx] = projected(args["rho"], args["u"], args["phi"]).imag / CSTEP
+        out.append(d)
+    dk = _parameter_derivative(lambda p, _t: projected(cx(rho), cx(u), cx(phi), p), prm, "kappa")
+    return out[0], out[1], out[2], dk
