@@ -111,13 +111,14 @@ def traffic_from_profile(workload):
     return int(float(info["traffic_bytes_per_launch"]))
 
 
-def cpu_baseline(model, n, slab_div=8):
+def cpu_baseline(model, n, slab_div=8, steps=8):
     """The FP64 oracle timed on the host: the C reference (oracle/lb_oracle.c,
     plain loops, OpenMP over sites; its results do not depend on the thread
-    count) from the workload's initial state.  All cores: one step of the
-    whole n^3 lattice.  One thread: one step of an n x n x n/slab_div slab of
-    the same workload (periodic, the same per-site work), so the sample stays
-    bounded.  MLUPS = sites / wall time of the step (initialisation not
+    count) from the workload's initial state.  All cores: `steps` steps of
+    the whole n^3 lattice.  One thread: `steps` steps of an n x n x
+    n/slab_div slab of the same workload (periodic, the same per-site work),
+    so the sample stays bounded (about 5-10 s of wall time each at 256^3).
+    MLUPS = site updates / wall time of the steps (initialisation not
     timed)."""
     import numpy as np
     from oracle import c_backend as C
@@ -135,21 +136,21 @@ def cpu_baseline(model, n, slab_div=8):
             lat.init_equilibrium(rho, u)
         del rho, u
         t0 = time.perf_counter()
-        lat.step(1)
+        lat.step(steps)
         dt = time.perf_counter() - t0
         ok = bool(np.isfinite(lat.sums()).all())
         lat.close()
         assert ok
-        return n * n * nz / dt / 1e6, dt, used
+        return n * n * nz * steps / dt / 1e6, dt, used
 
     v_all, t_all, cores = one_step(n, 0)
     nz1 = max(n // slab_div, 1)
     v_one, t_one, _ = one_step(nz1, 1)
     return {"value": round(v_all, 4), "unit": "MLUPS", "cores": cores, "kind": "oracle",
             "value_1_thread": round(v_one, 4),
-            "sample": "C reference (plain FP64 loops, OpenMP over sites): 1 step of the %d^3 %s-fluid workload "
-                      "on %d threads, %.1f s wall; 1 step of a %dx%dx%d slab of it on 1 thread, %.1f s wall"
-                      % (n, model, cores, t_all, n, n, nz1, t_one)}
+            "sample": "C reference (plain FP64 loops, OpenMP over sites): %d steps of the %d^3 %s-fluid workload "
+                      "on %d threads, %.1f s wall; %d steps of a %dx%dx%d slab of it on 1 thread, %.1f s wall"
+                      % (steps, n, model, cores, t_all, steps, n, n, nz1, t_one)}
 
 
 def copy_probe(torch, nbytes=2 << 30, reps=10):
