@@ -37,7 +37,9 @@
  *
  * Memory and streams.  Every pointer passed to a liblb.so function is a
  * DEVICE pointer unless stated otherwise.  The caller owns all memory: the
- * workspace given to lb_create and every input/output array.  All calls
+ * workspace given to lb_create and every input/output array (the one
+ * exception is the library's fixed device array behind the allocation-free
+ * lb_conserved_sums_noalloc).  All calls
  * that touch device memory are asynchronous on the context's stream and
  * never synchronise the device (the exceptions are lb_kernel_times, which
  * waits for the events it reads, and lb_destroy, which waits for the
@@ -66,6 +68,7 @@ extern "C" {
 #define LB_ENOMEM   (-2)   /* workspace smaller than lb_workspace_bytes() */
 #define LB_EDEVICE  (-3)   /* a HIP runtime call or kernel launch failed */
 #define LB_ENOTSUP  (-4)   /* valid request this build does not implement */
+#define LB_ERANGE   (-5)   /* lattice too large for the fixed scratch of an allocation-free call */
 
 /* Models. */
 #define LB_SINGLE   0      /* one fluid, distribution f */
@@ -401,6 +404,29 @@ int lb_destroy(lb_ctx* ctx);
  * bytes == 0 is a no-op; LB_EINVAL on NULL, misalignment, overlap or a
  * grid beyond 2^31 - 1 blocks.  Not in the paper (measurement). */
 int lb_stream_copy(void* dst, const void* src, size_t bytes, void* stream);
+
+/* Allocation-free variant of lb_conserved_sums, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc): no context and no workspace.  out[5]
+ * (device, FP64) = (sum rho, sum j_x, sum j_y, sum j_z, sum phi) of the
+ * state f (and g for LB_BINARY; NULL for LB_SINGLE) given in the canonical
+ * layout and storage dtype of *p (as lb_get_state writes it: 19*N values
+ * each, deviations for LB_F32 / LB_F16 with p->rho0, p->phi0), all device
+ * pointers of the current device, queued on `stream`.  Only p's extents,
+ * model, storage, rho0 and phi0 are read (the rest must still be valid).
+ * The same kernels and summation order as lb_conserved_sums on a context
+ * holding that state unpropagated, so the two give identical bits.
+ * Partial sums go to a fixed array of the library on each device, of
+ * LB_NOALLOC_MAX_BLOCKS blocks of 64 bytes (16 MiB, held by each device the
+ * library runs on until the process ends; every value read was written by
+ * the same call, so nothing needs clearing): lattices with
+ * ceil(nx/64) * ceil(ny/4) * nz > LB_NOALLOC_MAX_BLOCKS (a cube above
+ * 384^3, say) give LB_ERANGE.  Calls that overlap on one device (several
+ * streams, several threads) share that array and race; serialise them.
+ * Allocates nothing: no hipMalloc, no workspace.  LB_EINVAL on NULL or bad
+ * parameters; LB_EDEVICE if the device array cannot be located. */
+#define LB_NOALLOC_MAX_BLOCKS 262144
+int lb_conserved_sums_noalloc(const lb_params* p, const void* f, const void* g, double* out, void* stream);
 
 /* Static description of a status code.  Not in the paper. */
 const char* lb_strerror(int status);

@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <type_traits>
 #include <vector>
@@ -123,6 +124,34 @@ Layout layout_of(const lb_params* p) {
 }
 
 struct Rec { int kind; hipEvent_t start, stop; };
+
+}  // namespace
+
+// Partial sums of lb_conserved_sums_noalloc (8 doubles per block).  In host
+// code this name is only a stand-in for the symbol: kernels get the device
+// address that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) double scratch[8 * (size_t)LB_NOALLOC_MAX_BLOCKS];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mutex;
+double* scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device (each device holds its own copy of the array).
+int scratch_on_current_device(double** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return LB_EDEVICE;
+    std::lock_guard<std::mutex> lock(scratch_mutex);
+    if (!scratch_ptr[dev]) {
+        double* ptr = nullptr;
+        if (hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return LB_EDEVICE;
+        scratch_ptr[dev] = ptr;
+    }
+    *out = scratch_ptr[dev];
+    return LB_OK;
+}
 
 }  // namespace
 
@@ -827,6 +856,45 @@ int lb_conserved_sums(lb_ctx* c, double* out) {
     });
 }
 
+int lb_conserved_sums_noalloc(const lb_params* p, const void* f, const void* g, double* out, void* stream) {
+    if (!p || !f || !out) return LB_EINVAL;
+    int rc = check_params(p);
+    if (rc) return rc;
+    if ((p->model == LB_BINARY) != (g != nullptr)) return LB_EINVAL;
+    // the launch of lb_conserved_sums, on the canonical layout
+    Geo geo;
+    geo.nx = p->nx; geo.ny = p->ny; geo.nz = p->nz;
+    geo.plane = (uint32_t)p->nx * (uint32_t)p->ny;
+    geo.nsite = geo.plane * (uint32_t)p->nz;
+    geo.dstride = geo.nsite;
+    geo.gx = tiles(p->nx, Pol::TX);
+    geo.gy = tiles(p->ny, Pol::TY);
+    geo.gz = tiles(p->nz, Pol::TZ);
+    const int64_t nblocks = (int64_t)geo.gx * geo.gy * geo.gz;
+    if (nblocks > LB_NOALLOC_MAX_BLOCKS) return LB_ERANGE;
+    geo.nblocks = (int)nblocks;
+    double* partial = nullptr;
+    rc = scratch_on_current_device(&partial);
+    if (rc) return rc;
+    const hipStream_t s = (hipStream_t)stream;
+    const bool dev = p->storage != LB_F64;
+    const double n = (double)geo.nsite;
+    const double b0 = dev ? n * p->rho0 : 0.0;
+    const double b4 = (dev && p->model == LB_BINARY) ? n * p->phi0 : 0.0;
+    auto launch = [&](auto tag) {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        if (p->model == LB_BINARY)
+            k_sums_partial<Pol, MODEL_BINARY, S><<<geo.nblocks, Pol::TPB, 0, s>>>((const S*)f, (const S*)g, geo, partial);
+        else
+            k_sums_partial<Pol, MODEL_SINGLE, S><<<geo.nblocks, Pol::TPB, 0, s>>>((const S*)f, nullptr, geo, partial);
+        k_sums_final<Pol, 5><<<1, Pol::TPB, 0, s>>>(partial, geo.nblocks, out, b0, b4, 0);
+        return launch_status();
+    };
+    if (p->storage == LB_F64) return launch((double*)nullptr);
+    if (p->storage == LB_F32) return launch((float*)nullptr);
+    return launch((_Float16*)nullptr);
+}
+
 int lb_field_stats(lb_ctx* c, double* out) {
     if (!c || !out) return LB_EINVAL;
     return by_storage(c, [&](auto tag) {
@@ -1161,6 +1229,7 @@ const char* lb_strerror(int status) {
         case LB_ENOMEM: return "workspace too small";
         case LB_EDEVICE: return "HIP runtime or kernel launch failure";
         case LB_ENOTSUP: return "not supported for this model or storage";
+        case LB_ERANGE: return "lattice too large for the fixed scratch of an allocation-free call";
     }
     return "unknown status";
 }

@@ -13,7 +13,8 @@ import os
 
 import torch
 
-LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_ENOTSUP = 0, -1, -2, -3, -4
+LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_ENOTSUP, LB_ERANGE = 0, -1, -2, -3, -4, -5
+LB_NOALLOC_MAX_BLOCKS = 262144
 LB_SINGLE, LB_BINARY = 0, 1
 LB_F64, LB_F32, LB_F16 = 0, 1, 2
 LB_BGK, LB_TRT, LB_MRT = 0, 1, 2
@@ -92,6 +93,7 @@ _SIGNATURES = {
     "lb_kernel_times": (_int, [_vp, _int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     "lb_destroy": (_int, [_vp]),
     "lb_stream_copy": (_int, [_vp, _vp, ctypes.c_size_t, _vp]),
+    "lb_conserved_sums_noalloc": (_int, [ctypes.POINTER(lb_params), _vp, _vp, _vp, _vp]),
     "lb_strerror": (ctypes.c_char_p, [_int]),
 }
 
@@ -270,6 +272,15 @@ def lb_kernel_times(ctx, kind):
 def lb_destroy(ctx):
     if _lib is not None and ctx is not None:
         _check("lb_destroy", _lib.lb_destroy(ctx))
+
+
+def lb_conserved_sums_noalloc(params, f, g, out, stream=None):
+    """Allocation-free sums of a canonical state (f, g device tensors of the
+    storage dtype of `params`; g None for the single fluid) into out[5]."""
+    load()
+    dt = STORAGE_DTYPE[params.storage]
+    _check("lb_conserved_sums_noalloc", _lib.lb_conserved_sums_noalloc(
+        ctypes.byref(params), _ptr(f, dt), _ptr(g, dt), _f64(out), _stream() if stream is None else stream))
 
 
 def lb_strerror(status):

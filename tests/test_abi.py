@@ -46,7 +46,8 @@ def test_library_exports_every_declared_symbol(lib):
 
 def test_constants_match_header():
     text = open(HEADER).read()
-    for name in ("LB_OK", "LB_EINVAL", "LB_ENOMEM", "LB_EDEVICE", "LB_ENOTSUP", "LB_SINGLE", "LB_BGK", "LB_TRT", "LB_MRT",
+    for name in ("LB_OK", "LB_EINVAL", "LB_ENOMEM", "LB_EDEVICE", "LB_ENOTSUP", "LB_ERANGE", "LB_NOALLOC_MAX_BLOCKS",
+                 "LB_SINGLE", "LB_BGK", "LB_TRT", "LB_MRT",
                  "LB_BINARY", "LB_F64", "LB_F32", "LB_F16", "LB_K_COLLIDE", "LB_K_PHI", "LB_STEP_AUTO",
                  "LB_STEP_MARCH", "LB_STEP_TWO_PASS",
                  "LB_K_STREAM", "LB_K_ADJOINT", "LB_K_OTHER"):
@@ -252,6 +253,25 @@ def test_collision_support_of_the_adjoint_calls(lib):
         assert lib.lb_adjoint_segment_binary(ctx, fake[0], fake[1], None, None, 1, *fake[2:6]) == lb.LB_ENOTSUP
     finally:
         assert lib.lb_destroy(ctx) == lb.LB_OK
+
+
+@no_device
+def test_noalloc_sums_refusals(lib):
+    """lb_conserved_sums_noalloc checks its arguments and the size of its
+    fixed scratch before it looks up the device array or launches."""
+    fake = [ctypes.c_void_p((k + 2) << 20) for k in range(3)]
+    p = lb.make_params(8, 8, 8, model=lb.LB_BINARY)
+    assert lib.lb_conserved_sums_noalloc(None, fake[0], fake[1], fake[2], None) == lb.LB_EINVAL
+    assert lib.lb_conserved_sums_noalloc(ctypes.byref(p), None, fake[1], fake[2], None) == lb.LB_EINVAL
+    assert lib.lb_conserved_sums_noalloc(ctypes.byref(p), fake[0], None, fake[2], None) == lb.LB_EINVAL   # g: binary
+    assert lib.lb_conserved_sums_noalloc(ctypes.byref(p), fake[0], fake[1], None, None) == lb.LB_EINVAL
+    s = lb.make_params(8, 8, 8)
+    assert lib.lb_conserved_sums_noalloc(ctypes.byref(s), fake[0], fake[1], fake[2], None) == lb.LB_EINVAL  # no g
+    bad = lb.make_params(8, 8, 8, tau_f=0.4)
+    assert lib.lb_conserved_sums_noalloc(ctypes.byref(bad), fake[0], None, fake[2], None) == lb.LB_EINVAL
+    # ceil(64/64) * ceil(4/4) * nz blocks: one past the fixed array
+    big = lb.make_params(64, 4, lb.LB_NOALLOC_MAX_BLOCKS + 1)
+    assert lib.lb_conserved_sums_noalloc(ctypes.byref(big), fake[0], None, fake[2], None) == lb.LB_ERANGE
 
 
 def test_null_handles(lib):
