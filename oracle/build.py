@@ -12,7 +12,6 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "lb_oracle.c")
 LIB = os.path.join(HERE, "_lib", "liblb_oracle.so")
 
@@ -25,8 +24,7 @@ def build(verbose=False):
     tmp = LIB + ".tmp%d" % os.getpid()
     # plain IEEE double arithmetic: no fast-math, no FMA contraction
     # OpenMP over sites: per-site arithmetic is the same on any thread
-    cmd = [cc, "-O2", "-std=c99", "-Wall", "-fPIC", "-shared", "-ffp-contract=off", "-fopenmp", "-I",
-           os.path.join(ROOT, "include"), SRC, "-lm", "-o", tmp]
+    cmd = [cc, "-O2", "-std=c99", "-Wall", "-fPIC", "-shared", "-ffp-contract=off", "-fopenmp", SRC, "-lm", "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

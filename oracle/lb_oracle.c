@@ -1,4 +1,4 @@
-/* Plain FP64 CPU reference behind the library's C ABI (include/lb.h), with
+/* Plain FP64 CPU reference behind the library's C calling convention, with
  * HOST pointers: the same calls as liblb.so, computed by straightforward
  * loops over the lattice, one phase at a time.
  *
@@ -40,7 +40,24 @@
 #include <stdlib.h>
 #include <string.h>
 
-#include "lb.h"
+/* The library's C calling convention, declared here on its own (this file
+ * includes nothing of the library): the parameter record, field for field
+ * in the library's order, and the status and selector values it uses.
+ * The tests compile the library header's README example against this file
+ * and drive it through the same calls as the GPU library, which fails on
+ * any layout mismatch. */
+typedef struct lb_params {
+    int32_t nx, ny, nz, model, storage, vvl, collision, binary_step;
+    double tau_f, A, B, kappa, mobility, gamma, rho0, phi0;
+    double tau_minus, tau_bulk, tau_ghost_even, tau_ghost_odd;
+} lb_params;
+typedef struct lb_ctx lb_ctx;
+
+enum { LB_OK = 0, LB_EINVAL = -1, LB_ENOMEM = -2, LB_EDEVICE = -3, LB_ENOTSUP = -4 };
+enum { LB_SINGLE = 0, LB_BINARY = 1 };
+enum { LB_F64 = 0 };
+enum { LB_BGK = 0 };
+enum { LB_STEP_AUTO = 0, LB_STEP_TWO_PASS = 2 };
 
 #ifdef _OPENMP
 #include <omp.h>
