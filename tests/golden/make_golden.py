@@ -62,8 +62,26 @@ def compute(model, shape, steps, seed):
     return np.stack([f, g])
 
 
+# the library's order of the binary MRT rate sums: d/d omega of the shear
+# (tau_f), of g (tau_g), of kappa, then flux, bulk, even ghosts, odd ghosts
+MRT_GRAD_NAMES = ("omega_shear", "omega_g", "kappa", "omega_flux", "omega_bulk", "omega_ghost_even",
+                  "omega_ghost_odd")
+
+
+def adjoint_grads(shape, steps, seed):
+    """The seven parameter sums of the binary MRT adjoint step, in the
+    library's order."""
+    f, g, lf, lg = adjoint_inputs(shape, steps, seed)
+    _lf, _lg, grads = O.adjoint_step_binary(f, g, lf, lg, O.Params(tau_f=MRT_TAUS[0]), MRT_TAUS)
+    return np.array([grads[k] for k in MRT_GRAD_NAMES])
+
+
 def path(name):
     return os.path.join(HERE, name + ".txt")
+
+
+def grads_path(name):
+    return os.path.join(HERE, name + "_grads.txt")
 
 
 def main():
@@ -79,6 +97,12 @@ def main():
                   % (name, what, a.shape))
         np.savetxt(path(name), a.reshape(-1), fmt="%.17e", header=header)
         print(path(name))
+        if model == "binary_mrt_adjoint":
+            gr = adjoint_grads(shape, steps, seed)
+            np.savetxt(grads_path(name), gr, fmt="%.17e",
+                       header="%s: the adjoint step's parameter sums %s, oracle FP64, written by "
+                              "tests/golden/make_golden.py" % (name, ", ".join(MRT_GRAD_NAMES)))
+            print(grads_path(name))
 
 
 if __name__ == "__main__":

@@ -28,6 +28,15 @@ def test_oracle_reproduces_stored_values(name):
     assert np.abs(got - want).max() <= 1e-14 * np.abs(want).max()
 
 
+def test_oracle_reproduces_stored_adjoint_sums():
+    for name, (model, shape, steps, seed) in G.CASES.items():
+        if model != "binary_mrt_adjoint":
+            continue
+        want = np.loadtxt(G.grads_path(name))
+        got = G.adjoint_grads(shape, steps, seed)
+        assert np.abs(got - want).max() <= 1e-14 * np.abs(want).max()
+
+
 @pytest.mark.gpu
 @pytest.mark.parametrize("name", sorted(G.CASES))
 def test_gpu_matches_stored_values(lbgpu, name):
@@ -45,8 +54,12 @@ def test_gpu_matches_stored_values(lbgpu, name):
         lbgpu.lb_set_stream(lat.ctx, lbgpu._stream())
         lbgpu.lb_adjoint_step_binary(lat.ctx, f, g, lf, lg, lf_n, lg_n, grads)
         got = np.stack([lf_n.cpu().numpy(), lg_n.cpu().numpy()])
+        got_sums = grads.cpu().numpy()
         lat.close()
         assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+        want_sums = np.loadtxt(G.grads_path(name))
+        for k, w in enumerate(want_sums):
+            assert abs(got_sums[k] - w) <= 1e-12 * max(abs(w), 1.0), G.MRT_GRAD_NAMES[k]
         return
     if model == "single":
         rho, u = inputs.single_fluid_random(nx, ny, nz, seed=seed)

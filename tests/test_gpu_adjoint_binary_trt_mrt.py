@@ -230,9 +230,9 @@ def test_binary_trt_rollout_central_differences_24(lbgpu):
 
 
 def test_binary_mrt_rollout_central_differences_24(lbgpu):
-    """24^3, 12 steps, checkpoints every 5, f by MRT: the gradients in the
-    bulk, flux and odd-ghost times against central differences (eps 1e-6) of
-    the GPU forward."""
+    """24^3, 12 steps, checkpoints every 5, f by MRT: the gradients in all
+    five times (shear, flux, bulk, even and odd ghosts) against central
+    differences (eps 1e-6) of the GPU forward."""
     from paper_1405_6162_amd.adjoint import binary_loss, rollout_binary
     n, T, K, eps = 24, 12, 5, 1e-6
     prm = O.Params(tau_f=MRT_TAUS[0])
@@ -250,7 +250,7 @@ def test_binary_mrt_rollout_central_differences_24(lbgpu):
             return binary_loss(*rollout_binary(dev(rho), dev(u), dev(phi), lat, T, K, tau_f=tt), 1.0).item()
     # FP64 rounding of the two losses bounds what a central difference resolves
     floor = 4.0 * np.finfo(np.float64).eps * abs(loss.item()) / eps
-    for k in (1, 2, 4):                              # flux, bulk, odd ghosts
+    for k in range(5):                               # shear, flux, bulk, even ghosts, odd ghosts
         tp, tm = list(MRT_TAUS), list(MRT_TAUS)
         tp[k] += eps
         tm[k] -= eps
