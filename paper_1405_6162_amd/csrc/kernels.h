@@ -468,8 +468,11 @@ __global__ __launch_bounds__(P::TPB) void k_binary_march(const S* __restrict__ f
     for (int z = z0; z < z1; ++z) {
         const int zn = wrap_plane(z + 1, geo.nz);
         const Site sc = site_wrapped(xw, yw, z, geo);
+        // every lane loads (a lane outside a ragged tile reads the periodic
+        // image of its coordinates, valid memory it never stores), so these
+        // loads share one basic block, and one wait, with the g loads below
         T fc[Q];
-        if (active) load_site<P, true>(fsrc, sc, geo, fc);
+        load_site<P, true>(fsrc, sc, geo, fc);
         T gn[Q];
         load_site<P, true>(gsrc, site_wrapped(xw, yw, zn, geo), geo, gn);
         ring[slot(z + 1)][ly][lx] = phi_sum<typename Accum<S>::T>(gn, cp.phi0);
