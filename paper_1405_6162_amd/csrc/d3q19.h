@@ -90,16 +90,27 @@ template <> struct Compute<_Float16> { using T = float; };
 template <class S> struct Accum { using T = typename Compute<S>::T; };
 
 
-// Lattice geometry.  Site offsets fit in 32 bits (N < 2^31 is checked on
-// the host); direction offsets (i * dstride) are 64-bit.  gx, gy, gz and
-// nblocks describe the tiling of the launch that receives this Geo.
+// Lattice geometry and the layout of the distribution arrays it addresses.
+// Element (i, x, y, z) of a distribution is at
+//     i * dstride + z * zs + y * ys + (x / 64) * xbs + x % 64.
+// Canonical (structure of arrays, x fastest): zs = nx * ny, ys = nx,
+// xbs = 64, dstride >= N, i.e. i * dstride + x + nx (y + ny z).  Blocked:
+// each run of 64 x-consecutive sites holds its 19 directions together,
+// dstride = 64, xbs = 19 * 64, ys = ceil(nx / 64) * xbs, zs = ny * ys, so the
+// 19 pulls of a wavefront land in one 19 * 64-element block per source row
+// instead of 19 arrays N elements apart.  Offsets fit in 32 bits (checked on
+// the host); i * dstride is formed in 64 bits.  Scalar fields (phi, moments,
+// inputs) are always canonical: site index x + nx (y + ny z) (canon_at).
+// gx, gy, gz and nblocks describe the tiling of the launch that receives
+// this Geo.
 struct Geo {
     int nx, ny, nz;
     uint32_t plane;     // nx * ny
     uint32_t nsite;     // nx * ny * nz
-    int64_t dstride;    // elements between consecutive direction arrays
+    int64_t dstride;    // elements between consecutive directions
     int gx, gy, gz;     // tiles along x, y and z
     int nblocks;        // gx * gy * gz: the 1-D grid size
+    uint32_t zs, ys, xbs;   // site-offset strides of the distribution layout
 };
 
 // Launch policy.  A block covers TX x TY x TZ sites; each lane owns one
@@ -203,9 +214,22 @@ __device__ __forceinline__ void stg(S* base, uint32_t off, S v) {
     else *p = v;
 }
 
-// Offset of the site s + (dx, dy, dz), each of dx, dy, dz in {-1, 0, 1}.
+// Offset, within one direction of a distribution in g's layout, of the site
+// s + (dx, dy, dz), each of dx, dy, dz in {-1, 0, 1}.  Everything is formed
+// from the coordinates and g's own strides, so one Site can address arrays
+// of different layouts (a source and a destination).
 template <int DX, int DY, int DZ>
 __device__ __forceinline__ uint32_t offset_at(const Site& s, const Geo& g) {
+    const uint32_t xx = (uint32_t)(DX == 0 ? s.x : (DX > 0 ? s.xp : s.xm));
+    const int yy = DY == 0 ? s.y : (DY > 0 ? s.yp : s.ym);
+    const int zz = DZ == 0 ? s.z : (DZ > 0 ? s.zp : s.zm);
+    return (uint32_t)zz * g.zs + (uint32_t)yy * g.ys + (xx >> 6) * g.xbs + (xx & 63u);
+}
+
+// Canonical site index x + nx (y + ny z) of s + (dx, dy, dz): the index of
+// scalar fields and of caller arrays.
+template <int DX, int DY, int DZ>
+__device__ __forceinline__ uint32_t canon_at(const Site& s, const Geo& g) {
     const int xx = DX == 0 ? s.x : (DX > 0 ? s.xp : s.xm);
     const int yy = DY == 0 ? s.y : (DY > 0 ? s.yp : s.ym);
     const int zz = DZ == 0 ? s.z : (DZ > 0 ? s.zp : s.zm);

@@ -152,7 +152,7 @@ __global__ __launch_bounds__(P::TPB) void k_phi(const S* __restrict__ g, typenam
             constexpr int i = decltype(I)::value;
             acc = acc + static_cast<A>(static_cast<T>(ldg<P::nt_load>(g + i * geo.dstride, src_offset<i, GATHER>(st, geo))));
         });
-        phi[offset_at<0, 0, 0>(st, geo)] = static_cast<T>(static_cast<A>(phi0) + acc);
+        phi[canon_at<0, 0, 0>(st, geo)] = static_cast<T>(static_cast<A>(phi0) + acc);
     }
 }
 
@@ -330,11 +330,11 @@ __global__ __launch_bounds__(P::TPB) void k_collide(const S* fsrc, const S* gsrc
     }
 }
 
-// Single-fluid collision from and into arrays of any direction stride (used
-// to record each step's post-collision field into caller memory).
+// Single-fluid collision from an array of one layout (geo) into an array of
+// another (dgeo), used to record each step's post-collision field into
+// canonical caller memory.
 template <class P, class S, bool GATHER, int COLL = COLL_BGK>
-__global__ __launch_bounds__(P::TPB) void k_collide_single_strided(const S* fsrc, int64_t src_stride, S* fdst,
-                                                                   int64_t dst_stride, Geo geo,
+__global__ __launch_bounds__(P::TPB) void k_collide_single_strided(const S* fsrc, S* fdst, Geo geo, Geo dgeo,
                                                                    CollParams<typename Compute<S>::T> cp) {
     using T = typename Compute<S>::T;
     const Column col = column_of_thread<P>(geo);
@@ -343,8 +343,8 @@ __global__ __launch_bounds__(P::TPB) void k_collide_single_strided(const S* fsrc
         const Site st = site_at(col, v, geo);
         if (!st.active) continue;
         T f[Q];
-        load_site<P, GATHER>(fsrc, st, geo, f, src_stride);
-        relax_single<P, COLL>(f, fdst, offset_at<0, 0, 0>(st, geo), geo, cp, dst_stride);
+        load_site<P, GATHER>(fsrc, st, geo, f);
+        relax_single<P, COLL>(f, fdst, offset_at<0, 0, 0>(st, dgeo), dgeo, cp);
     }
 }
 
@@ -456,7 +456,7 @@ __global__ __launch_bounds__(P::TPB) void k_binary_march(const S* __restrict__ f
         load_site<P, true>(gsrc, s0, geo, gc);
         ring[slot(z0)][ly][lx] = phi_sum<typename Accum<S>::T>(gc, cp.phi0);
         if constexpr (PHI_OUT)
-            if (active) phi_out[offset_at<0, 0, 0>(s0, geo)] = ring[slot(z0)][ly][lx];
+            if (active) phi_out[canon_at<0, 0, 0>(s0, geo)] = ring[slot(z0)][ly][lx];
         if constexpr (GLDS) {
 #pragma unroll
             for (int i = 0; i < Q; ++i) gkeep[i][threadIdx.x] = gc[i];
@@ -477,7 +477,7 @@ __global__ __launch_bounds__(P::TPB) void k_binary_march(const S* __restrict__ f
         load_site<P, true>(gsrc, site_wrapped(xw, yw, zn, geo), geo, gn);
         ring[slot(z + 1)][ly][lx] = phi_sum<typename Accum<S>::T>(gn, cp.phi0);
         if constexpr (PHI_OUT)
-            if (active && z + 1 < z1) phi_out[offset_at<0, 0, 0>(site_wrapped(xw, yw, zn, geo), geo)] =
+            if (active && z + 1 < z1) phi_out[canon_at<0, 0, 0>(site_wrapped(xw, yw, zn, geo), geo)] =
                 ring[slot(z + 1)][ly][lx];
         if (has_halo)
             ring[slot(z + 1)][hly][hlx] = phi_of_gathered<P>(gsrc, site_wrapped(hx, hy, zn, geo), geo, cp.phi0);
@@ -511,23 +511,25 @@ __global__ __launch_bounds__(P::TPB) void k_binary_march(const S* __restrict__ f
 }
 
 // ---------------------------------------------------------------------------
-// Stand-alone propagation (pull): dst_i(s) = src_i(s - c_i).  Also used to
-// materialise a pending buffer into caller memory of another stride.
+// Stand-alone propagation (pull, GATHER): dst_i(s) = src_i(s - c_i), or a
+// plain copy (no GATHER): dst_i(s) = src_i(s).  The source is addressed with
+// geo's layout and the destination with dgeo's, so the same kernels move a
+// state between the context's layout and canonical caller memory.
 // ---------------------------------------------------------------------------
 
-template <class P, class S>
+template <class P, class S, bool GATHER = true>
 __global__ __launch_bounds__(P::TPB) void k_stream(const S* __restrict__ src, S* __restrict__ dst, Geo geo,
-                                                   int64_t dst_stride) {
+                                                   Geo dgeo) {
     const Column col = column_of_thread<P>(geo);
 #pragma unroll
     for (int v = 0; v < P::TZ; ++v) {
         const Site st = site_at(col, v, geo);
         if (!st.active) continue;
-        const uint32_t off = offset_at<0, 0, 0>(st, geo);
+        const uint32_t off = offset_at<0, 0, 0>(st, dgeo);
         static_for<0, Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            stg<P::nt_store>(dst + i * dst_stride, off,
-                             ldg<P::nt_load>(src + i * geo.dstride, src_offset<i, true>(st, geo)));
+            stg<P::nt_store>(dst + i * dgeo.dstride, off,
+                             ldg<P::nt_load>(src + i * geo.dstride, src_offset<i, GATHER>(st, geo)));
         });
     }
 }
@@ -536,23 +538,23 @@ __global__ __launch_bounds__(P::TPB) void k_stream(const S* __restrict__ src, S*
 // stores per site, the memory traffic of the binary step without its
 // arithmetic (what the step's access pattern can reach on this memory
 // system), and one launch instead of two for lb_propagate.
-template <class P, class S>
+template <class P, class S, bool GATHER = true>
 __global__ __launch_bounds__(P::TPB) void k_stream2(const S* __restrict__ fsrc, const S* __restrict__ gsrc,
                                                     S* __restrict__ fdst, S* __restrict__ gdst, Geo geo,
-                                                    int64_t dst_stride) {
+                                                    Geo dgeo) {
     const Column col = column_of_thread<P>(geo);
 #pragma unroll
     for (int v = 0; v < P::TZ; ++v) {
         const Site st = site_at(col, v, geo);
         if (!st.active) continue;
-        const uint32_t off = offset_at<0, 0, 0>(st, geo);
+        const uint32_t off = offset_at<0, 0, 0>(st, dgeo);
         static_for<0, Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            const uint32_t up = src_offset<i, true>(st, geo);
+            const uint32_t up = src_offset<i, GATHER>(st, geo);
             const S fv = ldg<P::nt_load>(fsrc + i * geo.dstride, up);
             const S gv = ldg<P::nt_load>(gsrc + i * geo.dstride, up);
-            stg<P::nt_store>(fdst + i * dst_stride, off, fv);
-            stg<P::nt_store>(gdst + i * dst_stride, off, gv);
+            stg<P::nt_store>(fdst + i * dgeo.dstride, off, fv);
+            stg<P::nt_store>(gdst + i * dgeo.dstride, off, gv);
         });
     }
 }
@@ -570,15 +572,16 @@ __global__ __launch_bounds__(P::TPB) void k_init(const double* __restrict__ rho_
         const Site st = site_at(col, v, geo);
         if (!st.active) continue;
         const uint32_t off = offset_at<0, 0, 0>(st, geo);
-        const double rho = rho_in[off];
-        const double ux = u_in[off], uy = u_in[geo.nsite + off], uz = u_in[2 * (size_t)geo.nsite + off];
+        const uint32_t sc = canon_at<0, 0, 0>(st, geo);
+        const double rho = rho_in[sc];
+        const double ux = u_in[sc], uy = u_in[geo.nsite + sc], uz = u_in[2 * (size_t)geo.nsite + sc];
         const double usq = ux * ux + uy * uy + uz * uz;
         const double drho = rho - cp.rho0;
         if constexpr (MODEL == MODEL_BINARY) {
-            const double p = phi_in[off];
-            const double pxm = phi_in[offset_at<-1, 0, 0>(st, geo)], pxp = phi_in[offset_at<1, 0, 0>(st, geo)];
-            const double pym = phi_in[offset_at<0, -1, 0>(st, geo)], pyp = phi_in[offset_at<0, 1, 0>(st, geo)];
-            const double pzm = phi_in[offset_at<0, 0, -1>(st, geo)], pzp = phi_in[offset_at<0, 0, 1>(st, geo)];
+            const double p = phi_in[sc];
+            const double pxm = phi_in[canon_at<-1, 0, 0>(st, geo)], pxp = phi_in[canon_at<1, 0, 0>(st, geo)];
+            const double pym = phi_in[canon_at<0, -1, 0>(st, geo)], pyp = phi_in[canon_at<0, 1, 0>(st, geo)];
+            const double pzm = phi_in[canon_at<0, 0, -1>(st, geo)], pzp = phi_in[canon_at<0, 0, 1>(st, geo)];
             const double lap = (pxp + pxm) + (pyp + pym) + (pzp + pzm) - 6.0 * p;
             const FreeEnergy<double> fe(p, 0.5 * (pxp - pxm), 0.5 * (pyp - pym), 0.5 * (pzp - pzm), lap, cp);
             const double dphi = p - cp.phi0;
@@ -615,7 +618,7 @@ __global__ __launch_bounds__(P::TPB) void k_moments(const S* __restrict__ f, con
     for (int v = 0; v < P::TZ; ++v) {
         const Site st = site_at(col, v, geo);
         if (!st.active) continue;
-        const uint32_t off = offset_at<0, 0, 0>(st, geo);
+        const uint32_t off = canon_at<0, 0, 0>(st, geo);
         double fv[Q];
         static_for<0, Q>([&](auto I) {
             constexpr int i = decltype(I)::value;

@@ -65,7 +65,9 @@ size_t compute_size(int storage) { return storage == LB_F64 ? 8 : 4; }
 
 struct Layout {
     int64_t nsite;
-    int64_t dstride;        // elements
+    int64_t dstride;        // elements between consecutive directions
+    bool blocked;           // 64-site blocks holding their 19 directions together
+    uint32_t zs, ys, xbs;   // site-offset strides (Geo)
     size_t dist_bytes;      // one 19-direction buffer
     size_t phi_bytes;
     int nblocks;
@@ -104,9 +106,30 @@ Layout layout_of(const lb_params* p) {
     Layout L{};
     L.nsite = (int64_t)p->nx * p->ny * p->nz;
     const size_t es = storage_size(p->storage);
-    const size_t stride_bytes = round_up((size_t)L.nsite * es, kAlign) + kDirPadBytes;
-    L.dstride = (int64_t)(stride_bytes / es);
-    L.dist_bytes = round_up(stride_bytes * Q, kAlign);
+    // Blocked layout (see Geo) whenever a buffer's offsets fit in 32 bits;
+    // the last x block of a row is padded to 64 sites.  Measured A/B on one
+    // box against the structure-of-arrays layout: the single-fluid step
+    // +4.6% (FP64) and +5.6% (FP32) at 256^3, the binary march +4.3% (FP64,
+    // 256^3), +3.0% (FP64, 128^3) and +3.6% (FP16, 384^3), but the binary
+    // FP32 march -3.2% at 256^3 (padding between the buffers changed none of
+    // these), so binary FP32 states stay structure-of-arrays.
+    const uint64_t xblocks = (uint64_t)tiles(p->nx, 64);
+    const uint64_t blocked_elems = (uint64_t)p->nz * (uint64_t)p->ny * xblocks * Q * 64;
+    L.blocked = blocked_elems * es < ((uint64_t)1 << 32) && !(p->model == LB_BINARY && p->storage == LB_F32);
+    if (L.blocked) {
+        L.dstride = 64;
+        L.xbs = Q * 64;
+        L.ys = (uint32_t)(xblocks * L.xbs);
+        L.zs = (uint32_t)((uint64_t)p->ny * L.ys);
+        L.dist_bytes = round_up((size_t)blocked_elems * es, kAlign);
+    } else {
+        const size_t stride_bytes = round_up((size_t)L.nsite * es, kAlign) + kDirPadBytes;
+        L.dstride = (int64_t)(stride_bytes / es);
+        L.xbs = 64;
+        L.ys = (uint32_t)p->nx;
+        L.zs = (uint32_t)p->nx * (uint32_t)p->ny;
+        L.dist_bytes = round_up(stride_bytes * Q, kAlign);
+    }
     L.phi_bytes = round_up((size_t)L.nsite * compute_size(p->storage), kAlign);
     L.nblocks = tiles(p->nx, Pol::TX) * tiles(p->ny, Pol::TY) * tiles(p->nz, Pol::TZ);
     L.partial_bytes = round_up((size_t)L.nblocks * 16 * sizeof(double), kAlign);
@@ -178,9 +201,16 @@ struct lb_ctx {
         g.gy = tiles(p.ny, Pol::TY);
         g.gz = tiles(p.nz, Pol::TZ);
         g.nblocks = g.gx * g.gy * g.gz;
+        g.zs = L.zs; g.ys = L.ys; g.xbs = L.xbs;
         return g;
     }
-    Geo canonical_geo() const { Geo g = geo(); g.dstride = L.nsite; return g; }
+    // g with the layout of canonical caller arrays: direction stride N, x fastest
+    Geo canonical(Geo g) const {
+        g.dstride = L.nsite;
+        g.zs = g.plane; g.ys = (uint32_t)p.nx; g.xbs = 64;
+        return g;
+    }
+    Geo canonical_geo() const { return canonical(geo()); }
     template <class P>
     Geo geo_for() const {
         Geo g = geo();
@@ -390,15 +420,26 @@ int run_collide(lb_ctx* c) {
     return LB_OK;
 }
 
-// Materialise propagate(buffer[src]) into (f, g) of the given stride.
+// Materialise propagate(buffer[src]) into (f, g) of layout dgeo.
 template <class S>
-int run_stream_into(lb_ctx* c, int src, S* f, S* g, int64_t stride) {
+int run_stream_into(lb_ctx* c, int src, S* f, S* g, const Geo& dgeo) {
     Timed t(c, LB_K_STREAM);
     if (c->p.model == LB_BINARY)
         k_stream2<Pol, S><<<c->grid(), c->block(), 0, c->stream>>>((const S*)c->fbuf(src), (const S*)c->gbuf(src), f,
-                                                                   g, c->geo(), stride);
+                                                                   g, c->geo(), dgeo);
     else
-        k_stream<Pol, S><<<c->grid(), c->block(), 0, c->stream>>>((const S*)c->fbuf(src), f, c->geo(), stride);
+        k_stream<Pol, S><<<c->grid(), c->block(), 0, c->stream>>>((const S*)c->fbuf(src), f, c->geo(), dgeo);
+    return launch_status();
+}
+
+// Copy a state (f, and g for the binary model) from layout sgeo to layout
+// dgeo, site by site (the context's layout <-> canonical caller memory).
+template <class S>
+int run_convert(lb_ctx* c, const S* fs, const S* gs, S* fd, S* gd, const Geo& sgeo, const Geo& dgeo) {
+    if (c->p.model == LB_BINARY)
+        k_stream2<Pol, S, false><<<c->grid(), c->block(), 0, c->stream>>>(fs, gs, fd, gd, sgeo, dgeo);
+    else
+        k_stream<Pol, S, false><<<c->grid(), c->block(), 0, c->stream>>>(fs, fd, sgeo, dgeo);
     return launch_status();
 }
 
@@ -406,7 +447,7 @@ template <class S>
 int run_propagate(lb_ctx* c) {
     if (!c->pending) { c->pending = true; return LB_OK; }   // propagation of a direct buffer is deferred
     const int dst = 1 - c->cur;
-    int rc = run_stream_into<S>(c, c->cur, (S*)c->fbuf(dst), (S*)c->gbuf(dst), c->L.dstride);
+    int rc = run_stream_into<S>(c, c->cur, (S*)c->fbuf(dst), (S*)c->gbuf(dst), c->geo());
     if (rc) return rc;
     c->cur = dst;
     return LB_OK;
@@ -475,28 +516,17 @@ int run_sums(lb_ctx* c, double* out) {
 
 template <class S>
 int run_get_state(lb_ctx* c, S* f, S* g) {
-    const int64_t n = c->L.nsite;
-    if (c->pending) return run_stream_into<S>(c, c->cur, f, g, n);
+    if (c->pending) return run_stream_into<S>(c, c->cur, f, g, c->canonical_geo());
     Timed t(c, LB_K_OTHER);
-    const size_t w = (size_t)n * sizeof(S), sp = (size_t)c->L.dstride * sizeof(S);
-    if (hipMemcpy2DAsync(f, w, c->fbuf(c->cur), sp, w, Q, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
-        return LB_EDEVICE;
-    if (c->p.model == LB_BINARY &&
-        hipMemcpy2DAsync(g, w, c->gbuf(c->cur), sp, w, Q, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
-        return LB_EDEVICE;
-    return LB_OK;
+    return run_convert<S>(c, (const S*)c->fbuf(c->cur), (const S*)c->gbuf(c->cur), f, g, c->geo(),
+                          c->canonical_geo());
 }
 
 template <class S>
 int run_set_state(lb_ctx* c, const S* f, const S* g) {
     Timed t(c, LB_K_OTHER);
-    const int64_t n = c->L.nsite;
-    const size_t w = (size_t)n * sizeof(S), sp = (size_t)c->L.dstride * sizeof(S);
-    if (hipMemcpy2DAsync(c->fbuf(c->cur), sp, f, w, w, Q, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
-        return LB_EDEVICE;
-    if (c->p.model == LB_BINARY &&
-        hipMemcpy2DAsync(c->gbuf(c->cur), sp, g, w, w, Q, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
-        return LB_EDEVICE;
+    const int rc = run_convert<S>(c, f, g, (S*)c->fbuf(c->cur), (S*)c->gbuf(c->cur), c->canonical_geo(), c->geo());
+    if (rc) return rc;
     c->pending = false;
     return LB_OK;
 }
@@ -510,7 +540,6 @@ template <class S>
 int run_step_record_binary(lb_ctx* c, int32_t n, S* post, typename Compute<S>::T* phi) {
     using T = typename Compute<S>::T;
     const int64_t N = c->L.nsite;
-    const size_t w = (size_t)N * sizeof(S), sp = (size_t)c->L.dstride * sizeof(S);
     const auto cp = coll_params<S>(c);
     if (phi) {                                        // phi of the state step 0 collides
         Timed t(c, LB_K_PHI);
@@ -522,16 +551,14 @@ int run_step_record_binary(lb_ctx* c, int32_t n, S* post, typename Compute<S>::T
     if (rc) return rc;
     {
         Timed t(c, LB_K_OTHER);
-        if (hipMemcpy2DAsync(post, w, c->fbuf(c->cur), sp, w, Q, hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
-            hipMemcpy2DAsync(post + Q * N, w, c->gbuf(c->cur), sp, w, Q, hipMemcpyDeviceToDevice, c->stream) !=
-                hipSuccess)
-            return LB_EDEVICE;
+        rc = run_convert<S>(c, (const S*)c->fbuf(c->cur), (const S*)c->gbuf(c->cur), post, post + Q * N, c->geo(),
+                            c->canonical_geo());
+        if (rc) return rc;
     }
     c->pending = true;
     using MP = typename March<S>::P;
     constexpr int BZ = March<S>::bz;
-    Geo g = c->template march_geo<MP, BZ>();
-    g.dstride = N;
+    const Geo g = c->canonical(c->template march_geo<MP, BZ>());
     const bool march = march_pays<S>(c);
     Geo cg = c->canonical_geo();
     for (int32_t k = 1; k < n; ++k) {
@@ -582,10 +609,9 @@ int run_step_record_binary(lb_ctx* c, int32_t n, S* post, typename Compute<S>::T
     if (n > 1) {
         Timed t(c, LB_K_OTHER);
         const S* last = post + (size_t)(n - 1) * 2 * Q * N;
-        if (hipMemcpy2DAsync(c->fbuf(c->cur), sp, last, w, w, Q, hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
-            hipMemcpy2DAsync(c->gbuf(c->cur), sp, last + Q * N, w, w, Q, hipMemcpyDeviceToDevice, c->stream) !=
-                hipSuccess)
-            return LB_EDEVICE;
+        rc = run_convert<S>(c, last, last + Q * N, (S*)c->fbuf(c->cur), (S*)c->gbuf(c->cur), c->canonical_geo(),
+                            c->geo());
+        if (rc) return rc;
     }
     return LB_OK;
 }
@@ -596,17 +622,17 @@ int run_step_record(lb_ctx* c, int32_t n, S* post, typename Compute<S>::T* phi) 
     const int64_t N = c->L.nsite;
     const auto cp = coll_params<S>(c);
     const dim3 grid = c->grid(), block = c->block();
-    // one strided collision (pull from a pending src when GATHER), for the context's collision
-    auto collide = [&](auto gather, const S* src, int64_t src_stride, S* dst) {
+    // one collision from src (layout sg; pull from a pending src when GATHER)
+    // into canonical dst, for the context's collision
+    const Geo cg = c->canonical_geo();
+    auto collide = [&](auto gather, const S* src, const Geo& sg, S* dst) {
         constexpr bool G = decltype(gather)::value;
         if (c->p.collision == LB_TRT)
-            k_collide_single_strided<Pol, S, G, COLL_TRT><<<grid, block, 0, c->stream>>>(src, src_stride, dst, N,
-                                                                                         c->geo(), cp);
+            k_collide_single_strided<Pol, S, G, COLL_TRT><<<grid, block, 0, c->stream>>>(src, dst, sg, cg, cp);
         else if (c->p.collision == LB_MRT)
-            k_collide_single_strided<Pol, S, G, COLL_MRT><<<grid, block, 0, c->stream>>>(src, src_stride, dst, N,
-                                                                                         c->geo(), cp);
+            k_collide_single_strided<Pol, S, G, COLL_MRT><<<grid, block, 0, c->stream>>>(src, dst, sg, cg, cp);
         else
-            k_collide_single_strided<Pol, S, G><<<grid, block, 0, c->stream>>>(src, src_stride, dst, N, c->geo(), cp);
+            k_collide_single_strided<Pol, S, G><<<grid, block, 0, c->stream>>>(src, dst, sg, cg, cp);
     };
     for (int32_t k = 0; k < n; ++k) {
         S* dst = post + (size_t)k * Q * N;
@@ -614,20 +640,19 @@ int run_step_record(lb_ctx* c, int32_t n, S* post, typename Compute<S>::T* phi) 
             Timed t(c, LB_K_COLLIDE);
             if (k == 0) {
                 const S* src = (const S*)c->fbuf(c->cur);
-                if (c->pending) collide(std::true_type{}, src, c->L.dstride, dst);
-                else collide(std::false_type{}, src, c->L.dstride, dst);
+                if (c->pending) collide(std::true_type{}, src, c->geo(), dst);
+                else collide(std::false_type{}, src, c->geo(), dst);
             } else {
-                collide(std::true_type{}, post + (size_t)(k - 1) * Q * N, N, dst);
+                collide(std::true_type{}, post + (size_t)(k - 1) * Q * N, cg, dst);
             }
         }
         int rc = launch_status();
         if (rc) return rc;
     }
     Timed t(c, LB_K_OTHER);
-    const size_t w = (size_t)N * sizeof(S), sp = (size_t)c->L.dstride * sizeof(S);
-    if (hipMemcpy2DAsync(c->fbuf(c->cur), sp, post + (size_t)(n - 1) * Q * N, w, w, Q, hipMemcpyDeviceToDevice,
-                         c->stream) != hipSuccess)
-        return LB_EDEVICE;
+    const int rc = run_convert<S>(c, post + (size_t)(n - 1) * Q * N, nullptr, (S*)c->fbuf(c->cur), nullptr, cg,
+                                  c->geo());
+    if (rc) return rc;
     c->pending = true;
     return LB_OK;
 }
@@ -867,6 +892,7 @@ int lb_conserved_sums_noalloc(const lb_params* p, const void* f, const void* g, 
     geo.plane = (uint32_t)p->nx * (uint32_t)p->ny;
     geo.nsite = geo.plane * (uint32_t)p->nz;
     geo.dstride = geo.nsite;
+    geo.zs = geo.plane; geo.ys = (uint32_t)p->nx; geo.xbs = 64;
     geo.gx = tiles(p->nx, Pol::TX);
     geo.gy = tiles(p->ny, Pol::TY);
     geo.gz = tiles(p->nz, Pol::TZ);
@@ -982,7 +1008,7 @@ int lb_adjoint_step_binary(lb_ctx* c, const double* f, const double* g, const do
     const Geo geo = c->canonical_geo();
     const auto cp = coll_params<double>(c);
     const double* phi = phi_n;
-    double* afield = (double*)c->fbuf(1 - c->cur);       // spare state buffer: 19 dstride >= 5 N doubles
+    double* afield = (double*)c->fbuf(1 - c->cur);       // spare state buffer: >= 19 N doubles, 5 N used
     if (!phi) {
         Timed t(c, LB_K_ADJOINT);
         double* p = (double*)c->phi();
@@ -1090,7 +1116,7 @@ int lb_adjoint_segment_binary(lb_ctx* c, const double* f0, const double* g0, con
     c->launched = true;
     const Geo geo = c->canonical_geo();
     const auto cp = coll_params<double>(c);
-    double* afield = (double*)c->fbuf(1 - c->cur);   // spare state buffer: 19 dstride >= 6 N doubles
+    double* afield = (double*)c->fbuf(1 - c->cur);   // spare state buffer: >= 19 N doubles, 6 N used
     double* bfield = afield + 5 * N;
     double* lf_cur = lf;                              // lambda_f^{n+1}
     double* lf_nxt = work;
