@@ -384,15 +384,14 @@ __device__ __forceinline__ int wrap_plane(int z, int nz) {
     return z < 0 ? z + nz : (z >= nz ? z - nz : z);
 }
 
+// phi of the pulled g at st: the 19 values are loaded into registers first
+// and then summed (in k_phi's order), so the loads go out as one batch
+// rather than one at a time behind the running sum.
 template <class P, class S, class T>
 __device__ __forceinline__ T phi_of_gathered(const S* g, const Site& st, const Geo& geo, T phi0) {
-    using A = typename Accum<S>::T;
-    A acc = A(0);
-    static_for<0, Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        acc = acc + static_cast<A>(static_cast<T>(ldg<P::nt_load>(g + i * geo.dstride, src_offset<i, true>(st, geo))));
-    });
-    return static_cast<T>(static_cast<A>(phi0) + acc);
+    T v[Q];
+    load_site<P, true>(g, st, geo, v);
+    return phi_sum<typename Accum<S>::T>(v, phi0);
 }
 
 // With GLDS the 19 pulled g of the next plane wait in LDS (each lane only
@@ -403,12 +402,19 @@ __device__ __forceinline__ T phi_of_gathered(const S* g, const Site& st, const G
 // next is never one still being read, so one barrier per plane suffices.
 // With PHI_OUT the kernel also stores the phi it computes for its own sites
 // (phi_out[s], canonical), i.e. phi of the state this step collides.
-template <class P, int BZ, class S, bool GLDS, int RING = 3, bool PHI_OUT = false, int COLL = COLL_BGK>
+// BLK: the arrays are in the blocked layout, whose direction stride (64
+// elements) is then a compile-time constant: every direction of a site is
+// one address plus an immediate offset, and a site's loads need one 64-bit
+// address instead of one per direction.
+template <class P, int BZ, class S, bool GLDS, int RING = 3, bool PHI_OUT = false, int COLL = COLL_BGK,
+          bool BLK = false>
 __global__ __launch_bounds__(P::TPB) void k_binary_march(const S* __restrict__ fsrc, const S* __restrict__ gsrc,
-                                                         S* __restrict__ fdst, S* __restrict__ gdst, Geo geo,
+                                                         S* __restrict__ fdst, S* __restrict__ gdst, Geo geo_in,
                                                          CollParams<typename Compute<S>::T> cp,
                                                          typename Compute<S>::T* __restrict__ phi_out = nullptr) {
     using T = typename Compute<S>::T;
+    Geo geo = geo_in;
+    if constexpr (BLK) geo.dstride = 64;
     constexpr int TX = P::TX, TY = P::TY, LX = TX + 2, LY = TY + 2;
     constexpr int NHALO = 2 * TX + 2 * TY;
     static_assert(NHALO <= P::TPB, "one halo site per lane");

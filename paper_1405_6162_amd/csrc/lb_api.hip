@@ -343,12 +343,19 @@ int run_binary_march(lb_ctx* c) {
         const S* gs = (const S*)c->gbuf(src);
         S* fd = (S*)c->fbuf(dst);
         S* gd = (S*)c->gbuf(dst);
-        if (c->p.collision == LB_TRT)
-            k_binary_march<MP, BZ, S, March<S>::glds, 3, false, COLL_TRT><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd, g, cp);
-        else if (c->p.collision == LB_MRT)
-            k_binary_march<MP, BZ, S, March<S>::glds, 3, false, COLL_MRT><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd, g, cp);
-        else
-            k_binary_march<MP, BZ, S, March<S>::glds><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd, g, cp);
+        auto go = [&](auto coll, auto blk) {
+            constexpr int COLL = decltype(coll)::value;
+            constexpr bool BLK = decltype(blk)::value;
+            k_binary_march<MP, BZ, S, March<S>::glds, 3, false, COLL, BLK><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd,
+                                                                                                         g, cp);
+        };
+        auto by_coll = [&](auto blk) {
+            if (c->p.collision == LB_TRT) go(std::integral_constant<int, COLL_TRT>{}, blk);
+            else if (c->p.collision == LB_MRT) go(std::integral_constant<int, COLL_MRT>{}, blk);
+            else go(std::integral_constant<int, COLL_BGK>{}, blk);
+        };
+        if (c->L.blocked) by_coll(std::true_type{});
+        else by_coll(std::false_type{});
     }
     int rc = launch_status();
     if (rc) return rc;
