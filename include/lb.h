@@ -95,8 +95,9 @@ extern "C" {
  * LB_STEP_TWO_PASS: a phi pass, then the fused collide (776 B/site), every
  * site in parallel: fastest on small lattices, where the march has too few
  * blocks to hide its per-plane latency.  LB_STEP_AUTO (0, the default): the
- * march when its grid has at least 400 blocks (64 x 4 tiles, 16-plane chunks;
- * 128^3 has 512), else the two-pass step. */
+ * march when its grid has at least 256 blocks (64 x 8 tiles, chunks of 16
+ * planes, or 32 where that still gives 400 blocks; 128^3 has 256), else the
+ * two-pass step. */
 #define LB_STEP_AUTO     0
 #define LB_STEP_MARCH    1
 #define LB_STEP_TWO_PASS 2

@@ -111,6 +111,7 @@ struct Geo {
     int gx, gy, gz;     // tiles along x, y and z
     int nblocks;        // gx * gy * gz: the 1-D grid size
     uint32_t zs, ys, xbs;   // site-offset strides of the distribution layout
+    int bz;             // z planes per block of the single-pass march (its chunk depth)
 };
 
 // Launch policy.  A block covers TX x TY x TZ sites; each lane owns one

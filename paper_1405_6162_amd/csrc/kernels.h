@@ -350,7 +350,7 @@ __global__ __launch_bounds__(P::TPB) void k_collide_single_strided(const S* fsrc
 
 // ---------------------------------------------------------------------------
 // Single-pass binary step: fused pull-stream + collision that computes phi
-// itself.  A block owns a TX x TY column tile and marches through BZ
+// itself.  A block owns a TX x TY column tile and marches through geo.bz
 // consecutive z planes.  phi(s) = phi0 + sum_i e_i(s - c_i) needs the pulled
 // g of s, which the collision of s needs anyway: each lane gathers g for
 // plane z+1, sums it into the plane's phi tile in LDS and keeps the 19 values
@@ -406,8 +406,7 @@ __device__ __forceinline__ T phi_of_gathered(const S* g, const Site& st, const G
 // elements) is then a compile-time constant: every direction of a site is
 // one address plus an immediate offset, and a site's loads need one 64-bit
 // address instead of one per direction.
-template <class P, int BZ, class S, bool GLDS, int RING = 3, bool PHI_OUT = false, int COLL = COLL_BGK,
-          bool BLK = false>
+template <class P, class S, bool GLDS, int RING = 3, bool PHI_OUT = false, int COLL = COLL_BGK, bool BLK = false>
 __global__ __launch_bounds__(P::TPB) void k_binary_march(const S* __restrict__ fsrc, const S* __restrict__ gsrc,
                                                          S* __restrict__ fdst, S* __restrict__ gdst, Geo geo_in,
                                                          CollParams<typename Compute<S>::T> cp,
@@ -426,8 +425,8 @@ __global__ __launch_bounds__(P::TPB) void k_binary_march(const S* __restrict__ f
     const int bx = b % geo.gx;
     const int t = b / geo.gx;
     const int by = t % geo.gy;
-    const int z0 = (t / geo.gy) * BZ;
-    const int z1 = min(z0 + BZ, geo.nz);
+    const int z0 = (t / geo.gy) * geo.bz;
+    const int z1 = min(z0 + geo.bz, geo.nz);
     const int x0 = bx * TX, y0 = by * TY;
     const int tx = (int)(threadIdx.x % TX), ty = (int)(threadIdx.x / TX);
     const bool active = (x0 + tx < geo.nx) && (y0 + ty < geo.ny);

@@ -29,27 +29,36 @@ using Pol = Tiling<64, 4, 1, false, true, true>;
 // The same with 2 and 4 sites per lane along z (lb_params.vvl).
 using Pol2 = Tiling<64, 4, 2, false, true, true>;
 using Pol4 = Tiling<64, 4, 4, false, true, true>;
-// Single-pass binary step (k_binary_march), per storage type: the tile, the
-// planes per block (the chunk's first and last plane cost one extra plane of
-// phi each, while shorter chunks give more blocks to fill the CUs) and
-// whether the next plane's g waits in LDS (lower register pressure) or in
-// registers; chosen by sweeps on 128^3, 256^3 and 384^3.
+// Single-pass binary step (k_binary_march), per storage type: the tile and
+// whether the next plane's g waits in LDS or in registers.  A 64 x 8 tile
+// has 144 halo sites per 512 against 136 per 256 for 64 x 4, so the halo's
+// phi gathers (mostly re-reads of neighbouring tiles' g) fall from 53% to
+// 28% of the sites gathered: measured A/B on one box, 64 x 8 is 6.5% faster
+// than 64 x 4 in FP64 at 256^3, 2% at 128^3, 3% in FP32 and 1% in FP16;
+// 64 x 16 and 32 x 16 were slower in every storage.  g waits in registers
+// in FP64 (1% faster than LDS at 256^3) and FP32, in LDS in FP16 (30%
+// faster than registers at 384^3).
 template <class S> struct March;
 template <> struct March<double> {
-    using P = Tiling<64, 4, 1, false, true, true>;
-    static constexpr int bz = 16;
-    static constexpr bool glds = true;
+    using P = Tiling<64, 8, 1, false, true, true>;
+    static constexpr bool glds = false;
 };
 template <> struct March<float> {
-    using P = Tiling<64, 4, 1, false, true, true>;
-    static constexpr int bz = 16;
+    using P = Tiling<64, 8, 1, false, true, true>;
     static constexpr bool glds = false;
 };
 template <> struct March<_Float16> {
-    using P = Tiling<64, 4, 1, false, true, true>;
-    static constexpr int bz = 16;
-    static constexpr bool glds = true;      // measured +2% over registers at 384^3
+    using P = Tiling<64, 8, 1, false, true, true>;
+    static constexpr bool glds = true;
 };
+// Chunk depth of the march: each chunk's first and last plane cost one
+// extra plane of phi (2/bz more g reads), while deeper chunks leave fewer
+// blocks to fill the CUs.  32 planes where that still gives
+// kMarchDeepBlocks blocks, else 16.  Measured A/B on one box (FP64): 32
+// planes 3% faster at 192^3 (432 blocks), 1.6% at 256^3, 1% at 320^3, but
+// 18% slower at 160^3 (300 blocks); FP32 1% faster at 192^3 and 256^3, FP16
+// equal within 1%.
+constexpr int kMarchDeepBlocks = 400;
 
 constexpr size_t kAlign = 4096;
 // Extra bytes between consecutive direction arrays, so the 19 (38) streams of
@@ -110,12 +119,12 @@ Layout layout_of(const lb_params* p) {
     // the last x block of a row is padded to 64 sites.  Measured A/B on one
     // box against the structure-of-arrays layout: the single-fluid step
     // +4.6% (FP64) and +5.6% (FP32) at 256^3, the binary march +4.3% (FP64,
-    // 256^3), +3.0% (FP64, 128^3) and +3.6% (FP16, 384^3), but the binary
-    // FP32 march -3.2% at 256^3 (padding between the buffers changed none of
-    // these), so binary FP32 states stay structure-of-arrays.
+    // 256^3), +3.0% (FP64, 128^3), +3.6% (FP16, 384^3) and +2.5 to +5.6%
+    // (FP32, 128^3 to 256^3); padding between the buffers changed none of
+    // these.
     const uint64_t xblocks = (uint64_t)tiles(p->nx, 64);
     const uint64_t blocked_elems = (uint64_t)p->nz * (uint64_t)p->ny * xblocks * Q * 64;
-    L.blocked = blocked_elems * es < ((uint64_t)1 << 32) && !(p->model == LB_BINARY && p->storage == LB_F32);
+    L.blocked = blocked_elems * es < ((uint64_t)1 << 32);
     if (L.blocked) {
         L.dstride = 64;
         L.xbs = Q * 64;
@@ -202,6 +211,7 @@ struct lb_ctx {
         g.gz = tiles(p.nz, Pol::TZ);
         g.nblocks = g.gx * g.gy * g.gz;
         g.zs = L.zs; g.ys = L.ys; g.xbs = L.xbs;
+        g.bz = Pol::TZ;
         return g;
     }
     // g with the layout of canonical caller arrays: direction stride N, x fastest
@@ -218,12 +228,13 @@ struct lb_ctx {
         g.nblocks = g.gx * g.gy * g.gz;
         return g;
     }
-    template <class MP, int BZ>
+    template <class MP>
     Geo march_geo() const {
         Geo g = geo();
         g.gx = tiles(p.nx, MP::TX);
         g.gy = tiles(p.ny, MP::TY);
-        g.gz = tiles(p.nz, BZ);
+        g.bz = g.gx * g.gy * tiles(p.nz, 32) >= kMarchDeepBlocks ? 32 : 16;
+        g.gz = tiles(p.nz, g.bz);
         g.nblocks = g.gx * g.gy * g.gz;
         return g;
     }
@@ -334,8 +345,7 @@ int run_binary_march(lb_ctx* c) {
     using MP = typename March<S>::P;
     const auto cp = coll_params<S>(c);
     const int src = c->cur, dst = 1 - c->cur;
-    constexpr int BZ = March<S>::bz;
-    const Geo g = c->template march_geo<MP, BZ>();
+    const Geo g = c->template march_geo<MP>();
     {
         Timed t(c, LB_K_COLLIDE);
         const dim3 grid(g.nblocks), block(MP::TPB);
@@ -346,8 +356,7 @@ int run_binary_march(lb_ctx* c) {
         auto go = [&](auto coll, auto blk) {
             constexpr int COLL = decltype(coll)::value;
             constexpr bool BLK = decltype(blk)::value;
-            k_binary_march<MP, BZ, S, March<S>::glds, 3, false, COLL, BLK><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd,
-                                                                                                         g, cp);
+            k_binary_march<MP, S, March<S>::glds, 3, false, COLL, BLK><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd, g, cp);
         };
         auto by_coll = [&](auto blk) {
             if (c->p.collision == LB_TRT) go(std::integral_constant<int, COLL_TRT>{}, blk);
@@ -366,19 +375,19 @@ int run_binary_march(lb_ctx* c) {
 
 // The single-pass march runs one block per tile column and chunk, each
 // marching its planes in sequence, so on small lattices it has too few blocks
-// to hide its per-plane latency: 64^3 FP64 (64 blocks) took 83 us a step
+// to hide its per-plane latency: 64^3 FP64 (32 blocks) took 122 us a step
 // against 39 us for the two-pass step (phi pass + fused collide, every site in
-// parallel), 112^3 (392 blocks) the same 207 us for both, and 128^3 (512
-// blocks) 261 against 303 us; FP32 and FP16 cross over at the same grid size.
-// With LB_STEP_AUTO the march runs from kMarchMinBlocks blocks up.  The two
-// paths give the same bits.
-constexpr int kMarchMinBlocks = 400;
+// parallel), 96^3 (144 blocks) 142 against 136 us, 112^3 (196 blocks) 198
+// against 204 us and 128^3 (256 blocks) 248 against 301 us; FP32 and FP16
+// cross over between 112^3 and 128^3.  With LB_STEP_AUTO the march runs from
+// kMarchMinBlocks blocks (one per CU) up.  The two paths give the same bits.
+constexpr int kMarchMinBlocks = 256;
 
 template <class S>
 bool march_pays(const lb_ctx* c) {
     if (c->p.binary_step == LB_STEP_MARCH) return true;
     if (c->p.binary_step == LB_STEP_TWO_PASS) return false;
-    return c->template march_geo<typename March<S>::P, March<S>::bz>().nblocks >= kMarchMinBlocks;
+    return c->template march_geo<typename March<S>::P>().nblocks >= kMarchMinBlocks;
 }
 
 template <class S>
@@ -564,8 +573,7 @@ int run_step_record_binary(lb_ctx* c, int32_t n, S* post, typename Compute<S>::T
     }
     c->pending = true;
     using MP = typename March<S>::P;
-    constexpr int BZ = March<S>::bz;
-    const Geo g = c->canonical(c->template march_geo<MP, BZ>());
+    const Geo g = c->canonical(c->template march_geo<MP>());
     const bool march = march_pays<S>(c);
     Geo cg = c->canonical_geo();
     for (int32_t k = 1; k < n; ++k) {
@@ -600,10 +608,10 @@ int run_step_record_binary(lb_ctx* c, int32_t n, S* post, typename Compute<S>::T
             auto go = [&](auto coll) {
                 constexpr int COLL = decltype(coll)::value;
                 if (phi)
-                    k_binary_march<MP, BZ, S, March<S>::glds, 3, true, COLL><<<grid, block, 0, c->stream>>>(
+                    k_binary_march<MP, S, March<S>::glds, 3, true, COLL><<<grid, block, 0, c->stream>>>(
                         src, src + Q * N, dst, dst + Q * N, g, cp, phi + (size_t)k * N);
                 else
-                    k_binary_march<MP, BZ, S, March<S>::glds, 3, false, COLL><<<grid, block, 0, c->stream>>>(
+                    k_binary_march<MP, S, March<S>::glds, 3, false, COLL><<<grid, block, 0, c->stream>>>(
                         src, src + Q * N, dst, dst + Q * N, g, cp);
             };
             if (c->p.collision == LB_TRT) go(std::integral_constant<int, COLL_TRT>{});
@@ -903,6 +911,7 @@ int lb_conserved_sums_noalloc(const lb_params* p, const void* f, const void* g, 
     geo.gx = tiles(p->nx, Pol::TX);
     geo.gy = tiles(p->ny, Pol::TY);
     geo.gz = tiles(p->nz, Pol::TZ);
+    geo.bz = Pol::TZ;
     const int64_t nblocks = (int64_t)geo.gx * geo.gy * geo.gz;
     if (nblocks > LB_NOALLOC_MAX_BLOCKS) return LB_ERANGE;
     geo.nblocks = (int)nblocks;
