@@ -717,18 +717,26 @@ template <int LG>
 void launch_adjoint_binary_local(lb_ctx* c, bool pending, const double* f, const double* g, const double* phi,
                                  const double* lf_next, const double* lg_next, const double* b_next, double* lf_n,
                                  double* p_out, double* afield, const Geo& geo, const CollParams<double>& cp) {
-    auto go = [&](auto coll) {
+    // 32-bit byte offsets from one base per array when every array of 19
+    // directions fits below 4 GiB (lattices up to about 300^3)
+    const bool off32 = (uint64_t)Q * (uint64_t)geo.dstride * sizeof(double) <= ((uint64_t)1 << 32);
+    auto go = [&](auto coll, auto o32) {
         constexpr int COLL = decltype(coll)::value;
+        constexpr bool OFF32 = decltype(o32)::value;
         if (pending)
-            k_adjoint_binary<Pol, true, LG, COLL><<<c->grid(), c->block(), 0, c->stream>>>(
+            k_adjoint_binary<Pol, true, LG, COLL, OFF32><<<c->grid(), c->block(), 0, c->stream>>>(
                 f, g, phi, lf_next, lg_next, b_next, lf_n, p_out, afield, c->partial(), geo, cp);
         else
-            k_adjoint_binary<Pol, false, LG, COLL><<<c->grid(), c->block(), 0, c->stream>>>(
+            k_adjoint_binary<Pol, false, LG, COLL, OFF32><<<c->grid(), c->block(), 0, c->stream>>>(
                 f, g, phi, lf_next, lg_next, b_next, lf_n, p_out, afield, c->partial(), geo, cp);
     };
-    if (c->p.collision == LB_TRT) go(std::integral_constant<int, COLL_TRT>{});
-    else if (c->p.collision == LB_MRT) go(std::integral_constant<int, COLL_MRT>{});
-    else go(std::integral_constant<int, COLL_BGK>{});
+    auto by_coll = [&](auto o32) {
+        if (c->p.collision == LB_TRT) go(std::integral_constant<int, COLL_TRT>{}, o32);
+        else if (c->p.collision == LB_MRT) go(std::integral_constant<int, COLL_MRT>{}, o32);
+        else go(std::integral_constant<int, COLL_BGK>{}, o32);
+    };
+    if (off32) by_coll(std::true_type{});
+    else by_coll(std::false_type{});
 }
 
 // Gradient sums of a binary adjoint step: dL/domega_f, dL/domega_g,
