@@ -186,21 +186,20 @@ __device__ __forceinline__ Site site_at(const Column& c, int v, const Geo& g) {
 }
 
 // Global loads and stores of element `off` of an array whose base is the
-// same for the whole launch, nontemporal when the policy says so.  For 4- and
-// 8-byte elements the byte offset is formed in 32 bits (every array here is
-// below 4 GiB, checked on the host), so the address is a scalar base plus a
-// 32-bit vector offset and no 64-bit address arithmetic is spent per lane.
-// 2-byte elements keep plain pointer arithmetic: measured, their loads ran
-// 20-30% slower through the 32-bit-offset form.
+// same for the whole launch, nontemporal when the policy says so.  The byte
+// offset is formed in 32 bits (every array here is below 4 GiB, checked on
+// the host), so the address is a scalar base plus a 32-bit vector offset and
+// no 64-bit address arithmetic is spent per lane.  (2-byte elements once ran
+// 20-30% slower in this form, because a running sum over 19 gathered values
+// then sent its loads out one at a time; with the values gathered into an
+// array before the sum the form is 1% faster for them as well.)
 template <class S>
 __device__ __forceinline__ const S* at(const S* base, uint32_t off) {
-    if constexpr (sizeof(S) == 2) return base + off;
-    else return reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + (uint32_t)(off * (uint32_t)sizeof(S)));
+    return reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + (uint32_t)(off * (uint32_t)sizeof(S)));
 }
 template <class S>
 __device__ __forceinline__ S* at(S* base, uint32_t off) {
-    if constexpr (sizeof(S) == 2) return base + off;
-    else return reinterpret_cast<S*>(reinterpret_cast<char*>(base) + (uint32_t)(off * (uint32_t)sizeof(S)));
+    return reinterpret_cast<S*>(reinterpret_cast<char*>(base) + (uint32_t)(off * (uint32_t)sizeof(S)));
 }
 template <bool NT, class S>
 __device__ __forceinline__ S ldg(const S* base, uint32_t off) {
