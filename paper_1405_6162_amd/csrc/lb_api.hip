@@ -20,11 +20,12 @@ using namespace lbk;
 
 namespace {
 
-// Launch policy of every kernel in the library: 64 x 4 sites per block, one
-// site per lane, nontemporal stores (the next step reads the values from
-// HBM anyway), XCD-ordered tiles.  Chosen by a sweep over tile shapes,
-// sites per lane (1, 2, 4), nontemporal loads/stores and direction padding
-// on 128^3 and 256^3 lattices; the differences were within 5%.
+// Launch policy of every kernel in the library but the single-pass binary
+// step (below): 64 x 4 sites per block, one site per lane, nontemporal
+// stores (the next step reads the values from HBM anyway), XCD-ordered
+// tiles.  Chosen by a sweep over tile shapes, sites per lane (1, 2, 4),
+// nontemporal loads/stores and direction padding on 128^3 and 256^3
+// lattices; the differences were within 5%.
 using Pol = Tiling<64, 4, 1, false, true, true>;
 // The same with 2 and 4 sites per lane along z (lb_params.vvl).
 using Pol2 = Tiling<64, 4, 2, false, true, true>;

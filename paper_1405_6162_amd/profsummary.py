@@ -25,12 +25,38 @@ from collections import defaultdict
 PKG = os.path.dirname(os.path.abspath(__file__))
 
 
+def _code_only(text):
+    """The source with its comments and blank space removed: // comments to
+    the end of the line (outside string literals), /* */ blocks, and runs of
+    whitespace collapsed, so that editing a comment changes no digest."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c == '"':                                   # string literal: copy through its end
+            j = i + 1
+            while j < n and text[j] != '"':
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def kernel_source_digest():
-    """sha256 of the kernel sources; a counter summary is stale once it changes."""
+    """sha256 of the kernel sources' code (comments and whitespace removed);
+    a counter summary is stale once it changes."""
     h = hashlib.sha256()
     for name in ("d3q19.h", "kernels.h", "lb_api.hip"):
-        with open(os.path.join(PKG, "csrc", name), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(PKG, "csrc", name), encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -126,3 +126,14 @@ def test_bench_host_helpers():
     # cos(2 pi 4 x / n) changes sign 8 times along x and never along y, z
     phi = phi + 0.123                     # avoid exact zeros at the nodes
     assert bench.interface_density(phi) == pytest.approx(8 / n / 3, rel=1e-12)
+
+
+def test_source_digest_ignores_comments_not_code():
+    """A counter summary goes stale when the kernels' code changes, not when
+    a comment or the spacing does."""
+    code = 'int a = 1; // one\n/* two\n   lines */ const char* s = "x // y /* z */";\n'
+    same = 'int a = 1;   // another comment\nconst char* s = "x // y /* z */";  /* trailing */\n'
+    other = 'int a = 2; // one\n/* two\n   lines */ const char* s = "x // y /* z */";\n'
+    assert profsummary._code_only(code) == profsummary._code_only(same)
+    assert profsummary._code_only(code) != profsummary._code_only(other)
+    assert "// y /* z */" in profsummary._code_only(code)          # inside a string literal: kept
