@@ -36,20 +36,29 @@ using Pol4 = Tiling<64, 4, 4, false, true, true>;
 // phi gathers (mostly re-reads of neighbouring tiles' g) fall from 53% to
 // 28% of the sites gathered: measured A/B on one box, 64 x 8 is 6.5% faster
 // than 64 x 4 in FP64 at 256^3, 2% at 128^3, 3% in FP32 and 1% in FP16;
-// 64 x 16 and 32 x 16 were slower in every storage.  g waits in registers
-// in FP64 (1% faster than LDS at 256^3) and FP32, in LDS in FP16 (30%
-// faster than registers at 384^3).
+// 64 x 16 and 32 x 16 were slower in every storage.  In FP32 and FP16 a
+// 128 x 4 tile (W), which has half the x-halo sites (whose gathers each hit
+// a cache line of their own, 2 or 4 bytes used), is faster again: 3% in
+// FP16 at 256^3 and 384^3, 0.8-1.5% in FP32 (FP64: 0.4% slower; 128 x 8
+// slower in FP16); it is used where its 128-site rows leave no more lanes
+// idle than 64-site rows (nx mod 128 is 0 or above 64).  g waits in
+// registers in FP64 (1% faster than LDS at 256^3) and FP32, in LDS in FP16
+// (30% faster than registers at 384^3; as FP16 values no faster than as
+// FP32).
 template <class S> struct March;
 template <> struct March<double> {
     using P = Tiling<64, 8, 1, false, true, true>;
+    using W = P;
     static constexpr bool glds = false;
 };
 template <> struct March<float> {
     using P = Tiling<64, 8, 1, false, true, true>;
+    using W = Tiling<128, 4, 1, false, true, true>;
     static constexpr bool glds = false;
 };
 template <> struct March<_Float16> {
     using P = Tiling<64, 8, 1, false, true, true>;
+    using W = Tiling<128, 4, 1, false, true, true>;
     static constexpr bool glds = true;
 };
 // Chunk depth of the march: each chunk's first and last plane cost one
@@ -344,12 +353,15 @@ int run_phi(lb_ctx* c) {
 template <class S>
 int run_binary_march(lb_ctx* c) {
     using MP = typename March<S>::P;
+    using MW = typename March<S>::W;
     const auto cp = coll_params<S>(c);
     const int src = c->cur, dst = 1 - c->cur;
-    const Geo g = c->template march_geo<MP>();
-    {
+    const bool wide = tiles(c->p.nx, MW::TX) * MW::TX == tiles(c->p.nx, MP::TX) * MP::TX;
+    auto launch = [&](auto tiling) {
+        using TP = decltype(tiling);
+        const Geo g = c->template march_geo<TP>();
         Timed t(c, LB_K_COLLIDE);
-        const dim3 grid(g.nblocks), block(MP::TPB);
+        const dim3 grid(g.nblocks), block(TP::TPB);
         const S* fs = (const S*)c->fbuf(src);
         const S* gs = (const S*)c->gbuf(src);
         S* fd = (S*)c->fbuf(dst);
@@ -357,7 +369,7 @@ int run_binary_march(lb_ctx* c) {
         auto go = [&](auto coll, auto blk) {
             constexpr int COLL = decltype(coll)::value;
             constexpr bool BLK = decltype(blk)::value;
-            k_binary_march<MP, S, March<S>::glds, 3, false, COLL, BLK><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd, g, cp);
+            k_binary_march<TP, S, March<S>::glds, 3, false, COLL, BLK><<<grid, block, 0, c->stream>>>(fs, gs, fd, gd, g, cp);
         };
         auto by_coll = [&](auto blk) {
             if (c->p.collision == LB_TRT) go(std::integral_constant<int, COLL_TRT>{}, blk);
@@ -366,7 +378,9 @@ int run_binary_march(lb_ctx* c) {
         };
         if (c->L.blocked) by_coll(std::true_type{});
         else by_coll(std::false_type{});
-    }
+    };
+    if (wide) launch(MW{});
+    else launch(MP{});
     int rc = launch_status();
     if (rc) return rc;
     c->cur = dst;
