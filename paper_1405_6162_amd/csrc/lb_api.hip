@@ -63,11 +63,12 @@ template <> struct March<_Float16> {
 };
 // Chunk depth of the march: each chunk's first and last plane cost one
 // extra plane of phi (2/bz more g reads), while deeper chunks leave fewer
-// blocks to fill the CUs.  32 planes where that still gives
-// kMarchDeepBlocks blocks, else 16.  Measured A/B on one box (FP64): 32
-// planes 3% faster at 192^3 (432 blocks), 1.6% at 256^3, 1% at 320^3, but
-// 18% slower at 160^3 (300 blocks); FP32 1% faster at 192^3 and 256^3, FP16
-// equal within 1%.
+// blocks to fill the CUs.  The deepest of 64 and 32 planes that still gives
+// kMarchDeepBlocks blocks, else 16.  Measured A/B on one box: 32 planes
+// against 16 3% faster in FP64 at 192^3 (432 blocks), 1.6% at 256^3, 1% at
+// 320^3, but 18% slower at 160^3 (300 blocks); 64 against 32 0.8% faster in
+// FP64 at 256^3 (512 blocks), 1.5% in FP32, 1% in FP64 at 320^3, equal at
+// 384^3.
 constexpr int kMarchDeepBlocks = 400;
 
 constexpr size_t kAlign = 4096;
@@ -243,7 +244,8 @@ struct lb_ctx {
         Geo g = geo();
         g.gx = tiles(p.nx, MP::TX);
         g.gy = tiles(p.ny, MP::TY);
-        g.bz = g.gx * g.gy * tiles(p.nz, 32) >= kMarchDeepBlocks ? 32 : 16;
+        const int col = g.gx * g.gy;
+        g.bz = col * tiles(p.nz, 64) >= kMarchDeepBlocks ? 64 : (col * tiles(p.nz, 32) >= kMarchDeepBlocks ? 32 : 16);
         g.gz = tiles(p.nz, g.bz);
         g.nblocks = g.gx * g.gy * g.gz;
         return g;

@@ -1,11 +1,15 @@
-"""The single-pass binary step with 32-plane chunks.
+"""The single-pass binary step with deep chunks.
 
-The march gives each block 16 z planes, or 32 where the lattice still has at
-least 400 blocks with them.  Here the lattice (200 x 204 x 100) is ragged
-in x (200 = 3 x 64 + 8), in y (204 = 25 x 8 + 4) and in its last chunk
-(100 = 3 x 32 + 4), and large enough for 32-plane chunks (4 x 26 x 4 = 416
-blocks of 64 x 8 columns):
+The march gives each block 16 z planes, or the deepest of 64 and 32 that
+still leaves at least 400 blocks.  Two lattices, ragged in x, y and in their
+last chunk:
 
+- 200 x 204 x 100: 200 = 3 x 64 + 8, 204 = 25 x 8 + 4; 32-plane chunks
+  (4 x 26 x 4 = 416 blocks of 64 x 8 columns), the last one 4 planes;
+- 256 x 320 x 150: 64-plane chunks (4 x 40 x 3 = 480 blocks), the last one
+  22 planes.
+
+For each:
 - FP64, BGK, 3 steps: every value of f and g within 1e-12 of the C oracle's
   (oracle/lb_oracle.c, FP64 loops on all host cores), relative to the
   largest;
@@ -23,10 +27,10 @@ from paper_1405_6162_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-NX, NY, NZ = 200, 204, 100
+SHAPES = [(200, 204, 100), (256, 320, 150)]
 
 
-def _fields():
+def _fields(NX, NY, NZ):
     rho, _u, phi = inputs.spinodal_quench(NX, NY, NZ, seed=41, phi_max=0.3)
     _r, u = inputs.single_fluid_random(NX, NY, NZ, seed=42, u_max=0.01)
     return rho, u, phi
@@ -36,9 +40,10 @@ def relerr(a, ref):
     return float(np.abs(np.asarray(a) - ref).max() / np.abs(ref).max())
 
 
-def test_deep_chunk_march_fp64_against_oracle(lbgpu):
-    print("case binary %dx%dx%d FP64 x3, 32-plane march vs C oracle" % (NX, NY, NZ), flush=True)
-    rho, u, phi = _fields()
+@pytest.mark.parametrize("NX,NY,NZ", SHAPES)
+def test_deep_chunk_march_fp64_against_oracle(lbgpu, NX, NY, NZ):
+    print("case binary %dx%dx%d FP64 x3, deep-chunk march vs C oracle" % (NX, NY, NZ), flush=True)
+    rho, u, phi = _fields(NX, NY, NZ)
     C.set_threads(0)
     ref = C.CLattice(NX, NY, NZ, model=1)
     ref.init_equilibrium(rho, u, phi)
@@ -51,18 +56,19 @@ def test_deep_chunk_march_fp64_against_oracle(lbgpu):
     f, g = (a.cpu().numpy() for a in lat.get_state())
     lat.close()
     ef, eg = relerr(f, fo), relerr(g, go)
-    print("32-plane march vs oracle: f %.2e g %.2e" % (ef, eg), flush=True)
+    print("deep-chunk march vs oracle: f %.2e g %.2e" % (ef, eg), flush=True)
     assert ef <= 1e-12 and eg <= 1e-12
 
 
+@pytest.mark.parametrize("NX,NY,NZ", SHAPES)
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
 @pytest.mark.parametrize("coll", ["bgk", "mrt"])
-def test_deep_chunk_march_equals_two_pass(lbgpu, storage, coll):
-    print("case binary %dx%dx%d %s %s, 32-plane march vs two-pass" % (NX, NY, NZ, storage, coll), flush=True)
+def test_deep_chunk_march_equals_two_pass(lbgpu, storage, coll, NX, NY, NZ):
+    print("case binary %dx%dx%d %s %s, deep-chunk march vs two-pass" % (NX, NY, NZ, storage, coll), flush=True)
     code = {"f64": lbgpu.LB_F64, "f32": lbgpu.LB_F32, "f16": lbgpu.LB_F16}[storage]
     kw = dict(collision=lbgpu.LB_MRT, tau_minus=1.25, tau_bulk=1.4, tau_ghost_even=0.9,
               tau_ghost_odd=1.2) if coll == "mrt" else {}
-    rho, u, phi = _fields()
+    rho, u, phi = _fields(NX, NY, NZ)
     states = {}
     for path, step in (("march", lbgpu.LB_STEP_MARCH), ("two_pass", lbgpu.LB_STEP_TWO_PASS)):
         lat = lbgpu.Lattice(NX, NY, NZ, model=lbgpu.LB_BINARY, storage=code, phi0=float(phi.mean()),
