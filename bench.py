@@ -153,6 +153,43 @@ def cpu_baseline(model, n, slab_div=8, steps=8):
                       % (steps, n, model, cores, t_all, steps, n, n, nz1, t_one)}
 
 
+def fp32_vs_fp64(torch, lb, inputs, n, steps, warmup, fp64_mlups):
+    """The metric's comparison on its own configuration: the binary lattice
+    in FP32 storage, timed like the FP64 line (plain launches between two
+    synchronizations), and its moments after 1 and 10 steps against an FP64
+    run from the same seeded state.  The FP64 path is itself held to the
+    FP64 oracle within 1e-12 by the GPU tests, so its moments stand in for
+    the oracle's here; the error is max |q - q64| / max |q64| per moment."""
+    rho, u, phi = inputs.spinodal_quench(n, n, n, seed=0)
+
+    def lattice(storage):
+        lat = lb.Lattice(n, n, n, model=lb.LB_BINARY, storage=storage, rho0=1.0, phi0=float(phi.mean()))
+        lat.init_equilibrium(rho, u, phi)
+        return lat
+
+    lat = lattice(lb.LB_F32)
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.step(steps)
+    torch.cuda.synchronize()
+    mlups = n ** 3 * steps / (time.perf_counter() - t0) / 1e6
+    lat.close()
+    a, b = lattice(lb.LB_F64), lattice(lb.LB_F32)
+    errors, done = {}, 0
+    for k in (1, 10):
+        a.step(k - done)
+        b.step(k - done)
+        done = k
+        errors[str(k)] = {name: float((y - x).abs().max() / x.abs().max())
+                          for name, x, y in zip(("rho", "u", "phi"), a.moments(), b.moments())}
+    a.close()
+    b.close()
+    return {"storage": "f32", "MLUPS": round(mlups, 2), "speedup": round(mlups / fp64_mlups, 3),
+            "errors_vs_fp64_after_steps": errors, "stated_err": {"u": 1e-6, "after_steps": 10},
+            "met": errors["10"]["u"] <= 1e-6}
+
+
 def copy_probe(torch, nbytes=2 << 30, reps=10):
     """The library's streaming copy (lb_stream_copy: 16-byte loads, nontemporal
     16-byte stores) of `nbytes` device bytes, timed with events on the
@@ -523,6 +560,8 @@ def main():
     ap.add_argument("--workload", default="binary256_f64", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-copy", action="store_true", help="skip the copy-bandwidth probe")
+    ap.add_argument("--no-fp32", action="store_true",
+                    help="skip the FP32 comparison of the binary 256^3 FP64 workload")
     ap.add_argument("--vvl", type=int, default=1, choices=(1, 2, 4),
                     help="sites per lane of the fused single-fluid kernel (the paper's VVL)")
     args = ap.parse_args()
@@ -646,6 +685,9 @@ def main():
             "event_ms_per_step": round(gpu_ms / args.steps, 5),
         },
     }
+    if args.workload == "binary256_f64" and not args.no_fp32:
+        log("bench: FP32 comparison")
+        out["fp32_vs_fp64"] = fp32_vs_fp64(torch, lb, inputs, n, args.steps, args.warmup, mlups)
     if not args.no_copy:
         out["copy_probe"] = copy_probe(torch)
         out["roofline"]["frac_of_copy_probe"] = round(achieved / out["copy_probe"]["GB/s"], 4)
