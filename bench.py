@@ -290,7 +290,7 @@ def bench_adjoint(args, n, desc, T=200, K=20):
         "ms_per_step": round(wall * 1e3 / (T * iters), 5), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": desc, "nx": n, "ny": n, "nz": n, "tau": taus, "rollout_steps": T,
-                   "checkpoint_every": K, "seed": 0},
+                   "checkpoint_every": K, "store_all": K == 0, "seed": 0},
         "roofline": {"bound": "hbm", "kernel": "k_adjoint%s (adjoint of the fused step)" % (" (MRT)" if mrt else ""),
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(args.workload),
@@ -360,7 +360,7 @@ def bench_adjoint_binary(args, n, desc, T=200, K=20):
         "ms_per_step": round(wall * 1e3 / (T * iters), 5), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": desc, "nx": n, "ny": n, "nz": n, "rollout_steps": T, "checkpoint_every": K,
-                   "seed": 0},
+                   "store_all": K == 0, "seed": 0},
         "roofline": {"bound": "hbm",
                      "kernel": "adjoint step: k_adjoint_binary%s + k_adjoint_binary_stencil" % (
                          " (TRT)" if trt else (" (MRT)" if mrt else "")),
@@ -560,6 +560,9 @@ def main():
     ap.add_argument("--workload", default="binary256_f64", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-copy", action="store_true", help="skip the copy-bandwidth probe")
+    ap.add_argument("--store-all", action="store_true",
+                    help="adjoint workloads: record every step in the forward (no recompute) instead of "
+                         "checkpoints every 20 steps")
     ap.add_argument("--no-fp32", action="store_true",
                     help="skip the FP32 comparison of the binary 256^3 FP64 workload")
     ap.add_argument("--vvl", type=int, default=1, choices=(1, 2, 4),
@@ -581,9 +584,9 @@ def main():
     lb.load()
     torch.cuda.set_device(0)
     if model == "adjoint":
-        return bench_adjoint(args, n, desc)
+        return bench_adjoint(args, n, desc, K=0 if args.store_all else 20)
     if model == "adjoint_binary":
-        return bench_adjoint_binary(args, n, desc)
+        return bench_adjoint_binary(args, n, desc, K=0 if args.store_all else 20)
     if model == "precision":
         return bench_precision(args, storage, n, desc)
     if model == "precision_single":

@@ -10,7 +10,10 @@ backward recomputes each segment of at most K steps on the GPU, recording
 every step's post-collision field (lb_step_record), and walks it in reverse;
 the adjoint kernel pulls f^n from the recorded field, so the recompute costs
 one fused step per step and nothing else.  A T-step rollout holds T/K + K
-states instead of T.
+states instead of T.  With every = 0 the forward records every step itself
+(one segment, no recompute): T - 1 recorded states (single fluid 19 N
+doubles each, binary fluid 39 N with phi; 130 GB for 200 binary steps at
+128^3), for a GPU whose memory holds them.
 
 The loss is ordinary torch code on the returned f_T (for instance the mean
 of u.u over the lattice); its gradient arrives as grad_output.
@@ -50,30 +53,43 @@ class LBRollout(torch.autograd.Function):
     tau_ghost_even, tau_ghost_odd) for MRT;
     lattice: an lb.Lattice with model LB_SINGLE and storage LB_F64, whose
     state and relaxation times this call overwrites; nsteps: T >= 0; every:
-    checkpoint interval K >= 1.  Gradients flow to f0 and tau.
+    checkpoint interval K >= 1, or 0 to record every step in the forward
+    (no recompute in the backward).  Gradients flow to f0 and tau.
     """
 
     @staticmethod
     def forward(ctx, f0, tau, lattice, nsteps, every):
         if lattice.model != lb.LB_SINGLE or lattice.storage != lb.LB_F64:
             raise ValueError("the adjoint is implemented for the single fluid in FP64")
-        if nsteps < 0 or every < 1:
-            raise ValueError("nsteps must be >= 0 and every >= 1")
+        if nsteps < 0 or every < 0:
+            raise ValueError("nsteps must be >= 0 and every >= 0")
         taus = _relaxation_times(tau, lattice)
         lattice.set_params(**taus)
         lattice.set_state(f0.detach())
         ckpts = [f0.detach().clone()]
-        done = 0
-        while done < nsteps:
-            k = min(every, nsteps - done)
-            lattice.step(k)
-            done += k
-            if done < nsteps:
-                ckpts.append(lattice.get_state()[0])
+        records = None
+        if every == 0:
+            # one segment, recorded as the forward runs
+            post = None
+            if nsteps > 1:
+                post = torch.empty((nsteps - 1,) + tuple(f0.shape), dtype=torch.float64, device=f0.device)
+                lb.lb_set_stream(lattice.ctx, lb._stream())
+                lb.lb_step_record(lattice.ctx, nsteps - 1, post)
+            if nsteps > 0:
+                lattice.step(1)
+            records, every = [post], max(nsteps, 1)
+        else:
+            done = 0
+            while done < nsteps:
+                k = min(every, nsteps - done)
+                lattice.step(k)
+                done += k
+                if done < nsteps:
+                    ckpts.append(lattice.get_state()[0])
         fT = lattice.get_state()[0] if nsteps > 0 else f0.detach().clone()
         ctx.lattice, ctx.nsteps, ctx.every, ctx.taus = lattice, nsteps, every, taus
         ctx.tau_shape = tau.shape
-        ctx.ckpts = ckpts
+        ctx.ckpts, ctx.records = ckpts, records
         return fT
 
     @staticmethod
@@ -93,17 +109,21 @@ class LBRollout(torch.autograd.Function):
             # post-collision fields post[k] give f^{start+k+1} in pull form;
             # then one library call walks the segment backwards
             ckpt = ctx.ckpts[seg]
-            lat.set_state(ckpt)
-            post = None
             lb.lb_set_stream(lat.ctx, lb._stream())
-            if length > 1:
-                post = torch.empty((length - 1,) + tuple(ckpt.shape), dtype=torch.float64, device=ckpt.device)
-                lb.lb_step_record(lat.ctx, length - 1, post)
+            if ctx.records is not None:
+                post = ctx.records[seg]                     # recorded by the forward
+            else:
+                lat.set_state(ckpt)
+                post = None
+                if length > 1:
+                    post = torch.empty((length - 1,) + tuple(ckpt.shape), dtype=torch.float64,
+                                       device=ckpt.device)
+                    lb.lb_step_record(lat.ctx, length - 1, post)
             lb.lb_adjoint_segment(lat.ctx, ckpt, post, length, lam, work, domega)
             del post
         tv = torch.tensor(list(taus.values()), dtype=torch.float64, device=lam.device)
         grad_tau = (-domega / (tv * tv)).reshape(ctx.tau_shape)
-        ctx.ckpts = None
+        ctx.ckpts = ctx.records = None
         return lam, grad_tau, None, None, None
 
 
@@ -120,7 +140,8 @@ class LBBinaryRollout(torch.autograd.Function):
     an lb.Lattice with model LB_BINARY and storage LB_F64, whose state and
     parameters this call overwrites.  Gradients flow to rho0, u0,
     phi0, kappa, mobility and tau_f.  The backward recomputes each segment of
-    at most `every` steps from its checkpoint, recording every step's
+    at most `every` steps from its checkpoint (every = 0: the forward records
+    every step itself, one segment, no recompute), recording every step's
     post-collision f and g, and reverses it in one call
     (lb_adjoint_segment_binary: the local and the stencil adjoint kernel per
     step), then the reverse of the initialisation (lb_adjoint_init_binary).
@@ -130,8 +151,8 @@ class LBBinaryRollout(torch.autograd.Function):
     def forward(ctx, rho0, u0, phi0, kappa, mobility, tau_f, lattice, nsteps, every):
         if lattice.model != lb.LB_BINARY or lattice.storage != lb.LB_F64:
             raise ValueError("the binary adjoint is implemented for the binary fluid in FP64")
-        if nsteps < 0 or every < 1:
-            raise ValueError("nsteps must be >= 0 and every >= 1")
+        if nsteps < 0 or every < 0:
+            raise ValueError("nsteps must be >= 0 and every >= 0")
         names = RATE_NAMES[lattice.params.collision]
         if tuple(tau_f.shape) != ((len(names),) if len(names) > 1 else ()):
             raise ValueError("tau_f must be %s on this lattice" % ("(%s)" % ", ".join(names) if len(names) > 1
@@ -141,16 +162,31 @@ class LBBinaryRollout(torch.autograd.Function):
         fields = tuple(t.detach().to(torch.float64).contiguous() for t in (rho0, u0, phi0))
         lattice.init_equilibrium(*fields)
         ckpts = [lattice.get_state()]
-        done = 0
-        while done < nsteps:
-            k = min(every, nsteps - done)
-            lattice.step(k)
-            done += k
-            if done < nsteps:
-                ckpts.append(lattice.get_state())
+        records = None
+        if every == 0:
+            # one segment, recorded as the forward runs
+            post = phi = None
+            if nsteps > 1:
+                shape = ckpts[0][0].shape
+                dev = ckpts[0][0].device
+                post = torch.empty((nsteps - 1, 2 * lb.Q) + tuple(shape[1:]), dtype=torch.float64, device=dev)
+                phi = torch.empty((nsteps - 1,) + tuple(shape[1:]), dtype=torch.float64, device=dev)
+                lb.lb_set_stream(lattice.ctx, lb._stream())
+                lb.lb_step_record(lattice.ctx, nsteps - 1, post, phi)
+            if nsteps > 0:
+                lattice.step(1)
+            records, every = [(post, phi)], max(nsteps, 1)
+        else:
+            done = 0
+            while done < nsteps:
+                k = min(every, nsteps - done)
+                lattice.step(k)
+                done += k
+                if done < nsteps:
+                    ckpts.append(lattice.get_state())
         fT, gT = lattice.get_state() if nsteps > 0 else (ckpts[0][0].clone(), ckpts[0][1].clone())
         ctx.lattice, ctx.nsteps, ctx.every = lattice, nsteps, every
-        ctx.ckpts, ctx.fields = ckpts, fields
+        ctx.ckpts, ctx.fields, ctx.records = ckpts, fields, records
         ctx.params = (float(kappa), float(mobility), times)
         return fT, gT
 
@@ -174,15 +210,19 @@ class LBBinaryRollout(torch.autograd.Function):
             if length <= 0:
                 continue
             f_ck, g_ck = ctx.ckpts[seg]
-            lat.set_state(f_ck, g_ck)
-            post = phi = None
             lb.lb_set_stream(lat.ctx, lb._stream())
-            if length > 1:
-                # post[k] and phi[k] (phi of the state step k collides) for k < length - 1;
-                # the last step's phi is computed by the sweep itself
-                post = torch.empty((length - 1, 2 * lb.Q) + tuple(shape[1:]), dtype=torch.float64, device=dev)
-                phi = torch.empty((length - 1,) + tuple(shape[1:]), dtype=torch.float64, device=dev)
-                lb.lb_step_record(lat.ctx, length - 1, post, phi)
+            if ctx.records is not None:
+                post, phi = ctx.records[seg]                # recorded by the forward
+            else:
+                lat.set_state(f_ck, g_ck)
+                post = phi = None
+                if length > 1:
+                    # post[k] and phi[k] (phi of the state step k collides) for k < length - 1;
+                    # the last step's phi is computed by the sweep itself
+                    post = torch.empty((length - 1, 2 * lb.Q) + tuple(shape[1:]), dtype=torch.float64,
+                                       device=dev)
+                    phi = torch.empty((length - 1,) + tuple(shape[1:]), dtype=torch.float64, device=dev)
+                    lb.lb_step_record(lat.ctx, length - 1, post, phi)
             lb.lb_adjoint_segment_binary(lat.ctx, f_ck, g_ck, post, phi, length, lf, lg, work, grads)
             del post, phi
         rho0, u0, phi0 = ctx.fields
@@ -197,7 +237,7 @@ class LBBinaryRollout(torch.autograd.Function):
         rate_sums = torch.cat([grads[:1], grads[3:]])
         tv = torch.tensor(list(times.values()), dtype=torch.float64, device=dev)
         g_tau = (-rate_sums / (tv * tv)).reshape(() if len(times) == 1 else (len(times),))
-        ctx.ckpts = ctx.fields = None
+        ctx.ckpts = ctx.fields = ctx.records = None
         return drho, du, dphi, g_kappa, g_mob, g_tau, None, None, None
 
 

@@ -185,7 +185,12 @@ def fake_lib(monkeypatch):
     monkeypatch.setattr(lb, "lb_adjoint_segment", _segment_single)
 
 
-@pytest.mark.parametrize("T,K", [(0, 3), (1, 1), (5, 1), (5, 5), (5, 8), (7, 3), (6, 2)])
+def _segment_length(T, K):
+    """every = 0 records every step in the forward: one segment of T steps."""
+    return max(T, 1) if K == 0 else K
+
+
+@pytest.mark.parametrize("T,K", [(0, 3), (1, 1), (5, 1), (5, 5), (5, 8), (7, 3), (6, 2), (0, 0), (1, 0), (7, 0)])
 def test_binary_rollout_checkpoint_logic(fake_lib, T, K):
     nx, ny, nz = 4, 3, 5
     rho, u, phi = inputs.spinodal_quench(nx, ny, nz, seed=3, phi_max=0.3)
@@ -197,14 +202,17 @@ def test_binary_rollout_checkpoint_logic(fake_lib, T, K):
     params = [torch.tensor(v, dtype=torch.float64, requires_grad=True)
               for v in (prm.kappa, prm.mobility, prm.tau_f)]
     fT, gT = adjoint.rollout_binary(r0, u0, p0, lat, T, K, *params)
+    # with every = 0 the forward itself records (once, when there is more than one step)
+    assert lat.calls["record"] == (int(T > 1) if K == 0 else 0)
     loss = adjoint.binary_loss(fT, gT, 0.5)
     assert abs(loss.item() - loss_o) <= 1e-14 * abs(loss_o)
     loss.backward()
+    L = _segment_length(T, K)
     assert lat.calls["adjoint"] == T                       # one adjoint step per step
-    assert lat.calls["segment"] == len(range(0, T, K))     # one sweep call per segment
-    assert lat.calls["record"] == sum(1 for s in range(0, T, K) if min(K, T - s) > 1)
+    assert lat.calls["segment"] == len(range(0, T, L))     # one sweep call per segment
+    assert lat.calls["record"] == sum(1 for s in range(0, T, L) if min(L, T - s) > 1)
     # every step but the last of each segment longer than one step reads a recorded phi
-    assert lat.calls["phi_given"] == sum(min(K, T - s) - 1 for s in range(0, T, K) if min(K, T - s) > 1)
+    assert lat.calls["phi_given"] == sum(min(L, T - s) - 1 for s in range(0, T, L) if min(L, T - s) > 1)
     scale = max(np.abs(a).max() for a in (dphi_o, drho_o, du_o))     # dL/drho0 vanishes at T = 0
     np.testing.assert_allclose(p0.grad.numpy(), dphi_o, rtol=0, atol=1e-13 * scale)
     np.testing.assert_allclose(r0.grad.numpy(), drho_o, rtol=0, atol=1e-13 * scale)
@@ -269,7 +277,7 @@ def test_binary_mrt_rollout_checkpoint_logic(fake_lib, T, K):
         assert abs(tau.grad[k].item() - want) <= 1e-12 * abs(want), name
 
 
-@pytest.mark.parametrize("T,K", [(0, 2), (1, 1), (6, 1), (6, 6), (6, 9), (7, 3)])
+@pytest.mark.parametrize("T,K", [(0, 2), (1, 1), (6, 1), (6, 6), (6, 9), (7, 3), (0, 0), (1, 0), (6, 0)])
 def test_single_rollout_checkpoint_logic(fake_lib, T, K):
     nx, ny, nz = 5, 4, 3
     rho, u = inputs.shear_wave(nx, ny, nz, amplitude=0.01, noise=1e-3, seed=13)
@@ -280,10 +288,13 @@ def test_single_rollout_checkpoint_logic(fake_lib, T, K):
     f = torch.from_numpy(f0.copy()).requires_grad_(True)
     t = torch.tensor(tau, dtype=torch.float64, requires_grad=True)
     loss = adjoint.velocity_loss(adjoint.rollout(f, t, lat, T, K))
+    assert lat.calls["record"] == (int(T > 1) if K == 0 else 0)
     assert abs(loss.item() - loss_o) <= 1e-14 * abs(loss_o)
     loss.backward()
+    L = _segment_length(T, K)
     assert lat.calls["adjoint"] == T
-    assert lat.calls["segment"] == len(range(0, T, K))
+    assert lat.calls["segment"] == len(range(0, T, L))
+    assert lat.calls["record"] == sum(1 for s in range(0, T, L) if min(L, T - s) > 1)
     np.testing.assert_allclose(f.grad.numpy(), g_o, rtol=0, atol=1e-13 * np.abs(g_o).max())
     if T > 0:
         assert abs(t.grad.item() - dtau_o) <= 1e-12 * abs(dtau_o)
