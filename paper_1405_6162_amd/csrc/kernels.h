@@ -1145,8 +1145,11 @@ __device__ __forceinline__ double trt_mu(double l, double lo, const CollParams<d
 // the projection of lambda*_f on m; the moments of lambda*_f, f and f^eq on
 // them give the bulk and ghost rate sums (partial[8 b + 4..6]), and the
 // shear and flux sums are the even and odd sums less those.
+// At least two waves per SIMD: BGK and TRT fit in 256 VGPRs anyway; the MRT
+// variant then spills 45 VGPRs to scratch but runs 5% faster than at one
+// wave (measured at 128^3).
 template <class P, bool F_PENDING, int LG, int COLL = COLL_BGK, bool OFF32 = false>
-__global__ __launch_bounds__(P::TPB) void k_adjoint_binary(const double* __restrict__ fn,
+__global__ __launch_bounds__(P::TPB, 2) void k_adjoint_binary(const double* __restrict__ fn,
                                                            const double* __restrict__ gn,
                                                            const double* __restrict__ phi,
                                                            const double* __restrict__ lf_next,
