@@ -186,20 +186,27 @@ __device__ __forceinline__ Site site_at(const Column& c, int v, const Geo& g) {
 }
 
 // Global loads and stores of element `off` of an array whose base is the
-// same for the whole launch, nontemporal when the policy says so.  The byte
-// offset is formed in 32 bits (every array here is below 4 GiB, checked on
-// the host), so the address is a scalar base plus a 32-bit vector offset and
-// no 64-bit address arithmetic is spent per lane.  (2-byte elements once ran
-// 20-30% slower in this form, because a running sum over 19 gathered values
-// then sent its loads out one at a time; with the values gathered into an
-// array before the sum the form is 1% faster for them as well.)
+// same for the whole launch, nontemporal when the policy says so.  For 2-
+// and 8-byte elements the byte offset is formed in 32 bits (such arrays are
+// below 4 GiB here, checked on the host), so the address is a scalar base
+// plus a 32-bit vector offset and no 64-bit address arithmetic is spent per
+// lane.  4-byte elements take the element offset, scaled in 64 bits, so
+// that an FP32 state of up to 2^32 values keeps the blocked layout (384^3:
+// 4.3 GB, 7% faster than the structure of arrays it needed in bytes; no
+// difference at 256^3).  For 8-byte elements the 64-bit form was 0.6%
+// slower at 256^3 and 14% slower in the binary adjoint kernel.  (2-byte
+// elements once ran 20-30% slower in the 32-bit form, because a running sum
+// over 19 gathered values then sent its loads out one at a time; with the
+// values gathered into an array before the sum it is 1% faster for them.)
 template <class S>
 __device__ __forceinline__ const S* at(const S* base, uint32_t off) {
-    return reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + (uint32_t)(off * (uint32_t)sizeof(S)));
+    if constexpr (sizeof(S) == 4) return base + off;
+    else return reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + (uint32_t)(off * (uint32_t)sizeof(S)));
 }
 template <class S>
 __device__ __forceinline__ S* at(S* base, uint32_t off) {
-    return reinterpret_cast<S*>(reinterpret_cast<char*>(base) + (uint32_t)(off * (uint32_t)sizeof(S)));
+    if constexpr (sizeof(S) == 4) return base + off;
+    else return reinterpret_cast<S*>(reinterpret_cast<char*>(base) + (uint32_t)(off * (uint32_t)sizeof(S)));
 }
 template <bool NT, class S>
 __device__ __forceinline__ S ldg(const S* base, uint32_t off) {

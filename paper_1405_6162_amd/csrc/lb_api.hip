@@ -126,7 +126,9 @@ Layout layout_of(const lb_params* p) {
     Layout L{};
     L.nsite = (int64_t)p->nx * p->ny * p->nz;
     const size_t es = storage_size(p->storage);
-    // Blocked layout (see Geo) whenever a buffer's offsets fit in 32 bits;
+    // Blocked layout (see Geo) whenever a buffer's offsets fit in 32 bits
+    // (in bytes; for 4-byte elements, which are addressed by element, in
+    // elements);
     // the last x block of a row is padded to 64 sites.  Measured A/B on one
     // box against the structure-of-arrays layout: the single-fluid step
     // +4.6% (FP64) and +5.6% (FP32) at 256^3, the binary march +4.3% (FP64,
@@ -135,7 +137,7 @@ Layout layout_of(const lb_params* p) {
     // these.
     const uint64_t xblocks = (uint64_t)tiles(p->nx, 64);
     const uint64_t blocked_elems = (uint64_t)p->nz * (uint64_t)p->ny * xblocks * Q * 64;
-    L.blocked = blocked_elems * es < ((uint64_t)1 << 32);
+    L.blocked = (es == 4 ? blocked_elems : blocked_elems * es) < ((uint64_t)1 << 32);
     if (L.blocked) {
         L.dstride = 64;
         L.xbs = Q * 64;

@@ -1,13 +1,14 @@
 """The 384^3 reduced-precision workloads at their full size.
 
 The binary spinodal quench on a 384^3 periodic lattice in FP16-deviation
-storage (blocked layout) and in FP32 storage (4.3 GB per distribution:
-beyond the blocked layout's 32-bit offsets, so structure of arrays), in the
-launch configuration the benchmark times, two steps.  No FP64 oracle run is
-sensible at this size in reduced precision, so the checks are properties
-that hold at any size:
+storage and in FP32 storage (4.3 GB per distribution, beyond 32-bit byte
+offsets: 4-byte elements are addressed by element), both in the blocked
+layout and in the launch configuration the benchmark times, two steps.  No
+FP64 oracle run is sensible at this size in reduced precision, so the
+checks are properties that hold at any size:
 
-- the single-pass march (the benchmark's kernel, 32-plane chunks here) and
+- the single-pass march (the benchmark's kernel: 128 x 4 tiles, 64-plane
+  chunks here) and
   the two-pass step give the same bits (they sum phi in the same order and
   share the collision; both are compared with the oracle at smaller sizes);
 - total mass and total phi after two steps equal their initial values
