@@ -1,0 +1,51 @@
+"""The single-pass march in each of its launch shapes.
+
+The march picks its tile per storage and lattice (64 x 8; in FP32 and FP16
+128 x 4 where nx mod 128 is 0 or above 64) and its chunk depth per lattice
+(the deepest of 64 and 32 planes that leaves 400 blocks, else 16).  The
+lattices below were chosen (seeded search, at most 6.2 M sites) so that
+every combination runs once, each ragged in x, y and in its last chunk:
+
+| lattice         | FP64 tile, chunk | FP32/FP16 tile, chunk | last chunk |
+|-----------------|------------------|-----------------------|------------|
+| 195 x 252 x 17  | 64 x 8, 16       | 128 x 4, 16           | 1 plane    |
+| 282 x 205 x 17  | 64 x 8, 16       | 64 x 8, 16            | 1 plane    |
+| 211 x 255 x 17  | 64 x 8, 16       | 128 x 4, 16           | 1 plane    |
+| 257 x 319 x 34  | 64 x 8, 32       | 64 x 8, 32            | 2 planes   |
+| 68 x 266 x 164  | 64 x 8, 32       | 128 x 4, 32           | 4 planes   |
+| 262 x 318 x 66  | 64 x 8, 64       | 64 x 8, 64            | 2 planes   |
+| 326 x 289 x 65  | 64 x 8, 64       | 128 x 4, 64           | 1 plane    |
+
+In every storage the march and the two-pass step (phi pass + fused
+collide, whose launch shape is fixed) give the same bits after three steps;
+both are compared with the oracle elsewhere.
+"""
+
+import pytest
+import torch
+
+from paper_1405_6162_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(195, 252, 17), (282, 205, 17), (211, 255, 17), (257, 319, 34), (68, 266, 164), (262, 318, 66),
+          (326, 289, 65)]
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("nx,ny,nz", SHAPES)
+def test_march_launch_shapes_equal_two_pass(lbgpu, storage, nx, ny, nz):
+    print("case binary %dx%dx%d %s x3: march vs two-pass" % (nx, ny, nz, storage), flush=True)
+    code = {"f64": lbgpu.LB_F64, "f32": lbgpu.LB_F32, "f16": lbgpu.LB_F16}[storage]
+    rho, _u, phi = inputs.spinodal_quench(nx, ny, nz, seed=71, phi_max=0.3)
+    _r, u = inputs.single_fluid_random(nx, ny, nz, seed=72, u_max=0.01)
+    states = {}
+    for path, step in (("march", lbgpu.LB_STEP_MARCH), ("two_pass", lbgpu.LB_STEP_TWO_PASS)):
+        lat = lbgpu.Lattice(nx, ny, nz, model=lbgpu.LB_BINARY, storage=code, phi0=float(phi.mean()),
+                            binary_step=step)
+        lat.init_equilibrium(rho, u, phi)
+        lat.step(3)
+        states[path] = lat.get_state()
+        lat.close()
+    for a, b in zip(states["march"], states["two_pass"]):
+        assert torch.equal(a, b)
