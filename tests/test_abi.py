@@ -324,3 +324,33 @@ def test_readme_example_compiles_and_runs_on_the_c_reference(tmp_path):
                                                         check=True, timeout=60).stdout.split())
     assert m1 == pytest.approx(m0, rel=1e-12) and m0 > 100
     assert p1 == pytest.approx(p0, abs=1e-12)
+
+
+def _round_up(n, a=4096):
+    return (n + a - 1) // a * a
+
+
+@pytest.mark.parametrize("n,storage,blocked", [
+    (256, lb.LB_F64, True),      # 2.55 GB per buffer
+    (320, lb.LB_F64, False),     # 4.98 GB: 8-byte elements take byte offsets, below 4 GiB only
+    (384, lb.LB_F32, True),      # 4.30 GB: 4-byte elements are addressed by element
+    (384, lb.LB_F16, True),      # 2.15 GB
+])
+def test_state_layout_choice(lib, n, storage, blocked):
+    """The workspace of a binary lattice holds four distribution buffers,
+    phi and the block partials; its size shows which state layout the
+    library chose: 64-site blocks of all 19 directions (no padding between
+    directions) or a structure of arrays (each direction padded to 4 KiB plus
+    9472 bytes)."""
+    rc, got = _ws(lb.make_params(n, n, n, model=lb.LB_BINARY, storage=storage))
+    assert rc == lb.LB_OK
+    es = {lb.LB_F64: 8, lb.LB_F32: 4, lb.LB_F16: 2}[storage]
+    N = n ** 3
+    xblocks = -(-n // 64)
+    if blocked:
+        dist = _round_up(n * n * xblocks * 19 * 64 * es)
+    else:
+        dist = _round_up((_round_up(N * es) + 9472) * 19)
+    phi = _round_up(N * (8 if storage == lb.LB_F64 else 4))
+    partial = _round_up(xblocks * (-(-n // 4)) * n * 16 * 8)
+    assert got == 4 * dist + phi + partial
