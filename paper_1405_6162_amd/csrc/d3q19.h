@@ -147,11 +147,14 @@ struct Site {
 };
 
 template <class P>
+__device__ __forceinline__ bool xcd_remapped(const Geo& g) {
+    return P::xcd && (g.nblocks & 7) == 0;
+}
+
+template <class P>
 __device__ __forceinline__ int tile_index(const Geo& g) {
     int b = blockIdx.x;
-    if constexpr (P::xcd) {
-        if ((g.nblocks & 7) == 0) b = (b & 7) * (g.nblocks >> 3) + (b >> 3);
-    }
+    if (xcd_remapped<P>(g)) b = (b & 7) * (g.nblocks >> 3) + (b >> 3);
     return b;
 }
 

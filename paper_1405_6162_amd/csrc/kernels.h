@@ -350,8 +350,8 @@ __global__ __launch_bounds__(P::TPB) void k_collide_single_strided(const S* fsrc
 
 // ---------------------------------------------------------------------------
 // Single-pass binary step: fused pull-stream + collision that computes phi
-// itself.  A block owns a TX x TY column tile and marches through geo.bz
-// consecutive z planes.  phi(s) = phi0 + sum_i e_i(s - c_i) needs the pulled
+// itself.  A block owns a TX x TY column tile and marches through one chunk
+// of at most geo.bz consecutive z planes (geo.gz chunks).  phi(s) = phi0 + sum_i e_i(s - c_i) needs the pulled
 // g of s, which the collision of s needs anyway: each lane gathers g for
 // plane z+1, sums it into the plane's phi tile in LDS and keeps the 19 values
 // for the next plane's collision, in registers or (GLDS) in LDS.  On small
@@ -425,8 +425,21 @@ __global__ __launch_bounds__(P::TPB) void k_binary_march(const S* __restrict__ f
     const int bx = b % geo.gx;
     const int t = b / geo.gx;
     const int by = t % geo.gy;
-    const int z0 = (t / geo.gy) * geo.bz;
-    const int z1 = min(z0 + geo.bz, geo.nz);
+    // Under the XCD remap each XCD takes a contiguous run of tiles, so a short
+    // last chunk would land on the last XCDs and leave them idle while the
+    // others finish: the gz chunks then split nz evenly (8-14% faster at 208^3
+    // with 64-plane chunks).  Without the remap blocks reach the XCDs in launch
+    // order and the short last chunk, launched last, fills the tail (even
+    // chunks measured 5-6% slower at 272^3).
+    const int zc = t / geo.gy;
+    int z0, z1;
+    if (xcd_remapped<P>(geo)) {
+        z0 = (int)((int64_t)zc * geo.nz / geo.gz);
+        z1 = (int)((int64_t)(zc + 1) * geo.nz / geo.gz);
+    } else {
+        z0 = zc * geo.bz;
+        z1 = min(z0 + geo.bz, geo.nz);
+    }
     const int x0 = bx * TX, y0 = by * TY;
     const int tx = (int)(threadIdx.x % TX), ty = (int)(threadIdx.x / TX);
     const bool active = (x0 + tx < geo.nx) && (y0 + ty < geo.ny);

@@ -68,7 +68,9 @@ template <> struct March<_Float16> {
 // against 16 3% faster in FP64 at 192^3 (432 blocks), 1.6% at 256^3, 1% at
 // 320^3, but 18% slower at 160^3 (300 blocks); 64 against 32 0.8% faster in
 // FP64 at 256^3 (512 blocks), 1.5% in FP32, 1% in FP64 at 320^3, equal at
-// 384^3.
+// 384^3.  The kernel cuts nz into the gz chunks evenly where the blocks are
+// remapped to XCDs (block count a multiple of 8), else in full-depth chunks
+// and a short last one.
 constexpr int kMarchDeepBlocks = 400;
 
 constexpr size_t kAlign = 4096;

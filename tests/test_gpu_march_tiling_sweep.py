@@ -1,22 +1,26 @@
 """The single-pass march in each of its launch shapes.
 
 The march picks its tile per storage and lattice (64 x 8; in FP32 and FP16
-128 x 4 where nx mod 128 is 0 or above 64) and its chunk depth per lattice
-(the deepest of 64 and 32 planes that leaves 400 blocks, else 16).  The
-lattices below were chosen (seeded search, at most 6.2 M sites) so that
-every combination runs once, each ragged in x, y and in its last chunk:
+128 x 4 where nx mod 128 is 0 or above 64), its chunk depth per lattice
+(the deepest of 64 and 32 planes that leaves 400 blocks, else 16), and how
+nz is cut: where the block count is a multiple of 8 (blocks remapped to XCDs
+in contiguous runs) the chunks split nz evenly, else all but the last chunk
+take the full depth.  The lattices below were chosen (seeded search, at most
+6.2 M sites) so that every combination runs once, each ragged in x and y:
 
-| lattice         | FP64 tile, chunk | FP32/FP16 tile, chunk | last chunk |
-|-----------------|------------------|-----------------------|------------|
-| 195 x 252 x 17  | 64 x 8, 16       | 128 x 4, 16           | 1 plane    |
-| 282 x 205 x 17  | 64 x 8, 16       | 64 x 8, 16            | 1 plane    |
-| 211 x 255 x 17  | 64 x 8, 16       | 128 x 4, 16           | 1 plane    |
-| 257 x 319 x 34  | 64 x 8, 32       | 64 x 8, 32            | 2 planes   |
-| 68 x 266 x 164  | 64 x 8, 32       | 128 x 4, 32           | 4 planes   |
-| 262 x 318 x 66  | 64 x 8, 64       | 64 x 8, 64            | 2 planes   |
-| 326 x 289 x 65  | 64 x 8, 64       | 128 x 4, 64           | 1 plane    |
+| lattice         | FP64: tile, depth, chunks  | FP32/FP16: tile, depth, chunks |
+|-----------------|----------------------------|--------------------------------|
+| 195 x 252 x 17  | 64 x 8, 16, even 8/9       | 128 x 4, 16, last 1 plane      |
+| 282 x 205 x 17  | 64 x 8, 16, last 1 plane   | 64 x 8, 16, last 1 plane       |
+| 211 x 255 x 17  | 64 x 8, 16, even 8/9       | 128 x 4, 16, even 8/9          |
+| 257 x 319 x 34  | 64 x 8, 32, even 17        | 64 x 8, 32, even 17            |
+| 68 x 266 x 164  | 64 x 8, 32, even 27/28     | 128 x 4, 32, last 4 planes     |
+| 262 x 322 x 35  | 64 x 8, 32, last 3 planes  | 64 x 8, 32, last 3 planes      |
+| 262 x 318 x 66  | 64 x 8, 64, even 33        | 64 x 8, 64, even 33            |
+| 326 x 289 x 65  | 64 x 8, 64, last 1 plane   | 128 x 4, 64, last 1 plane      |
 
-In every storage the march and the two-pass step (phi pass + fused
+(128 x 4 tiles with even 32- and 64-plane chunks run in the deep-chunk
+tests.)  In every storage the march and the two-pass step (phi pass + fused
 collide, whose launch shape is fixed) give the same bits after three steps;
 both are compared with the oracle elsewhere.
 """
@@ -28,8 +32,8 @@ from paper_1405_6162_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [(195, 252, 17), (282, 205, 17), (211, 255, 17), (257, 319, 34), (68, 266, 164), (262, 318, 66),
-          (326, 289, 65)]
+SHAPES = [(195, 252, 17), (282, 205, 17), (211, 255, 17), (257, 319, 34), (68, 266, 164), (262, 322, 35),
+          (262, 318, 66), (326, 289, 65)]
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
