@@ -95,8 +95,9 @@ extern "C" {
  * LB_STEP_TWO_PASS: a phi pass, then the fused collide (776 B/site), every
  * site in parallel: fastest on small lattices, where the march has too few
  * blocks to hide its per-plane latency.  LB_STEP_AUTO (0, the default): the
- * march when its grid has at least 256 blocks (64 x 8 tiles, chunks of at most 16
- * planes, or 64 or 32 where that still gives 400 blocks; 128^3 has 256), else the
+ * march when its grid has at least 256 blocks (64 x 8 tiles; chunks of 64
+ * planes where that gives more than 512 blocks, else as many chunks as fill 512
+ * blocks, at most nz/16 of them; 128^3 has 256), else the
  * two-pass step.  (FP32 and FP16 march on 128 x 4 tiles where nx mod 128 is
  * 0 or above 64.) */
 #define LB_STEP_AUTO     0

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
@@ -61,17 +62,20 @@ template <> struct March<_Float16> {
     using W = Tiling<128, 4, 1, false, true, true>;
     static constexpr bool glds = true;
 };
-// Chunk depth of the march: each chunk's first and last plane cost one
-// extra plane of phi (2/bz more g reads), while deeper chunks leave fewer
-// blocks to fill the CUs.  The deepest of 64 and 32 planes that still gives
-// kMarchDeepBlocks blocks, else 16.  Measured A/B on one box: 32 planes
-// against 16 3% faster in FP64 at 192^3 (432 blocks), 1.6% at 256^3, 1% at
-// 320^3, but 18% slower at 160^3 (300 blocks); 64 against 32 0.8% faster in
-// FP64 at 256^3 (512 blocks), 1.5% in FP32, 1% in FP64 at 320^3, equal at
-// 384^3.  The kernel cuts nz into the gz chunks evenly where the blocks are
-// remapped to XCDs (block count a multiple of 8), else in full-depth chunks
-// and a short last one.
-constexpr int kMarchDeepBlocks = 400;
+// Chunks of the march: each chunk's first and last plane cost one extra
+// plane of phi (2/depth more g reads), while deeper chunks leave fewer blocks.
+// Two 512-lane march blocks fit a CU, so kMarchSlots blocks run at once.
+// Where 64-plane chunks give more blocks than that, the depth is 64 (64
+// against 32 planes 0.8% faster in FP64 at 256^3, 1.5% in FP32, 1% at 320^3,
+// equal at 384^3).  Otherwise nz is cut into as many chunks as fill one round
+// of slots, at least nz/64 and at most nz/16 of them (rounded up).  Measured
+// A/B against the fixed depths of 64, 32 or 16 planes it replaced: 8-12%
+// faster at 160^3 (480 blocks of 20 planes instead of 600 of 16) and 4-9% at
+// 192^3 (504 of 28 instead of 432 of 32) in FP64, FP32 and FP16, 1% slower at
+// 176^3.  The kernel cuts nz evenly where the blocks are remapped to XCDs
+// (block count a multiple of 8), else into chunks of the depth and a shorter
+// last one.
+constexpr int kMarchSlots = 512;
 
 constexpr size_t kAlign = 4096;
 // Extra bytes between consecutive direction arrays, so the 19 (38) streams of
@@ -249,7 +253,12 @@ struct lb_ctx {
         g.gx = tiles(p.nx, MP::TX);
         g.gy = tiles(p.ny, MP::TY);
         const int col = g.gx * g.gy;
-        g.bz = col * tiles(p.nz, 64) >= kMarchDeepBlocks ? 64 : (col * tiles(p.nz, 32) >= kMarchDeepBlocks ? 32 : 16);
+        if (col * tiles(p.nz, 64) > kMarchSlots) {
+            g.bz = 64;
+        } else {
+            const int chunks = std::min(tiles(p.nz, 16), std::max(tiles(p.nz, 64), kMarchSlots / col));
+            g.bz = tiles(p.nz, chunks);
+        }
         g.gz = tiles(p.nz, g.bz);
         g.nblocks = g.gx * g.gy * g.gz;
         return g;

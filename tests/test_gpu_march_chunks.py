@@ -1,15 +1,15 @@
 """The single-pass binary step with deep chunks.
 
-The march gives each block a chunk of at most 16 z planes, or of the
-deepest of 64 and 32 that still leaves at least 400 blocks; where the block
+The march gives each block a chunk of z planes: 64 where that gives more
+than 512 blocks, else as many chunks as fill 512 blocks; where the block
 count is a multiple of 8 the chunks split nz evenly.  Two lattices, ragged
-in x and y, whose nz is no multiple of the depth:
+in x and y, with deep chunks:
 
-- 200 x 204 x 100: 200 = 3 x 64 + 8, 204 = 25 x 8 + 4; depth 32
-  (4 x 26 x 4 = 416 blocks of 64 x 8 columns; 2 x 51 x 4 = 408 of 128 x 4
-  in FP32 and FP16), four chunks of 25 planes;
-- 256 x 320 x 150: depth 64 (4 x 40 x 3 = 480 blocks; 2 x 80 x 3 of
-  128 x 4), three chunks of 50 planes.
+- 200 x 204 x 100: 200 = 3 x 64 + 8, 204 = 25 x 8 + 4; in FP64 four even
+  chunks of 25 planes (4 x 26 x 4 = 416 blocks of 64 x 8 columns), in FP32
+  and FP16 five of 20 (2 x 51 x 5 = 510 blocks of 128 x 4);
+- 256 x 320 x 150: three even chunks of 50 planes (4 x 40 x 3 = 480 blocks;
+  2 x 80 x 3 of 128 x 4).
 
 For each:
 - FP64, BGK, 3 steps: every value of f and g within 1e-12 of the C oracle's

@@ -1,26 +1,28 @@
 """The single-pass march in each of its launch shapes.
 
 The march picks its tile per storage and lattice (64 x 8; in FP32 and FP16
-128 x 4 where nx mod 128 is 0 or above 64), its chunk depth per lattice
-(the deepest of 64 and 32 planes that leaves 400 blocks, else 16), and how
-nz is cut: where the block count is a multiple of 8 (blocks remapped to XCDs
-in contiguous runs) the chunks split nz evenly, else all but the last chunk
-take the full depth.  The lattices below were chosen (seeded search, at most
-6.2 M sites) so that every combination runs once, each ragged in x and y:
+128 x 4 where nx mod 128 is 0 or above 64) and its chunks per lattice: depth
+64 where that gives more than 512 blocks (two per CU), else as many chunks
+as fill 512 blocks (at least nz/64, at most nz/16, rounded up).  Where the
+block count is a multiple of 8 (blocks remapped to XCDs in contiguous runs)
+the chunks split nz evenly, else all but the last take the full depth.  The
+lattices below were chosen so that every combination runs, each ragged in x
+and y:
 
-| lattice         | FP64: tile, depth, chunks  | FP32/FP16: tile, depth, chunks |
-|-----------------|----------------------------|--------------------------------|
-| 195 x 252 x 17  | 64 x 8, 16, even 8/9       | 128 x 4, 16, last 1 plane      |
-| 282 x 205 x 17  | 64 x 8, 16, last 1 plane   | 64 x 8, 16, last 1 plane       |
-| 211 x 255 x 17  | 64 x 8, 16, even 8/9       | 128 x 4, 16, even 8/9          |
-| 257 x 319 x 34  | 64 x 8, 32, even 17        | 64 x 8, 32, even 17            |
-| 68 x 266 x 164  | 64 x 8, 32, even 27/28     | 128 x 4, 32, last 4 planes     |
-| 262 x 322 x 35  | 64 x 8, 32, last 3 planes  | 64 x 8, 32, last 3 planes      |
-| 262 x 318 x 66  | 64 x 8, 64, even 33        | 64 x 8, 64, even 33            |
-| 326 x 289 x 65  | 64 x 8, 64, last 1 plane   | 128 x 4, 64, last 1 plane      |
+| lattice          | FP64: tile, blocks, chunks    | FP32/FP16: tile, blocks, chunks |
+|------------------|-------------------------------|---------------------------------|
+| 195 x 252 x 17   | 64 x 8, 256, even 8/9         | 128 x 4, 252, 9 + 8             |
+| 282 x 205 x 17   | 64 x 8, 260, 9 + 8            | 64 x 8, 260, 9 + 8              |
+| 211 x 255 x 17   | 64 x 8, 256, even 8/9         | 128 x 4, 256, even 8/9          |
+| 257 x 319 x 34   | 64 x 8, 400, even 17          | 64 x 8, 400, even 17            |
+| 68 x 266 x 164   | 64 x 8, 476, 6 x 24 + 20      | 128 x 4, 469, 6 x 24 + 20       |
+| 262 x 322 x 35   | 64 x 8, 410, 18 + 17          | 64 x 8, 410, 18 + 17            |
+| 262 x 318 x 66   | 64 x 8, 400, even 33          | 64 x 8, 400, even 33            |
+| 326 x 289 x 65   | 64 x 8, 444, 33 + 32          | 128 x 4, 438, 33 + 32           |
+| 65 x 1025 x 66   | 64 x 8, 516, 64 + 2           | 128 x 4, 514, 64 + 2            |
+| 65 x 1037 x 66   | 64 x 8, 520, even 33          | 128 x 4, 520, even 33           |
 
-(128 x 4 tiles with even 32- and 64-plane chunks run in the deep-chunk
-tests.)  In every storage the march and the two-pass step (phi pass + fused
+In every storage the march and the two-pass step (phi pass + fused
 collide, whose launch shape is fixed) give the same bits after three steps;
 both are compared with the oracle elsewhere.
 """
@@ -33,7 +35,7 @@ from paper_1405_6162_amd import inputs
 pytestmark = pytest.mark.gpu
 
 SHAPES = [(195, 252, 17), (282, 205, 17), (211, 255, 17), (257, 319, 34), (68, 266, 164), (262, 322, 35),
-          (262, 318, 66), (326, 289, 65)]
+          (262, 318, 66), (326, 289, 65), (65, 1025, 66), (65, 1037, 66)]
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
